@@ -1,0 +1,185 @@
+/*
+ * mk.h -- C ABI of the MI355X (gfx950) Marchenko synthesis library.
+ *
+ * The library runs the iterative (Neumann-series) Marchenko scheme of
+ * Koehne et al., "A multi-GPU benchmark for 2D Marchenko Imaging"
+ * (arXiv 2106.04649): Eq. (1) of the Theory section and Algorithm 1, with
+ * the synthesis of Algorithm 2 as hand-written HIP kernels on one GPU.
+ *
+ * Conventions shared by every call:
+ *   - Time axis: nt samples, periodic, t = 0 at sample 0.  Time reversal
+ *     maps sample k to (nt - k) mod nt.
+ *   - Frequency: numpy rfft convention, kernel exp(-2 pi i k n / nt),
+ *     unnormalised; bins w = 0 .. nt/2.  Complex values are interleaved
+ *     (re, im) float pairs.
+ *   - Mute theta_t of Eq. (1): sample k of trace (f, r) is kept when
+ *     |t_k| < itd[f][r] - shift, with t_k = k for k < nt/2 and k - nt above;
+ *     the sample nt/2 is never kept.
+ *   - One synthesis: S(x)[r](t) = c * sum_s (R[r][s] * x[s])(t), circular
+ *     time convolution evaluated in the frequency domain over the stored
+ *     band, with c = dx * dt (Riemann weight of the double integral).
+ *     Bins outside the band are zero before the inverse transform.
+ *   - Sources and receivers share one grid (nr == ns), since each output
+ *     trace of a synthesis is an integration position of the next one.
+ *   - "on_device" arguments: 0 = host pointer, 1 = device pointer (HIP
+ *     device memory of the current device).  Device inputs are read only
+ *     during the call; the caller owns every buffer it passes.
+ *   - All GPU work is ordered on the plan's stream.  Calls that return data
+ *     to host memory synchronise that stream.
+ *   - Errors are reported by status code; nothing aborts or throws across
+ *     the ABI.  mk_last_error() gives a message for the last failure.
+ *   - A plan is not thread-safe: one plan per host thread and stream.
+ */
+#ifndef MK_H
+#define MK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mk_plan_s* mk_plan_t;
+
+typedef enum {
+    MK_OK = 0,
+    MK_ERR_ARG = 1,          /* invalid argument (null, size, range, NaN input) */
+    MK_ERR_STATE = 2,        /* call out of order (e.g. iterate before load_R)  */
+    MK_ERR_OOM = 3,          /* device allocation failed                        */
+    MK_ERR_HIP = 4,          /* a HIP runtime call failed                       */
+    MK_ERR_UNSUPPORTED = 5,  /* valid request this build does not implement     */
+    MK_ERR_DIVERGED = 6      /* series norms non-finite or above div_factor     */
+} mk_status;
+
+/* Storage precision of R inside the plan. */
+typedef enum {
+    MK_R_C64 = 0,    /* complex64 (FP32 pairs)                                 */
+    MK_R_F16S = 1,   /* FP16 pairs with one FP32 scale per frequency           */
+    MK_R_BF16S = 2   /* BF16 pairs with one FP32 scale per frequency           */
+} mk_rprec;
+
+/* Fields returned by mk_get, each [nf][nr][nt] float32. */
+typedef enum {
+    MK_F1PLUS = 0,   /* f1+ : N_{-1} plus the odd-pass terms  (Algorithm 1)    */
+    MK_F1MINUS = 1,  /* f1- : minus the time-reversed even-pass terms          */
+    MK_GPLUS = 2,    /* G+  : f1+(-t) - S[f1-(-t)]   (one extra synthesis)     */
+    MK_GMINUS = 3,   /* G-  : S[f1+] - f1-           (last lines of Alg. 1)    */
+    MK_NLAST = 4     /* N_i of the last pass (muted, time-reversed field)      */
+} mk_field;
+
+/* Plan flags. */
+#define MK_FLAG_GRAPH   0x1u  /* replay the per-pass kernels as a HIP graph   */
+#define MK_FLAG_PROFILE 0x2u  /* time every kernel with HIP events            */
+
+typedef struct {
+    int32_t nr;          /* receivers (output positions x_R)                    */
+    int32_t ns;          /* shots (integration positions x); must equal nr      */
+    int32_t nt;          /* time samples = FFT length; power of two, 16..4096   */
+    int32_t iw_lo;       /* first stored rfft bin (inclusive), >= 0             */
+    int32_t iw_hi;       /* last stored rfft bin (inclusive), <= nt/2           */
+    int32_t nf_max;      /* largest focal batch mk_set_focal will be given      */
+    double dt;           /* time sampling (s), > 0                              */
+    double dx;           /* receiver spacing (m), > 0                           */
+    double div_factor;   /* divergence threshold on ||N_i|| / ||N_-1||; <= 0 -> 1e3 */
+    int32_t rprec;       /* mk_rprec                                            */
+    uint32_t flags;      /* MK_FLAG_*                                           */
+    void* stream;        /* hipStream_t to order work on; NULL = null stream    */
+} mk_plan_desc;
+
+/*
+ * mk_plan -- validate the problem description and create a plan.
+ * Follows the problem statement of the Theory section (R, G_d, the mute and
+ * niter are the inputs) and the batching of Algorithm 2.  Allocates the
+ * plan's device workspace for nf_max focal points.
+ * Errors: MK_ERR_ARG (null pointers, nr != ns, nt not a power of two in
+ * [16, 4096], band outside [0, nt/2], nf_max < 1, dt or dx not positive,
+ * unknown rprec), MK_ERR_OOM, MK_ERR_HIP.  *out is NULL on failure.
+ */
+mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out);
+
+/*
+ * mk_load_R -- copy the frequency-domain reflection response into the plan.
+ * R: interleaved complex float32, layout receivers x frequencies x shots,
+ * R[r][w - iw_lo][s] for w in [iw_lo, iw_hi] (the layout of the
+ * Introduction and Implementation sections: the space integral runs over
+ * the fastest axis).  The plan repacks it frequency-major (and quantises it
+ * for MK_R_F16S / MK_R_BF16S); the caller may free R on return.
+ * Errors: MK_ERR_ARG (null, non-finite value), MK_ERR_HIP.
+ */
+mk_status mk_load_R(mk_plan_t plan, const float* R, int on_device);
+
+/*
+ * mk_set_focal -- start a new series for nf focal points.
+ * Gd: float32 [nf][nr][nt], the first-arrival field G_d(x_R, x_F, t) of the
+ * Theory section; the series starts from N_{-1} = f1+ = G_d(-t), f1- = 0.
+ * itd: int32 [nf][nr], first-arrival time in samples (the mute window of
+ * Algorithm 1's applyMute); shift: mute margin in samples (>= 0).
+ * band: int32 [nf][2] per-focal inclusive rfft-bin band inside the plan
+ * band, or NULL for the plan band.  All four arrays are host or device per
+ * on_device.  Runs the first forward transform on the GPU.
+ * Errors: MK_ERR_ARG (nf outside [1, nf_max], null Gd or itd, negative
+ * shift, band outside the plan band, non-finite Gd), MK_ERR_STATE (R not
+ * loaded), MK_ERR_HIP.
+ */
+mk_status mk_set_focal(mk_plan_t plan, int32_t nf, const float* Gd, const int32_t* itd,
+                       int32_t shift, const int32_t* band, int on_device);
+
+/*
+ * mk_iterate -- run niter more passes of Algorithm 1's loop.
+ * Pass i: RN_i = S(N_{i-1}); N_i = theta(-RN_i(-t)); even i: f1- -= N_i(-t);
+ * odd i: f1+ += N_i.  Continues the series across calls.
+ * norms: host double [niter][nf] receiving ||N_i||_2 (FP64 reduction), or
+ * NULL.  With norms != NULL the call synchronises and returns
+ * MK_ERR_DIVERGED when a norm is non-finite or exceeds div_factor times
+ * ||N_-1||; the passes have still been applied.
+ * Errors: MK_ERR_ARG (niter < 0), MK_ERR_STATE (no focal set), MK_ERR_HIP,
+ * MK_ERR_DIVERGED.
+ */
+mk_status mk_iterate(mk_plan_t plan, int32_t niter, double* norms);
+
+/*
+ * mk_get -- copy one field, float32 [nf][nr][nt], into out.
+ * MK_GPLUS / MK_GMINUS run the G assembly of the Theory section and the
+ * last lines of Algorithm 1: both are formed together from one batched
+ * synthesis of f1+ and f1-(-t), with the final subtraction in FP64; the
+ * result is cached until the series changes.  Synchronises when out is a
+ * host pointer.
+ * Errors: MK_ERR_ARG (null out, unknown field), MK_ERR_STATE (no focal
+ * set), MK_ERR_HIP.
+ */
+mk_status mk_get(mk_plan_t plan, int32_t field, float* out, int on_device);
+
+/*
+ * mk_passes -- number of passes applied since the last mk_set_focal.
+ * Errors: MK_ERR_ARG (null).
+ */
+mk_status mk_passes(mk_plan_t plan, int32_t* passes);
+
+/*
+ * mk_profile -- accumulated time of one kernel class, recorded with HIP
+ * events on the plan's stream when the plan has MK_FLAG_PROFILE.
+ * kind: 0 contraction (the space integral of Eq. (1)), 1 per-pass epilogue
+ * (inverse FFT, reverse, mute, accumulate, forward FFT), 2 norm reduction,
+ * 3 first forward transform, 4 G assembly.  Synchronises.  reset != 0
+ * clears the counters after reading.
+ * Errors: MK_ERR_ARG, MK_ERR_UNSUPPORTED (plan without MK_FLAG_PROFILE).
+ */
+mk_status mk_profile(mk_plan_t plan, int32_t kind, double* total_ms, int64_t* launches,
+                     int reset);
+
+/* mk_destroy -- free the plan and its device memory (NULL is a no-op). */
+mk_status mk_destroy(mk_plan_t plan);
+
+/* mk_strerror -- static description of a status code. */
+const char* mk_strerror(mk_status status);
+
+/* mk_last_error -- message of the plan's last failure ("" if none); with a
+ * NULL plan, the message of the last failed mk_plan on this thread. */
+const char* mk_last_error(mk_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MK_H */

@@ -1,0 +1,345 @@
+// Per-trace kernels: everything between two contractions of the Neumann
+// series, fused so that a trace of nt samples never leaves LDS.
+//
+// One wavefront owns one trace (f, r); a 256-thread block holds four traces.
+// The real transforms of length nt use one complex transform of length
+// M = nt/2 on packed even/odd samples (Stockham autosort, radix 4 with one
+// radix-2 stage when log2 M is odd), with exact twiddles from a table of
+// exp(-2 pi i k / nt) computed in double on the host.
+//
+// TM_ITER implements one pass of Algorithm 1 after the space integral of
+// Eq. (1): inverse transform with zero-filled out-of-band bins ("padding"),
+// time reversal with a sign flip, the mute theta_t, the accumulation of
+// f1- (even passes) or f1+ (odd passes), the FP64 norm of N_i, and the
+// forward transform of N_i that feeds the next contraction.
+#include "mk_internal.h"
+
+namespace {
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// twiddle exp(DIR * 2 pi i idx / nt) from the forward table exp(-2 pi i idx / nt)
+template <int DIR>
+__device__ __forceinline__ float2 twid(const float2* __restrict__ tw, int idx) {
+    float2 t = tw[idx];
+    if (DIR > 0) t.y = -t.y;
+    return t;
+}
+
+// In-place complex transform of M = NT/2 points held in LDS by one wave.
+// DIR = -1: forward (exp(-i...)), DIR = +1: inverse, both unnormalised.
+// Barriers are block-wide; every wave of the block calls this with the same NT.
+template <int NT, int DIR>
+__device__ void fft_wave(float2* z, const float2* __restrict__ tw, int lane) {
+    constexpr int M = NT / 2;
+    constexpr int LOG2M = ilog2c(M);
+    constexpr int N4 = LOG2M / 2;
+    constexpr int Q = M / 4;
+    constexpr int PER4 = (Q + 63) / 64;
+#pragma unroll
+    for (int st = 0; st < N4; ++st) {
+        const int lns = 2 * st;          // log2 of the current sub-transform span Ns
+        const int Ns = 1 << lns;
+        float2 v[PER4][4];
+#pragma unroll
+        for (int p = 0; p < PER4; ++p) {
+            const int j = lane + 64 * p;
+            if (j < Q) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[p][q] = z[j + q * Q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PER4; ++p) {
+            const int j = lane + 64 * p;
+            if (j < Q) {
+                const int k = j & (Ns - 1);
+                const int base = k * (NT >> (lns + 2));     // k * NT / (4 Ns)
+                const float2 a0 = v[p][0];
+                const float2 a1 = st == 0 ? v[p][1] : cmul(v[p][1], twid<DIR>(tw, base));
+                const float2 a2 = st == 0 ? v[p][2] : cmul(v[p][2], twid<DIR>(tw, 2 * base));
+                const float2 a3 = st == 0 ? v[p][3] : cmul(v[p][3], twid<DIR>(tw, 3 * base));
+                const float2 s02 = make_float2(a0.x + a2.x, a0.y + a2.y);
+                const float2 d02 = make_float2(a0.x - a2.x, a0.y - a2.y);
+                const float2 s13 = make_float2(a1.x + a3.x, a1.y + a3.y);
+                const float2 d13 = make_float2(a1.x - a3.x, a1.y - a3.y);
+                float2 y1, y3;
+                if (DIR < 0) {   // y1 = d02 - i d13, y3 = d02 + i d13
+                    y1 = make_float2(d02.x + d13.y, d02.y - d13.x);
+                    y3 = make_float2(d02.x - d13.y, d02.y + d13.x);
+                } else {         // y1 = d02 + i d13, y3 = d02 - i d13
+                    y1 = make_float2(d02.x - d13.y, d02.y + d13.x);
+                    y3 = make_float2(d02.x + d13.y, d02.y - d13.x);
+                }
+                const int idxD = ((j - k) << 2) + k;
+                z[idxD] = make_float2(s02.x + s13.x, s02.y + s13.y);
+                z[idxD + Ns] = y1;
+                z[idxD + 2 * Ns] = make_float2(s02.x - s13.x, s02.y - s13.y);
+                z[idxD + 3 * Ns] = y3;
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr ((LOG2M & 1) != 0) {
+        constexpr int H = M / 2;
+        constexpr int PER2 = (H + 63) / 64;
+        constexpr int lns = 2 * N4;
+        constexpr int Ns = 1 << lns;
+        float2 v[PER2][2];
+#pragma unroll
+        for (int p = 0; p < PER2; ++p) {
+            const int j = lane + 64 * p;
+            if (j < H) {
+                v[p][0] = z[j];
+                v[p][1] = z[j + H];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PER2; ++p) {
+            const int j = lane + 64 * p;
+            if (j < H) {
+                const int k = j & (Ns - 1);
+                const float2 a0 = v[p][0];
+                const float2 a1 = lns == 0 ? v[p][1] : cmul(v[p][1], twid<DIR>(tw, k * (NT >> (lns + 1))));
+                const int idxD = ((j - k) << 1) + k;
+                z[idxD] = make_float2(a0.x + a1.x, a0.y + a1.y);
+                z[idxD + Ns] = make_float2(a0.x - a1.x, a0.y - a1.y);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// rfft bin k of the real trace whose packed transform Z is in z (k in [0, M]).
+template <int NT>
+__device__ __forceinline__ float2 unpack_bin(const float2* z, const float2* __restrict__ tw, int k) {
+    constexpr int M = NT / 2;
+    const float2 zk = z[k & (M - 1)];
+    const float2 zm = z[(M - k) & (M - 1)];
+    const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    const float2 d = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
+    const float2 wd = cmul(tw[k], d);
+    return make_float2(e.x + wd.y, e.y - wd.x);          // E - i W^k D
+}
+
+template <int NT, int MODE>
+__global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
+    constexpr int M = NT / 2;
+    constexpr int PM = (M + 63) / 64;
+    __shared__ float2 lds[4 * M];
+    const int wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    float2* z = lds + wv * M;
+
+    const int ntr = a.nfo * a.nr;
+    int trace = blockIdx.x * 4 + wv;
+    const bool valid = trace < ntr;
+    if (!valid) trace = ntr - 1;            // keep the wave in the barriers, store nothing
+    const int fo = trace / a.nr;
+    const int r = trace - fo * a.nr;
+    const int f = fo % a.nf;
+    const int hi = a.lo + a.B - 1;
+    int flo = a.lo, fhi = hi;
+    if (a.fband) {
+        flo = max(flo, a.fband[2 * f]);
+        fhi = min(fhi, a.fband[2 * f + 1]);
+    }
+    const size_t tbase = ((size_t)f * a.nr + r) * NT;
+    const float s = a.scale;
+
+    // ---- spectrum -> time (TM_ITER, TM_GOUT) --------------------------------
+    if (MODE == TM_ITER || MODE == TM_GOUT) {
+        const float2* Yt = a.Y + (size_t)fo * a.B * a.nr + r;
+        for (int k = lane; k < M; k += 64) {
+            const int km = M - k;
+            float2 xk = make_float2(0.f, 0.f), xm = make_float2(0.f, 0.f);
+            if (k >= flo && k <= fhi) xk = Yt[(size_t)(k - a.lo) * a.nr];
+            if (km >= flo && km <= fhi) xm = Yt[(size_t)(km - a.lo) * a.nr];
+            if (k == 0) { xk.y = 0.f; xm.y = 0.f; }          // DC and Nyquist are real
+            const float2 e = make_float2(0.5f * (xk.x + xm.x), 0.5f * (xk.y - xm.y));
+            const float2 d = make_float2(0.5f * (xk.x - xm.x), 0.5f * (xk.y + xm.y));
+            const float2 t = a.tw[k];
+            const float2 o = make_float2(d.x * t.x + d.y * t.y, d.y * t.x - d.x * t.y);   // d * conj(W^k)
+            z[k] = make_float2(e.x - o.y, e.y + o.x);                                      // E + i O
+        }
+        __syncthreads();
+        fft_wave<NT, +1>(z, a.tw, lane);
+        // z[m] = (RN[2m], RN[2m+1]) / s
+    }
+
+    double nacc = 0.0;
+    float2 out[PM];
+
+    if (MODE == TM_ITER) {
+        const int L = a.itd[f * a.nr + r] - a.shift;        // keep |t| < L
+        float* acc = (a.parity == 0) ? a.f1m : a.f1p;
+#pragma unroll
+        for (int p = 0; p < PM; ++p) {
+            const int m = lane + 64 * p;
+            if (m < M) {
+                const int t0 = 2 * m, t1 = 2 * m + 1;
+                const int s0 = t0 < M ? t0 : t0 - NT;
+                const int s1 = t1 < M ? t1 : t1 - NT;
+                const bool k0 = (s0 < L) && (-s0 < L) && (t0 != M);
+                const bool k1 = (s1 < L) && (-s1 < L);
+                // N[t] = -RN[(nt - t) mod nt] inside the window
+                const float n0 = k0 ? -s * z[(M - m) & (M - 1)].x : 0.f;
+                const float n1 = k1 ? -s * z[M - 1 - m].y : 0.f;
+                nacc += (double)n0 * n0 + (double)n1 * n1;
+                if (valid && (k0 || k1)) {
+                    float2* pa = reinterpret_cast<float2*>(acc + tbase) + m;
+                    float2 o = *pa;
+                    if (a.parity == 0) {             // f1- -= N(-t)  ==  f1- += theta RN
+                        const float2 zm = z[m];
+                        if (k0) o.x += s * zm.x;
+                        if (k1) o.y += s * zm.y;
+                    } else {                          // f1+ += N
+                        o.x += n0;
+                        o.y += n1;
+                    }
+                    *pa = o;
+                }
+                out[p] = make_float2(n0, n1);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PM; ++p) {
+            const int m = lane + 64 * p;
+            if (m < M) z[m] = out[p];
+        }
+    } else if (MODE == TM_INIT) {
+        const float* g = a.src + tbase;
+#pragma unroll
+        for (int p = 0; p < PM; ++p) {
+            const int m = lane + 64 * p;
+            if (m < M) {
+                // N_-1[t] = Gd[(nt - t) mod nt]
+                const float n0 = g[(NT - 2 * m) & (NT - 1)];
+                const float n1 = g[NT - 2 * m - 1];
+                nacc += (double)n0 * n0 + (double)n1 * n1;
+                if (valid) {
+                    reinterpret_cast<float2*>(a.f1p + tbase)[m] = make_float2(n0, n1);
+                    reinterpret_cast<float2*>(a.f1m + tbase)[m] = make_float2(0.f, 0.f);
+                }
+                z[m] = make_float2(n0, n1);
+            }
+        }
+    } else if (MODE == TM_GFWD) {
+        const bool minus = fo >= a.nf;
+#pragma unroll
+        for (int p = 0; p < PM; ++p) {
+            const int m = lane + 64 * p;
+            if (m < M) {
+                float2 v;
+                if (!minus) {
+                    v = reinterpret_cast<const float2*>(a.f1p + tbase)[m];
+                } else {                             // f1-(-t)
+                    const float* q = a.f1m + tbase;
+                    v = make_float2(q[(NT - 2 * m) & (NT - 1)], q[NT - 2 * m - 1]);
+                }
+                z[m] = v;
+            }
+        }
+    } else if (MODE == TM_GOUT) {
+        const bool plus = fo >= a.nf;
+#pragma unroll
+        for (int p = 0; p < PM; ++p) {
+            const int m = lane + 64 * p;
+            if (m < M && valid) {
+                const float2 zm = z[m];
+                const double rn0 = (double)(s * zm.x), rn1 = (double)(s * zm.y);
+                if (!plus) {                          // G- = S[f1+] - f1-
+                    const float2 q = reinterpret_cast<const float2*>(a.f1m + tbase)[m];
+                    reinterpret_cast<float2*>(a.gm + tbase)[m] =
+                        make_float2((float)(rn0 - (double)q.x), (float)(rn1 - (double)q.y));
+                } else {                              // G+ = f1+(-t) - S[f1-(-t)]
+                    const float* q = a.f1p + tbase;
+                    const double r0 = q[(NT - 2 * m) & (NT - 1)], r1 = q[NT - 2 * m - 1];
+                    reinterpret_cast<float2*>(a.gp + tbase)[m] =
+                        make_float2((float)(r0 - rn0), (float)(r1 - rn1));
+                }
+            }
+        }
+        return;
+    }
+
+    // ---- time -> spectrum (TM_INIT, TM_ITER, TM_GFWD) ---------------------
+    __syncthreads();
+    fft_wave<NT, -1>(z, a.tw, lane);
+    float2* Xt = a.X + (size_t)fo * a.B * a.ns_pad + r;
+    for (int k = a.lo + lane; k <= hi; k += 64) {
+        float2 v = make_float2(0.f, 0.f);
+        if (k >= flo && k <= fhi) v = unpack_bin<NT>(z, a.tw, k);
+        if (valid) Xt[(size_t)(k - a.lo) * a.ns_pad] = v;
+    }
+    if (MODE == TM_INIT || MODE == TM_ITER) {
+        nacc = wave_sum_d(nacc);
+        if (valid && lane == 0) a.npart[(size_t)fo * a.nr + r] = nacc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_norm_reduce(const double* __restrict__ npart, int nr,
+                                                     double* __restrict__ out) {
+    __shared__ double sh[256];
+    const double* p = npart + (size_t)blockIdx.x * nr;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nr; i += 256) acc += p[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(sh[0]);
+}
+
+template <int NT>
+hipError_t launch_trace_nt(int mode, const TraceArgs& a, hipStream_t s) {
+    const int ntr = a.nfo * a.nr;
+    const dim3 grid((ntr + 3) / 4), block(256);
+    switch (mode) {
+        case TM_INIT: hipLaunchKernelGGL((k_trace<NT, TM_INIT>), grid, block, 0, s, a); break;
+        case TM_ITER: hipLaunchKernelGGL((k_trace<NT, TM_ITER>), grid, block, 0, s, a); break;
+        case TM_GFWD: hipLaunchKernelGGL((k_trace<NT, TM_GFWD>), grid, block, 0, s, a); break;
+        case TM_GOUT: hipLaunchKernelGGL((k_trace<NT, TM_GOUT>), grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_trace(int mode, int nt, const TraceArgs& a, hipStream_t s) {
+    if (a.nfo * a.nr <= 0) return hipSuccess;
+    switch (nt) {
+        case 16: return launch_trace_nt<16>(mode, a, s);
+        case 32: return launch_trace_nt<32>(mode, a, s);
+        case 64: return launch_trace_nt<64>(mode, a, s);
+        case 128: return launch_trace_nt<128>(mode, a, s);
+        case 256: return launch_trace_nt<256>(mode, a, s);
+        case 512: return launch_trace_nt<512>(mode, a, s);
+        case 1024: return launch_trace_nt<1024>(mode, a, s);
+        case 2048: return launch_trace_nt<2048>(mode, a, s);
+        case 4096: return launch_trace_nt<4096>(mode, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out, hipStream_t s) {
+    if (nfo <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_norm_reduce, dim3(nfo), dim3(256), 0, s, npart, nr, out);
+    return hipGetLastError();
+}

@@ -1,0 +1,230 @@
+"""ctypes binding of the C ABI in include/mk.h (argument marshalling only).
+
+Every step of the Marchenko series runs in the HIP kernels of libmk.so; this
+module only converts numpy arrays / torch tensors into pointers, passes the
+torch stream, and turns status codes into exceptions.  If the library is
+missing it raises: there is no fallback path.
+
+Functions carry the ABI's names: mk_plan, mk_load_R, mk_set_focal,
+mk_iterate, mk_get, mk_passes, mk_profile, mk_destroy.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmk.so")
+
+MK_OK, MK_ERR_ARG, MK_ERR_STATE, MK_ERR_OOM, MK_ERR_HIP, MK_ERR_UNSUPPORTED, MK_ERR_DIVERGED = range(7)
+MK_R_C64, MK_R_F16S, MK_R_BF16S = 0, 1, 2
+MK_F1PLUS, MK_F1MINUS, MK_GPLUS, MK_GMINUS = 0, 1, 2, 3
+MK_FLAG_GRAPH, MK_FLAG_PROFILE = 0x1, 0x2
+FIELDS = {"f1plus": MK_F1PLUS, "f1minus": MK_F1MINUS, "Gplus": MK_GPLUS, "Gminus": MK_GMINUS}
+KERNEL_KINDS = {"contract": 0, "epilogue": 1, "norms": 2, "init": 3, "gassembly": 4}
+
+
+class mk_plan_desc(ctypes.Structure):
+    _fields_ = [
+        ("nr", ctypes.c_int32),
+        ("ns", ctypes.c_int32),
+        ("nt", ctypes.c_int32),
+        ("iw_lo", ctypes.c_int32),
+        ("iw_hi", ctypes.c_int32),
+        ("nf_max", ctypes.c_int32),
+        ("dt", ctypes.c_double),
+        ("dx", ctypes.c_double),
+        ("div_factor", ctypes.c_double),
+        ("rprec", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class MKError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2106_04649_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    sigs = {
+        "mk_plan": (i32, [ctypes.POINTER(mk_plan_desc), ctypes.POINTER(P)]),
+        "mk_load_R": (i32, [P, P, ctypes.c_int]),
+        "mk_set_focal": (i32, [P, i32, P, P, i32, P, ctypes.c_int]),
+        "mk_iterate": (i32, [P, i32, P]),
+        "mk_get": (i32, [P, i32, P, ctypes.c_int]),
+        "mk_passes": (i32, [P, ctypes.POINTER(i32)]),
+        "mk_profile": (i32, [P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                             ctypes.c_int]),
+        "mk_destroy": (i32, [P]),
+        "mk_strerror": (ctypes.c_char_p, [i32]),
+        "mk_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, plan: Optional[int]) -> None:
+    if status == MK_OK:
+        return
+    lib = load_library()
+    msg = lib.mk_last_error(plan).decode() or lib.mk_strerror(status).decode()
+    raise MKError(status, msg)
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype: str) -> Tuple[int, int, object]:
+    """(pointer, on_device, keepalive) of a contiguous numpy array or torch tensor."""
+    if x is None:
+        return 0, 0, None
+    if _is_torch(x):
+        import torch
+
+        want = {"float32": torch.float32, "int32": torch.int32, "complex64": torch.complex64}[dtype]
+        if x.dtype != want:
+            raise TypeError(f"expected a {dtype} tensor, got {x.dtype}")
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr(), 1 if x.is_cuda else 0, x
+    a = np.ascontiguousarray(x, dtype=np.dtype(dtype))
+    return a.ctypes.data, 0, a
+
+
+def _current_stream() -> int:
+    import torch
+
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """Owner of an mk_plan_t handle (destroyed with the object)."""
+
+    def __init__(self, handle: int, desc: mk_plan_desc):
+        self.handle = handle
+        self.desc = desc
+        self.nf = 0
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                load_library().mk_destroy(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def mk_plan(nr: int, ns: int, nt: int, dt: float, dx: float, band: Optional[Tuple[int, int]] = None,
+            nf_max: int = 1, rprec: int = MK_R_C64, flags: int = 0, div_factor: float = 0.0,
+            stream: Optional[int] = None) -> Plan:
+    lib = load_library()
+    lo, hi = band if band is not None else (0, nt // 2)
+    if stream is None:
+        stream = _current_stream()
+    d = mk_plan_desc(nr, ns, nt, lo, hi, nf_max, dt, dx, div_factor, rprec, flags, stream)
+    h = ctypes.c_void_p()
+    _check(lib.mk_plan(ctypes.byref(d), ctypes.byref(h)), None)
+    return Plan(h.value, d)
+
+
+def mk_load_R(plan: Plan, R) -> None:
+    """R: complex64 [nr][B][ns] (numpy or torch, host or device)."""
+    if _is_torch(R) and R.dtype.is_complex:
+        import torch
+
+        R = torch.view_as_real(R)
+        ptr, dev, keep = _ptr(R, "float32")
+    elif isinstance(R, np.ndarray) and np.iscomplexobj(R):
+        keep = np.ascontiguousarray(R, dtype=np.complex64)
+        ptr, dev = keep.ctypes.data, 0
+    else:
+        ptr, dev, keep = _ptr(R, "float32")
+    _check(load_library().mk_load_R(plan.handle, ptr, dev), plan.handle)
+
+
+def mk_set_focal(plan: Plan, Gd, itd, shift: int, band=None) -> None:
+    """Gd float32 [nf][nr][nt], itd int32 [nf][nr], band int32 [nf][2] or None."""
+    gp, gdev, gk = _ptr(Gd, "float32")
+    ip, idev, ik = _ptr(itd, "int32")
+    bp, bdev, bk = _ptr(band, "int32")
+    if band is not None and bdev != gdev:
+        raise ValueError("Gd and band must both be host or both be device arrays")
+    if idev != gdev:
+        raise ValueError("Gd and itd must both be host or both be device arrays")
+    nf = int(Gd.shape[0])
+    _check(load_library().mk_set_focal(plan.handle, nf, gp, ip, int(shift), bp, gdev), plan.handle)
+    plan.nf = nf
+
+
+def mk_iterate(plan: Plan, niter: int, want_norms: bool = True) -> Optional[np.ndarray]:
+    """Run niter passes; returns ||N_i|| as float64 [niter][nf] (synchronises) or None."""
+    if want_norms and niter > 0:
+        out = np.zeros((niter, plan.nf), dtype=np.float64)
+        _check(load_library().mk_iterate(plan.handle, int(niter), out.ctypes.data), plan.handle)
+        return out
+    _check(load_library().mk_iterate(plan.handle, int(niter), None), plan.handle)
+    return None
+
+
+def mk_get(plan: Plan, field, out=None):
+    """Copy a field [nf][nr][nt] float32 into out (torch device tensor or numpy), returns out."""
+    fid = FIELDS[field] if isinstance(field, str) else int(field)
+    shape = (plan.nf, plan.desc.nr, plan.desc.nt)
+    if out is None:
+        import torch
+
+        out = torch.empty(shape, dtype=torch.float32, device="cuda")
+    if tuple(out.shape) != shape:
+        raise ValueError(f"out must have shape {shape}")
+    if _is_torch(out):
+        ptr, dev, _ = _ptr(out, "float32")
+    else:
+        if out.dtype != np.float32 or not out.flags.c_contiguous:
+            raise TypeError("out must be a C-contiguous float32 array")
+        ptr, dev = out.ctypes.data, 0
+    _check(load_library().mk_get(plan.handle, fid, ptr, dev), plan.handle)
+    return out
+
+
+def mk_passes(plan: Plan) -> int:
+    v = ctypes.c_int32()
+    _check(load_library().mk_passes(plan.handle, ctypes.byref(v)), plan.handle)
+    return v.value
+
+
+def mk_profile(plan: Plan, kind, reset: bool = False) -> Tuple[float, int]:
+    k = KERNEL_KINDS[kind] if isinstance(kind, str) else int(kind)
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load_library().mk_profile(plan.handle, k, ctypes.byref(ms), ctypes.byref(n), int(reset)),
+           plan.handle)
+    return ms.value, n.value
+
+
+def mk_destroy(plan: Plan) -> None:
+    if plan.handle:
+        _check(load_library().mk_destroy(plan.handle), None)
+        plan.handle = None

@@ -1,0 +1,88 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2106_04649_amd import mk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mk.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:mk_status|const char\*)\s+(mk_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return mk.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ["mk_plan", "mk_load_R", "mk_set_focal", "mk_iterate", "mk_get", "mk_destroy",
+                 "mk_strerror", "mk_last_error"]:
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror(lib):
+    for s in range(7):
+        assert lib.mk_strerror(s).decode()
+    assert lib.mk_strerror(99).decode() == "unknown status"
+
+
+def _desc(**kw):
+    base = dict(nr=8, ns=8, nt=64, iw_lo=0, iw_hi=32, nf_max=1, dt=0.004, dx=10.0, div_factor=0.0,
+                rprec=0, flags=0, stream=None)
+    base.update(kw)
+    return mk.mk_plan_desc(*[base[f] for f, _ in mk.mk_plan_desc._fields_])
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(ns=9), mk.MK_ERR_ARG),                 # nr != ns
+    (dict(nr=0, ns=0), mk.MK_ERR_ARG),
+    (dict(nt=48), mk.MK_ERR_ARG),                # not a power of two
+    (dict(nt=8), mk.MK_ERR_ARG),                 # below 16
+    (dict(nt=8192, iw_hi=100), mk.MK_ERR_ARG),   # above 4096
+    (dict(iw_lo=5, iw_hi=4), mk.MK_ERR_ARG),
+    (dict(iw_hi=33), mk.MK_ERR_ARG),             # above nt/2
+    (dict(iw_lo=-1), mk.MK_ERR_ARG),
+    (dict(nf_max=0), mk.MK_ERR_ARG),
+    (dict(dt=0.0), mk.MK_ERR_ARG),
+    (dict(dx=-1.0), mk.MK_ERR_ARG),
+    (dict(dt=float("inf")), mk.MK_ERR_ARG),
+    (dict(div_factor=float("nan")), mk.MK_ERR_ARG),
+    (dict(rprec=7), mk.MK_ERR_ARG),
+    (dict(flags=0x100), mk.MK_ERR_ARG),
+])
+def test_plan_rejects_bad_descriptions(lib, kw, status):
+    d = _desc(**kw)
+    h = ctypes.c_void_p()
+    st = lib.mk_plan(ctypes.byref(d), ctypes.byref(h))
+    assert st == status
+    assert h.value is None
+    assert lib.mk_last_error(None).decode().startswith("mk_plan")
+
+
+def test_null_arguments(lib):
+    h = ctypes.c_void_p()
+    assert lib.mk_plan(None, ctypes.byref(h)) == mk.MK_ERR_ARG
+    d = _desc()
+    assert lib.mk_plan(ctypes.byref(d), None) == mk.MK_ERR_ARG
+    assert lib.mk_load_R(None, None, 0) == mk.MK_ERR_ARG
+    assert lib.mk_set_focal(None, 1, None, None, 0, None, 0) == mk.MK_ERR_ARG
+    assert lib.mk_iterate(None, 1, None) == mk.MK_ERR_ARG
+    assert lib.mk_get(None, 0, None, 0) == mk.MK_ERR_ARG
+    assert lib.mk_passes(None, None) == mk.MK_ERR_ARG
+    assert lib.mk_profile(None, 0, None, None, 0) == mk.MK_ERR_ARG
+    assert lib.mk_destroy(None) == mk.MK_OK
