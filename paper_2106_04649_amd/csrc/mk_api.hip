@@ -189,14 +189,19 @@ mk_status device_all_finite(mk_plan_t p, const float* x, int64_t n, bool* ok) {
     return MK_OK;
 }
 
+// G+ and G- from one batched synthesis of [f1+, f1-(-t)].  The spectra go to
+// X slabs [nf, 3 nf): slabs [0, nf) hold the spectrum of the last N_i, which
+// the next pass of the series still needs.
 mk_status assemble_G(mk_plan_t p) {
     const int nf = p->nf;
     TraceArgs a = trace_args(p, 2 * nf);
+    float2* Xg = p->X + (size_t)nf * p->B * p->ns_pad;
+    a.X = Xg;
     mk_status st = run_trace(p, TM_GFWD, a, 4);
     if (st != MK_OK) return st;
     hipEvent_t ev = nullptr;
     HIP_TRY(p, prof_begin(p, &ev));
-    HIP_TRY(p, launch_contract_c64(p->R, p->X, p->Y, p->d.nr, p->B, p->d.ns, p->ns_pad, 2 * nf,
+    HIP_TRY(p, launch_contract_c64(p->R, Xg, p->Y, p->d.nr, p->B, p->d.ns, p->ns_pad, 2 * nf,
                                    p->stream));
     HIP_TRY(p, prof_end(p, ev, 4));
     st = run_trace(p, TM_GOUT, a, 4);
@@ -267,7 +272,7 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     const size_t nfm = (size_t)d.nf_max;
     const size_t trace = (size_t)d.nr * d.nt;
     if ((e = dalloc(&p->R, (size_t)p->B * d.nr * p->ns_pad)) != hipSuccess) return bail(e, "R");
-    if ((e = dalloc(&p->X, 2 * nfm * p->B * p->ns_pad)) != hipSuccess) return bail(e, "X");
+    if ((e = dalloc(&p->X, 3 * nfm * p->B * p->ns_pad)) != hipSuccess) return bail(e, "X");
     if ((e = dalloc(&p->Y, 2 * nfm * p->B * d.nr)) != hipSuccess) return bail(e, "Y");
     if ((e = dalloc(&p->f1p, nfm * trace)) != hipSuccess) return bail(e, "f1+");
     if ((e = dalloc(&p->f1m, nfm * trace)) != hipSuccess) return bail(e, "f1-");
@@ -280,7 +285,7 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     if ((e = dalloc(&p->tw, (size_t)d.nt)) != hipSuccess) return bail(e, "twiddles");
     if ((e = dalloc(&p->flag, 1)) != hipSuccess) return bail(e, "flag");
     // the padding columns of X (s >= ns) must read as zero
-    if ((e = hipMemsetAsync(p->X, 0, 2 * nfm * p->B * p->ns_pad * sizeof(float2), p->stream)) !=
+    if ((e = hipMemsetAsync(p->X, 0, 3 * nfm * p->B * p->ns_pad * sizeof(float2), p->stream)) !=
         hipSuccess)
         return bail(e, "clear X");
     std::vector<float2> tw(d.nt);

@@ -62,7 +62,7 @@ struct mk_plan_s {
 
     // device memory (plan-owned)
     float2* R = nullptr;       // [B][nr][ns_pad] complex64
-    float2* X = nullptr;       // [2 nf_max][B][ns_pad]
+    float2* X = nullptr;       // [3 nf_max][B][ns_pad]: series slabs, then G-assembly slabs
     float2* Y = nullptr;       // [2 nf_max][B][nr]
     float* f1p = nullptr;      // [nf_max][nr][nt]
     float* f1m = nullptr;

@@ -47,7 +47,9 @@ def run_gpu(p, niter=None, fbands=None, R=None, flags=0, nf_max=None, on_device=
         mk.mk_set_focal(plan, p.Gd, p.itd, p.shift, fbands)
     norms = []
     for n in (chunks or [niter]):
-        if n:
+        if n == "G":                       # assemble G between chunks: must not disturb the series
+            mk.mk_get(plan, "Gplus", np.zeros((p.nf, nr, nt), np.float32))
+        elif n:
             norms.append(mk.mk_iterate(plan, n))
     out = {}
     for name in FIELD_NAMES:

@@ -98,11 +98,14 @@ def test_continuation_and_determinism():
     a = run_gpu(p, chunks=[8])
     b = run_gpu(p, chunks=[3, 0, 5])
     c = run_gpu(p, chunks=[8])
+    d = run_gpu(p, chunks=[2, "G", 3, "G", 3])
     assert b["passes"] == 8
     for k in FIELD_NAMES:
         assert np.array_equal(a[k], b[k]), k
         assert np.array_equal(a[k], c[k]), k
+        assert np.array_equal(a[k], d[k]), k
     assert np.array_equal(a["norms"], b["norms"])
+    assert np.array_equal(a["norms"], d["norms"])
 
 
 def test_zero_passes_and_zero_R():
