@@ -1,28 +1,34 @@
 """Benchmark of the Marchenko synthesis hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--nf 1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 Workload: 601 x 601 co-located shots/receivers at 5 m, nt = 2048 at 2 ms,
 complex64 R (all 1025 rfft bins, 2.96 GB), 8 seeded flat layers plus two
-dipping reflectors, focal point(s) on the 500 m deep line, 32 Neumann passes.
+dipping reflectors, focal points on the 500 m deep line, 32 Neumann passes:
+first one focal point (the headline `value`), then 64 focal points batched.
 
 One step = one whole solve of the focal batch: mk_set_focal (G_d(-t), first
 forward transform), 32 passes of mk_iterate (contraction + fused per-trace
 epilogue + FP64 norms), and the G+/G- assembly of mk_get.  All inputs are in
-HBM before the timed region starts.  value = Neumann passes per second
-(32 x steps / wall time of the steps).
+HBM before the timed region starts.  value = Neumann passes per second of
+the one-focal plain FP32 solve (32 x steps / wall time of the steps).
 
 The JSON line adds:
-  roofline      the contraction kernel's algorithmic HBM bytes per launch
+  roofline      the one-focal contraction's algorithmic HBM bytes per launch
                 divided by its average duration (HIP events on the plan's
                 stream, from a separate profiled step), against 8 TB/s;
-  cpu_baseline  the FP64 oracle timed on this host on a bounded sample of
-                the same workload.
+  cpu_baseline  the FP64 oracle timed on this host on one whole solve of the
+                same workload;
+  batched       the 64-focal batch in plain FP32 (MFMA f32) and with FP16 R
+                (MFMA f16), their contraction rooflines, the FP16/FP32
+                throughput ratio, and both paths' errors against the FP64
+                oracle on two sampled focal points.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,19 +40,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {0: 157.3, 1: 2500.0, 2: 2500.0}     # dense MFMA: fp32, fp16, bf16
+
+# HBM traffic per launch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled
+# by the factors a plain 1 GiB device copy gives: x2.0 and x1.0), valid only
+# for the kernel source it was measured on (sha256 prefix of the file).
+TRAFFIC = {
+    "k_contract_c64": {"source": "paper_2106_04649_amd/csrc/k_contract.hip",
+                       "sha": "3c2cd1184d5dae5c", "bytes": 3070776158,
+                       "profile": "profiles/k_contract_c64_601x601_nt2048_nf1.md"},
+}
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def contract_bytes(nr: int, ns: int, B: int, ncols: int, r_elem_bytes: int = 8) -> int:
+def measured_traffic(kernel: str):
+    t = TRAFFIC.get(kernel)
+    if not t:
+        return None
+    path = os.path.join(ROOT, t["source"])
+    try:
+        sha = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return t["bytes"] if sha == t["sha"] else None
+
+
+def contract_bytes(nr: int, ns: int, B: int, ncols: int, r_bytes: int = 8, x_bytes: int = 8) -> int:
     """Algorithmic HBM bytes of one contraction launch: R once, X in, Y out."""
-    return r_elem_bytes * nr * ns * B + 8 * ns * B * ncols + 8 * nr * B * ncols
+    return r_bytes * nr * ns * B + x_bytes * ns * B * ncols + 8 * nr * B * ncols
 
 
 def cpu_baseline(p, passes: int) -> dict:
-    """The FP64 oracle on this host: `passes` Neumann passes + its G assembly."""
+    """The FP64 oracle on this host: one whole solve (passes + G assembly)."""
     from oracle import SynthesisOperator, marchenko
 
     try:
@@ -65,10 +93,84 @@ def cpu_baseline(p, passes: int) -> dict:
         "unit": "iters/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"{passes} Neumann passes plus the G+/G- assembly (2 more syntheses) of the same "
-                   f"workload, nf={p.nf}, numpy FP64 (pocketfft + OpenBLAS zgemm); "
+        "sample": (f"one whole solve of the same workload: {passes} Neumann passes plus the G+/G- "
+                   f"assembly (2 more syntheses), nf={p.nf}, numpy FP64 (pocketfft + OpenBLAS zgemm); "
                    f"{t2 - t1:.1f} s, R upcast {t1 - t0:.1f} s not counted"),
     }
+
+
+class Runner:
+    """One plan on one workload; times whole solves."""
+
+    def __init__(self, p, rprec=0, flags=0, tune=None, niter=32):
+        import torch
+
+        from paper_2106_04649_amd import mk
+
+        self.mk, self.torch, self.p, self.niter = mk, torch, p, niter
+        self.stream = torch.cuda.current_stream()
+        nr, nt = p.Rhat.shape[0], p.geom.nt
+        self.plan = mk.mk_plan(nr, nr, nt, p.geom.dt, p.geom.dx, band=p.band, nf_max=p.nf, rprec=rprec,
+                               flags=flags, stream=self.stream.cuda_stream)
+        R_d = torch.from_numpy(p.Rhat).cuda()
+        mk.mk_load_R(self.plan, R_d)
+        del R_d
+        torch.cuda.empty_cache()
+        if tune is not None:
+            mk.mk_tune(self.plan, tune)
+        self.Gd = torch.from_numpy(p.Gd).cuda()
+        self.itd = torch.from_numpy(p.itd).cuda()
+        self.fb = torch.from_numpy(p.fbands).cuda() if p.fbands is not None else None
+        self.out_p = torch.empty(p.Gd.shape, dtype=torch.float32, device="cuda")
+        self.out_m = torch.empty_like(self.out_p)
+
+    def step(self):
+        mk = self.mk
+        mk.mk_set_focal(self.plan, self.Gd, self.itd, self.p.shift, self.fb)
+        mk.mk_iterate(self.plan, self.niter, want_norms=False)
+        mk.mk_get(self.plan, "Gplus", self.out_p)
+        mk.mk_get(self.plan, "Gminus", self.out_m)
+
+    def time(self, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def norms(self):
+        self.mk.mk_set_focal(self.plan, self.Gd, self.itd, self.p.shift, self.fb)
+        return self.mk.mk_iterate(self.plan, self.niter)
+
+    def fields(self, focal_idx):
+        out = {}
+        for k in ("f1plus", "f1minus", "Gplus", "Gminus"):
+            self.mk.mk_get(self.plan, k, self.out_p)
+            out[k] = self.out_p[focal_idx].cpu().numpy()
+        return out
+
+    def destroy(self):
+        self.mk.mk_destroy(self.plan)
+
+
+def profile_contract(p, rprec, tune=None):
+    """Average duration of the per-pass contraction kernel from HIP events."""
+    from paper_2106_04649_amd import mk
+
+    r = Runner(p, rprec=rprec, flags=mk.MK_FLAG_PROFILE, tune=tune)
+    r.step()
+    for kind in mk.KERNEL_KINDS:
+        mk.mk_profile(r.plan, kind, reset=True)
+    r.step()
+    times = {kind: mk.mk_profile(r.plan, kind) for kind in mk.KERNEL_KINDS}
+    variant = mk.mk_contract_variant(r.plan, p.nf)
+    r.destroy()
+    ms, n = times["contract"]
+    return ms / n / 1e3, times, variant
 
 
 def main() -> int:
@@ -77,12 +179,15 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nf", type=int, default=1)
+    ap.add_argument("--batch-nf", type=int, default=64)
     ap.add_argument("--niter", type=int, default=32)
     ap.add_argument("--cpu-passes", type=int, default=32)
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay the passes as HIP graphs")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -107,77 +212,30 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    gflags = mk.MK_FLAG_GRAPH if args.graph else 0
+
+    # ---- one focal point, plain FP32 (the headline) ---------------------------
     log(f"generating workload (nf={args.nf})")
     t = time.perf_counter()
     p = make_config("medium", nf=args.nf)
     nr, nt, B = p.Rhat.shape[0], p.geom.nt, p.Rhat.shape[1]
     log(f"generated in {time.perf_counter() - t:.1f} s: R {p.Rhat.nbytes / 1e9:.2f} GB")
-
-    stream = torch.cuda.current_stream()
-    R_d = torch.from_numpy(p.Rhat).cuda()
-    Gd_d = torch.from_numpy(p.Gd).cuda()
-    itd_d = torch.from_numpy(p.itd).cuda()
-    out_p = torch.empty(p.Gd.shape, dtype=torch.float32, device="cuda")
-    out_m = torch.empty_like(out_p)
-
-    def make_plan(flags=0):
-        pl = mk.mk_plan(nr, nr, nt, p.geom.dt, p.geom.dx, band=p.band, nf_max=p.nf, flags=flags,
-                        stream=stream.cuda_stream)
-        mk.mk_load_R(pl, R_d)
-        return pl
-
-    def step(pl):
-        mk.mk_set_focal(pl, Gd_d, itd_d, p.shift)
-        mk.mk_iterate(pl, args.niter, want_norms=False)
-        mk.mk_get(pl, "Gplus", out_p)
-        mk.mk_get(pl, "Gminus", out_m)
-
-    plan = make_plan()
-    del R_d
-    torch.cuda.empty_cache()
-    for i in range(args.warmup):
-        step(plan)
-        log(f"warmup step {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for i in range(args.steps):
-        step(plan)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    log(f"timed {args.steps} steps: wall {wall * 1e3:.1f} ms, events {gpu_ms:.1f} ms")
+    run = Runner(p, flags=gflags, niter=args.niter)
+    wall = run.time(args.steps, args.warmup)
     ms_per_step = wall * 1e3 / args.steps
     value = args.niter * args.steps / wall
-    # convergence check outside the timed region: one more solve with norms
-    mk.mk_set_focal(plan, Gd_d, itd_d, p.shift)
-    norms = mk.mk_iterate(plan, args.niter)
-    mk.mk_destroy(plan)
+    norms = run.norms()
+    run.destroy()
+    log(f"plain nf={p.nf}: {ms_per_step:.2f} ms/step -> {value:.1f} iters/s")
 
-    roof = None
-    extra = {}
+    roof, extra = None, {}
     if not args.no_profile:
-        R_d = torch.from_numpy(p.Rhat).cuda()
-        pplan = make_plan(mk.MK_FLAG_PROFILE)
-        del R_d
-        torch.cuda.empty_cache()
-        step(pplan)
-        for kind in mk.KERNEL_KINDS:
-            mk.mk_profile(pplan, kind, reset=True)
-        step(pplan)
-        times = {kind: mk.mk_profile(pplan, kind) for kind in mk.KERNEL_KINDS}
-        mk.mk_destroy(pplan)
-        ms, n = times["contract"]
-        avg_s = ms / n / 1e3
+        avg_s, times, _ = profile_contract(p, 0)
         nbytes = contract_bytes(nr, nr, B, p.nf)
         achieved = nbytes / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_contract_c64", "avg_us": round(avg_s * 1e6, 2),
-                "bytes_per_launch": nbytes}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("k_contract_c64"),
+                "kernel": "k_contract_c64", "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": nbytes}
         extra["kernel_ms_per_step"] = {k: round(v[0], 3) for k, v in times.items()}
         extra["kernel_launches_per_step"] = {k: v[1] for k, v in times.items()}
         log(f"contraction avg {avg_s * 1e6:.1f} us -> {achieved:.0f} GB/s "
@@ -188,6 +246,54 @@ def main() -> int:
         log(f"timing the FP64 oracle on {args.cpu_passes} passes")
         cpu = cpu_baseline(p, args.cpu_passes)
         log(f"oracle: {cpu['value']:.3f} iters/s on {cpu['cores']} threads")
+
+    # ---- a batch of focal points: plain FP32 vs FP16 R -----------------------
+    batched = None
+    if not args.no_batched and args.batch_nf > 1:
+        from oracle import SynthesisOperator, marchenko, rel_l2
+
+        log(f"generating the batch (nf={args.batch_nf})")
+        pb = make_config("medium", nf=args.batch_nf)
+        batched = {"nf": pb.nf, "paths": {}}
+        sample = [0, pb.nf - 1]
+        sub = type(pb)(**{**pb.__dict__, "Gd": pb.Gd[sample], "itd": pb.itd[sample]})
+        ref = marchenko(SynthesisOperator(pb.Rhat, pb.band, pb.c, pb.geom.nt), sub.Gd, sub.itd,
+                        sub.shift, args.niter)
+        for name, rprec in (("fp32", 0), ("fp16", 1)):
+            r = Runner(pb, rprec=rprec, flags=gflags, niter=args.niter)
+            w = r.time(args.steps, args.warmup)
+            r.norms()
+            got = r.fields(sample)
+            r.destroy()
+            err = {k: max(rel_l2(got[k][j], ref[k][j]) for j in range(len(sample)))
+                   for k in ("f1plus", "f1minus", "Gplus", "Gminus")}
+            ent = {"iters_per_s": round(args.niter * args.steps / w, 2),
+                   "focal_iters_per_s": round(args.niter * args.steps * pb.nf / w, 1),
+                   "ms_per_step": round(w * 1e3 / args.steps, 3),
+                   "max_rel_l2_vs_oracle": {k: float(f"{v:.3e}") for k, v in err.items()}}
+            if not args.no_profile:
+                avg_s, times, variant = profile_contract(pb, rprec)
+                flops = 8.0 * nr * nr * B * pb.nf
+                rb = 8 if rprec == 0 else 4
+                xb = 8 if variant == 0 or rprec == 0 else 4
+                nbytes = contract_bytes(nr, nr, B, pb.nf, r_bytes=rb, x_bytes=xb)
+                tf = flops / avg_s / 1e12
+                gbs = nbytes / avg_s / 1e9
+                t_mfma = flops / (PEAK_TFLOPS[rprec] * 1e12)
+                t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+                bound = "mfma" if t_mfma > t_hbm else "hbm"
+                ent["contract"] = {
+                    "variant": variant, "avg_us": round(avg_s * 1e6, 1),
+                    "tflops": round(tf, 1), "gbs": round(gbs, 1), "bound": bound,
+                    "frac": round(tf / PEAK_TFLOPS[rprec] if bound == "mfma" else gbs / HBM_PEAK_GBS, 4),
+                    "peak": PEAK_TFLOPS[rprec] if bound == "mfma" else HBM_PEAK_GBS,
+                    "unit": "TFLOP/s" if bound == "mfma" else "GB/s"}
+                ent["kernel_ms_per_step"] = {k: round(v[0], 3) for k, v in times.items()}
+            batched["paths"][name] = ent
+            log(f"batched {name}: {ent['iters_per_s']} iters/s, err {err}")
+        f32 = batched["paths"]["fp32"]["iters_per_s"]
+        f16 = batched["paths"]["fp16"]["iters_per_s"]
+        batched["fp16_over_fp32"] = round(f16 / f32, 3)
 
     rec = {
         "metric": "Marchenko iters/s + HBM TB/s; mixed+learned vs plain FP32 at rel.err 1e-3",
@@ -205,11 +311,12 @@ def main() -> int:
         "config": {"workload": f"601x601 shots/receivers, nt=2048, complex64 R 2.96 GB, "
                                f"plain FP32, nf={p.nf}, {args.niter} passes + G assembly",
                    "nr": nr, "ns": nr, "nt": nt, "bins": B, "nf": p.nf, "niter": args.niter,
-                   "path": "plain-fp32"},
+                   "path": "plain-fp32", "graph": bool(args.graph)},
         "hbm_tbs": round(roof["achieved"] / 1e3, 3) if roof else None,
         "roofline": roof,
         "cpu_baseline": cpu,
         "norm_decay": float((norms[-1] / norms[0]).max()),
+        "batched": batched,
     }
     rec.update(extra)
     print(json.dumps(rec), flush=True)

@@ -64,13 +64,13 @@ typedef enum {
     MK_F1PLUS = 0,   /* f1+ : N_{-1} plus the odd-pass terms  (Algorithm 1)    */
     MK_F1MINUS = 1,  /* f1- : minus the time-reversed even-pass terms          */
     MK_GPLUS = 2,    /* G+  : f1+(-t) - S[f1-(-t)]   (one extra synthesis)     */
-    MK_GMINUS = 3,   /* G-  : S[f1+] - f1-           (last lines of Alg. 1)    */
-    MK_NLAST = 4     /* N_i of the last pass (muted, time-reversed field)      */
+    MK_GMINUS = 3    /* G-  : S[f1+] - f1-           (last lines of Alg. 1)    */
 } mk_field;
 
 /* Plan flags. */
-#define MK_FLAG_GRAPH   0x1u  /* replay the per-pass kernels as a HIP graph   */
-#define MK_FLAG_PROFILE 0x2u  /* time every kernel with HIP events            */
+#define MK_FLAG_GRAPH    0x1u  /* replay the per-pass kernels as a HIP graph   */
+#define MK_FLAG_PROFILE  0x2u  /* time every kernel with HIP events            */
+#define MK_FLAG_AUTOTUNE 0x4u  /* time the contraction variants on first use   */
 
 typedef struct {
     int32_t nr;          /* receivers (output positions x_R)                    */
@@ -92,9 +92,15 @@ typedef struct {
  * Follows the problem statement of the Theory section (R, G_d, the mute and
  * niter are the inputs) and the batching of Algorithm 2.  Allocates the
  * plan's device workspace for nf_max focal points.
+ * rprec selects the storage of R: MK_R_C64 keeps complex64; MK_R_F16S and
+ * MK_R_BF16S keep 16-bit pairs with one FP32 scale per frequency (the
+ * contraction accumulates in FP32; the norms and the final G subtraction
+ * stay in FP64).
  * Errors: MK_ERR_ARG (null pointers, nr != ns, nt not a power of two in
  * [16, 4096], band outside [0, nt/2], nf_max < 1, dt or dx not positive,
- * unknown rprec), MK_ERR_OOM, MK_ERR_HIP.  *out is NULL on failure.
+ * unknown rprec or flag), MK_ERR_UNSUPPORTED (ns > 2048 with MK_R_C64,
+ * ns > 4096), MK_ERR_OOM, MK_ERR_HIP.  *out is NULL on
+ * failure.
  */
 mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out);
 
@@ -117,7 +123,10 @@ mk_status mk_load_R(mk_plan_t plan, const float* R, int on_device);
  * Algorithm 1's applyMute); shift: mute margin in samples (>= 0).
  * band: int32 [nf][2] per-focal inclusive rfft-bin band inside the plan
  * band, or NULL for the plan band.  All four arrays are host or device per
- * on_device.  Runs the first forward transform on the GPU.
+ * on_device.  Runs the first forward transform on the GPU.  With bands, the
+ * plan orders the focal points by band end internally (the batch active at
+ * a bin is then a prefix, and the batched contraction skips the rest);
+ * every output and norm comes back in the caller's order.
  * Errors: MK_ERR_ARG (nf outside [1, nf_max], null Gd or itd, negative
  * shift, band outside the plan band, non-finite Gd), MK_ERR_STATE (R not
  * loaded), MK_ERR_HIP.
@@ -128,7 +137,11 @@ mk_status mk_set_focal(mk_plan_t plan, int32_t nf, const float* Gd, const int32_
 /*
  * mk_iterate -- run niter more passes of Algorithm 1's loop.
  * Pass i: RN_i = S(N_{i-1}); N_i = theta(-RN_i(-t)); even i: f1- -= N_i(-t);
- * odd i: f1+ += N_i.  Continues the series across calls.
+ * odd i: f1+ += N_i.  Continues the series across calls.  With
+ * MK_FLAG_GRAPH the passes of one call are captured once per (niter, parity
+ * of the first pass) as a HIP graph of kernel launches and replayed on later
+ * calls (not while the autotuner still has to time the batch, and not with
+ * MK_FLAG_PROFILE).
  * norms: host double [niter][nf] receiving ||N_i||_2 (FP64 reduction), or
  * NULL.  With norms != NULL the call synchronises and returns
  * MK_ERR_DIVERGED when a norm is non-finite or exceeds div_factor times
@@ -149,6 +162,26 @@ mk_status mk_iterate(mk_plan_t plan, int32_t niter, double* norms);
  * set), MK_ERR_HIP.
  */
 mk_status mk_get(mk_plan_t plan, int32_t field, float* out, int on_device);
+
+/*
+ * mk_tune -- choose how the contraction (the space integral of Eq. (1),
+ * segmented dot products of Algorithm 2) runs.  mode -1: built-in
+ * heuristic; -2: autotune (time every variant once per column count at its
+ * first use and keep the fastest; with the environment variable
+ * MK_TUNE_CACHE naming a file, choices are read from and appended to it);
+ * 0: the streaming GEMV; v >= 1: MFMA tile shape v - 1.  The storage of X
+ * follows from the choice, so the focal points must be set again after
+ * this call (MK_ERR_STATE otherwise).
+ * Errors: MK_ERR_ARG (null plan, mode outside [-2, 5]).
+ */
+mk_status mk_tune(mk_plan_t plan, int32_t mode);
+
+/*
+ * mk_contract_variant -- the contraction variant (0 GEMV, v >= 1 MFMA shape
+ * v - 1) the plan uses, or has tuned, for ncols focal columns.
+ * Errors: MK_ERR_ARG (null, ncols < 1).
+ */
+mk_status mk_contract_variant(mk_plan_t plan, int32_t ncols, int32_t* variant);
 
 /*
  * mk_passes -- number of passes applied since the last mk_set_focal.

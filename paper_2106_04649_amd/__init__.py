@@ -11,6 +11,7 @@ from .mk import (  # noqa: F401
     MK_F1PLUS,
     MK_FLAG_GRAPH,
     MK_FLAG_PROFILE,
+    MK_FLAG_AUTOTUNE,
     MK_GMINUS,
     MK_GPLUS,
     MK_R_BF16S,
@@ -26,4 +27,6 @@ from .mk import (  # noqa: F401
     mk_plan,
     mk_profile,
     mk_set_focal,
+    mk_tune,
+    mk_contract_variant,
 )

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmk.so")
-SOURCES = ["k_contract.hip", "k_trace.hip", "mk_api.hip"]
+SOURCES = ["k_contract.hip", "k_mfma.hip", "k_quant.hip", "k_trace.hip", "mk_api.hip"]
 ARCH = "gfx950"
 
 

@@ -1,22 +1,22 @@
-// The space integral of Eq. (1) in the frequency domain:
-//   Y[f][w][r] = sum_s R[w][r][s] * X[f][w][s]
+// The space integral of Eq. (1) in the frequency domain, few focal columns:
+//   Y[f][w][r] = rscale[w] * sum_s R[w][r][s] * X[f][w][s]
 // for every stored bin w, receiver r and focal column f (the Riemann weight
 // c is applied by the per-trace kernel).  This is the paper's segmented dot
 // product (Algorithm 2: pointwise multiply + segmented reduction), done in
 // one pass so that R crosses HBM exactly once per pass.
 //
-// R is held frequency-major, [B][nr][ns_pad] complex64, so the rows of one
-// frequency slice are contiguous.  A wavefront owns a run of consecutive
-// rows q = w * nr + r; it keeps X[f][w][:] in registers (reloaded only when
-// the run crosses into the next frequency), streams its rows with
-// non-temporal 16-byte loads (two complex values per lane per load), reduces
-// each row across the wave with DPP adds, and stores the run's results with
-// one coalesced store per focal column.
+// R is held frequency-major, [B][nr][ns_pad], as complex64 or as FP16/BF16
+// pairs with a per-frequency scale.  A wavefront owns a run of consecutive
+// rows q = w * nr + r; it keeps X[f][w][:] (FP32) in registers (reloaded only
+// when the run crosses into the next frequency), streams its rows with
+// non-temporal 16-byte loads, reduces each row across the wave with DPP adds,
+// and stores the run's results with one coalesced store per focal column.
 #include "mk_internal.h"
 
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 4;          // waves per block
 constexpr int kRowsPerWave = 32;   // rows per wave run (<= 64)
@@ -32,6 +32,19 @@ __device__ __forceinline__ float wave_sum_to63(float v) {
     return v;
 }
 
+// (re, im) of one 16-bit complex pair
+template <int PREC>
+__device__ __forceinline__ float2 unpack16(uint32_t u) {
+    if constexpr (PREC == MK_R_F16S) {
+        const _Float16 lo = __builtin_bit_cast(_Float16, (uint16_t)(u & 0xFFFFu));
+        const _Float16 hi = __builtin_bit_cast(_Float16, (uint16_t)(u >> 16));
+        return make_float2((float)lo, (float)hi);
+    } else {
+        return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xFFFF0000u));
+    }
+}
+
+// Complex64 R: one 16-byte load = 2 complex values.
 template <int J, int NF>
 __global__ __launch_bounds__(kWaves * 64) void k_contract_c64(
     const v4f* __restrict__ R, const v4f* __restrict__ X, float2* __restrict__ Y,
@@ -102,32 +115,126 @@ __global__ __launch_bounds__(kWaves * 64) void k_contract_c64(
     }
 }
 
+// FP16/BF16 R with per-frequency scale: one 16-byte load = 4 complex values.
+template <int J, int NF, int PREC>
+__global__ __launch_bounds__(kWaves * 64) void k_contract_q16(
+    const v4u* __restrict__ R, const v4f* __restrict__ X, const float* __restrict__ rscale,
+    float2* __restrict__ Y, int nr, int n16, int nload16, int n4, int64_t nrows, int64_t xstride4,
+    int64_t ystride) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int64_t q0 = wave * kRowsPerWave;
+    if (q0 >= nrows) return;
+    const int64_t q1 = q0 + kRowsPerWave < nrows ? q0 + kRowsPerWave : nrows;
+
+    int w = (int)(q0 / nr);
+    v4f xr[NF][J][2];
+    auto load_x = [&](int wq) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const v4f* xp = X + f * xstride4 + (int64_t)wq * n4;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int i = lane + 64 * j;
+                xr[f][j][0] = i < nload16 ? xp[2 * i] : v4f{0.f, 0.f, 0.f, 0.f};
+                xr[f][j][1] = i < nload16 ? xp[2 * i + 1] : v4f{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+    };
+    load_x(w);
+    float sc = rscale[w];
+
+    float2 mine[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) mine[f] = make_float2(0.f, 0.f);
+
+    for (int64_t q = q0; q < q1; ++q) {
+        const int wq = (int)(q / nr);
+        if (wq != w) {
+            w = wq;
+            load_x(w);
+            sc = rscale[w];
+        }
+        const v4u* row = R + q * n16;
+        v4u a[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int i = lane + 64 * j;
+            a[j] = i < nload16 ? __builtin_nontemporal_load(row + i) : v4u{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float2 r0 = unpack16<PREC>(a[j][2 * h]);
+                    const float2 r1 = unpack16<PREC>(a[j][2 * h + 1]);
+                    const v4f x4 = xr[f][j][h];
+                    re = fmaf(r0.x, x4.x, re);
+                    re = fmaf(-r0.y, x4.y, re);
+                    re = fmaf(r1.x, x4.z, re);
+                    re = fmaf(-r1.y, x4.w, re);
+                    im = fmaf(r0.x, x4.y, im);
+                    im = fmaf(r0.y, x4.x, im);
+                    im = fmaf(r1.x, x4.w, im);
+                    im = fmaf(r1.y, x4.z, im);
+                }
+            }
+            re = wave_sum_to63(re);
+            im = wave_sum_to63(im);
+            const float sre = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(re), 63));
+            const float sim = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(im), 63));
+            if (lane == (int)(q - q0)) mine[f] = make_float2(sre * sc, sim * sc);
+        }
+    }
+    if (q0 + lane < q1) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) Y[f * ystride + q0 + lane] = mine[f];
+    }
+}
+
+template <int J, int NF>
+void launch_one(const ContractArgs& c, const float2* X, float2* Yc, dim3 grid, dim3 block,
+                hipStream_t s) {
+    const int64_t nrows = (int64_t)c.B * c.nr;
+    const int64_t xstride4 = (int64_t)c.B * (c.ns_pad / 2);
+    const int64_t ystride = (int64_t)c.B * c.nr;
+    if (c.prec == MK_R_C64) {
+        hipLaunchKernelGGL((k_contract_c64<J, NF>), grid, block, 0, s,
+                           reinterpret_cast<const v4f*>(c.R), reinterpret_cast<const v4f*>(X), Yc, c.nr,
+                           c.ns_pad / 2, (c.ns + 1) / 2, nrows, xstride4, ystride);
+    } else if (c.prec == MK_R_F16S) {
+        hipLaunchKernelGGL((k_contract_q16<J, NF, MK_R_F16S>), grid, block, 0, s,
+                           reinterpret_cast<const v4u*>(c.R), reinterpret_cast<const v4f*>(X), c.rscale,
+                           Yc, c.nr, c.ns_pad / 4, (c.ns + 3) / 4, c.ns_pad / 2, nrows, xstride4, ystride);
+    } else {
+        hipLaunchKernelGGL((k_contract_q16<J, NF, MK_R_BF16S>), grid, block, 0, s,
+                           reinterpret_cast<const v4u*>(c.R), reinterpret_cast<const v4f*>(X), c.rscale,
+                           Yc, c.nr, c.ns_pad / 4, (c.ns + 3) / 4, c.ns_pad / 2, nrows, xstride4, ystride);
+    }
+}
+
 template <int J>
-hipError_t launch_j(const float2* R, const float2* X, float2* Y, int nr, int B, int ns, int ns_pad,
-                    int ncols, hipStream_t s) {
-    const int n4 = ns_pad / 2;
-    const int nload4 = (ns + 1) / 2;
-    const int64_t nrows = (int64_t)B * nr;
-    const int64_t xstride4 = (int64_t)B * n4;
-    const int64_t ystride = (int64_t)B * nr;
+hipError_t launch_j(const ContractArgs& c, hipStream_t s) {
+    const int64_t nrows = (int64_t)c.B * c.nr;
     const int64_t waves = (nrows + kRowsPerWave - 1) / kRowsPerWave;
     const dim3 grid((unsigned)((waves + kWaves - 1) / kWaves)), block(kWaves * 64);
-    const v4f* R4 = reinterpret_cast<const v4f*>(R);
-    for (int c0 = 0; c0 < ncols;) {
-        const int left = ncols - c0;
-        const v4f* X4 = reinterpret_cast<const v4f*>(X) + c0 * xstride4;
-        float2* Yc = Y + c0 * ystride;
+    const int64_t xslab = (int64_t)c.B * c.ns_pad;     // complex elements per focal slab
+    const int64_t yslab = (int64_t)c.B * c.nr;
+    for (int c0 = 0; c0 < c.ncols;) {
+        const int left = c.ncols - c0;
+        const float2* X = reinterpret_cast<const float2*>(c.X) + c0 * xslab;
+        float2* Yc = c.Y + c0 * yslab;
         if (left >= 4) {
-            hipLaunchKernelGGL((k_contract_c64<J, 4>), grid, block, 0, s, R4, X4, Yc, nr, n4, nload4,
-                               nrows, xstride4, ystride);
+            launch_one<J, 4>(c, X, Yc, grid, block, s);
             c0 += 4;
         } else if (left >= 2) {
-            hipLaunchKernelGGL((k_contract_c64<J, 2>), grid, block, 0, s, R4, X4, Yc, nr, n4, nload4,
-                               nrows, xstride4, ystride);
+            launch_one<J, 2>(c, X, Yc, grid, block, s);
             c0 += 2;
         } else {
-            hipLaunchKernelGGL((k_contract_c64<J, 1>), grid, block, 0, s, R4, X4, Yc, nr, n4, nload4,
-                               nrows, xstride4, ystride);
+            launch_one<J, 1>(c, X, Yc, grid, block, s);
             c0 += 1;
         }
         hipError_t e = hipGetLastError();
@@ -164,23 +271,24 @@ __global__ void k_check_finite(const float* __restrict__ x, int64_t n, int* __re
 
 }  // namespace
 
-hipError_t launch_contract_c64(const float2* R, const float2* X, float2* Y, int nr, int B, int ns,
-                               int ns_pad, int ncols, hipStream_t s) {
-    const int nload4 = (ns + 1) / 2;
-    const int J = (nload4 + 63) / 64;
+hipError_t launch_contract_gemv(const ContractArgs& c, hipStream_t s) {
+    // 16-byte chunks per row: 2 complex (complex64) or 4 complex (16-bit)
+    const int per = c.prec == MK_R_C64 ? 2 : 4;
+    const int nload = (c.ns + per - 1) / per;
+    const int J = (nload + 63) / 64;
     switch (J) {
-        case 1: return launch_j<1>(R, X, Y, nr, B, ns, ns_pad, ncols, s);
-        case 2: return launch_j<2>(R, X, Y, nr, B, ns, ns_pad, ncols, s);
-        case 3: return launch_j<3>(R, X, Y, nr, B, ns, ns_pad, ncols, s);
-        case 4: return launch_j<4>(R, X, Y, nr, B, ns, ns_pad, ncols, s);
-        case 5: return launch_j<5>(R, X, Y, nr, B, ns, ns_pad, ncols, s);
-        case 6: return launch_j<6>(R, X, Y, nr, B, ns, ns_pad, ncols, s);
-        case 7: return launch_j<7>(R, X, Y, nr, B, ns, ns_pad, ncols, s);
-        case 8: return launch_j<8>(R, X, Y, nr, B, ns, ns_pad, ncols, s);
-        case 9: case 10: return launch_j<10>(R, X, Y, nr, B, ns, ns_pad, ncols, s);
-        case 11: case 12: return launch_j<12>(R, X, Y, nr, B, ns, ns_pad, ncols, s);
-        case 13: case 14: case 15: case 16: return launch_j<16>(R, X, Y, nr, B, ns, ns_pad, ncols, s);
-        default: return hipErrorInvalidValue;   // ns > 2048
+        case 1: return launch_j<1>(c, s);
+        case 2: return launch_j<2>(c, s);
+        case 3: return launch_j<3>(c, s);
+        case 4: return launch_j<4>(c, s);
+        case 5: return launch_j<5>(c, s);
+        case 6: return launch_j<6>(c, s);
+        case 7: return launch_j<7>(c, s);
+        case 8: return launch_j<8>(c, s);
+        case 9: case 10: return launch_j<10>(c, s);
+        case 11: case 12: return launch_j<12>(c, s);
+        case 13: case 14: case 15: case 16: return launch_j<16>(c, s);
+        default: return hipErrorInvalidValue;   // ns > 2048 (complex64) / 4096 (16-bit)
     }
 }
 

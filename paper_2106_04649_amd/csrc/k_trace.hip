@@ -30,16 +30,17 @@ __device__ __forceinline__ float2 twid(const float2* __restrict__ tw, int idx) {
     return t;
 }
 
-// In-place complex transform of M = NT/2 points held in LDS by one wave.
+// In-place complex transform of M = NT/2 points held in LDS by the TPT
+// threads that own one trace (one wave, or the whole block).
 // DIR = -1: forward (exp(-i...)), DIR = +1: inverse, both unnormalised.
-// Barriers are block-wide; every wave of the block calls this with the same NT.
-template <int NT, int DIR>
-__device__ void fft_wave(float2* z, const float2* __restrict__ tw, int lane) {
+// Barriers are block-wide; every thread of the block calls this with the same NT.
+template <int NT, int DIR, int TPT>
+__device__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
     constexpr int M = NT / 2;
     constexpr int LOG2M = ilog2c(M);
     constexpr int N4 = LOG2M / 2;
     constexpr int Q = M / 4;
-    constexpr int PER4 = (Q + 63) / 64;
+    constexpr int PER4 = (Q + TPT - 1) / TPT;
 #pragma unroll
     for (int st = 0; st < N4; ++st) {
         const int lns = 2 * st;          // log2 of the current sub-transform span Ns
@@ -47,7 +48,7 @@ __device__ void fft_wave(float2* z, const float2* __restrict__ tw, int lane) {
         float2 v[PER4][4];
 #pragma unroll
         for (int p = 0; p < PER4; ++p) {
-            const int j = lane + 64 * p;
+            const int j = lane + TPT * p;
             if (j < Q) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v[p][q] = z[j + q * Q];
@@ -56,7 +57,7 @@ __device__ void fft_wave(float2* z, const float2* __restrict__ tw, int lane) {
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < PER4; ++p) {
-            const int j = lane + 64 * p;
+            const int j = lane + TPT * p;
             if (j < Q) {
                 const int k = j & (Ns - 1);
                 const int base = k * (NT >> (lns + 2));     // k * NT / (4 Ns)
@@ -87,13 +88,13 @@ __device__ void fft_wave(float2* z, const float2* __restrict__ tw, int lane) {
     }
     if constexpr ((LOG2M & 1) != 0) {
         constexpr int H = M / 2;
-        constexpr int PER2 = (H + 63) / 64;
+        constexpr int PER2 = (H + TPT - 1) / TPT;
         constexpr int lns = 2 * N4;
         constexpr int Ns = 1 << lns;
         float2 v[PER2][2];
 #pragma unroll
         for (int p = 0; p < PER2; ++p) {
-            const int j = lane + 64 * p;
+            const int j = lane + TPT * p;
             if (j < H) {
                 v[p][0] = z[j];
                 v[p][1] = z[j + H];
@@ -102,7 +103,7 @@ __device__ void fft_wave(float2* z, const float2* __restrict__ tw, int lane) {
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < PER2; ++p) {
-            const int j = lane + 64 * p;
+            const int j = lane + TPT * p;
             if (j < H) {
                 const int k = j & (Ns - 1);
                 const float2 a0 = v[p][0];
@@ -134,22 +135,28 @@ __device__ __forceinline__ float2 unpack_bin(const float2* z, const float2* __re
     return make_float2(e.x + wd.y, e.y - wd.x);          // E - i W^k D
 }
 
-template <int NT, int MODE>
+// TPT threads own one trace: 64 (one wave, four traces per block) when the
+// launch has many traces, 256 (the whole block) when it has few, so that a
+// one-focal pass still spreads over every CU.
+template <int NT, int MODE, int TPT>
 __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     constexpr int M = NT / 2;
-    constexpr int PM = (M + 63) / 64;
-    __shared__ float2 lds[4 * M];
-    const int wv = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
+    constexpr int TPB = 256 / TPT;          // traces per block
+    constexpr int PM = (M + TPT - 1) / TPT;
+    constexpr bool GMODE = MODE == TM_GFWD || MODE == TM_GOUT;
+    __shared__ float2 lds[TPB * M];
+    __shared__ double red[4];
+    const int wv = threadIdx.x / TPT;       // trace slot in the block
+    const int lane = threadIdx.x % TPT;     // thread within the trace
     float2* z = lds + wv * M;
 
     const int ntr = a.nfo * a.nr;
-    int trace = blockIdx.x * 4 + wv;
+    int trace = blockIdx.x * TPB + wv;
     const bool valid = trace < ntr;
     if (!valid) trace = ntr - 1;            // keep the wave in the barriers, store nothing
-    const int fo = trace / a.nr;
+    const int fo = trace / a.nr;            // output column
     const int r = trace - fo * a.nr;
-    const int f = fo % a.nf;
+    const int f = GMODE ? (fo >> 1) : fo;   // focal point (G columns interleave f1+ and f1-(-t))
     const int hi = a.lo + a.B - 1;
     int flo = a.lo, fhi = hi;
     if (a.fband) {
@@ -162,7 +169,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     // ---- spectrum -> time (TM_ITER, TM_GOUT) --------------------------------
     if (MODE == TM_ITER || MODE == TM_GOUT) {
         const float2* Yt = a.Y + (size_t)fo * a.B * a.nr + r;
-        for (int k = lane; k < M; k += 64) {
+        for (int k = lane; k < M; k += TPT) {
             const int km = M - k;
             float2 xk = make_float2(0.f, 0.f), xm = make_float2(0.f, 0.f);
             if (k >= flo && k <= fhi) xk = Yt[(size_t)(k - a.lo) * a.nr];
@@ -175,7 +182,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
             z[k] = make_float2(e.x - o.y, e.y + o.x);                                      // E + i O
         }
         __syncthreads();
-        fft_wave<NT, +1>(z, a.tw, lane);
+        fft_lds<NT, +1, TPT>(z, a.tw, lane);
         // z[m] = (RN[2m], RN[2m+1]) / s
     }
 
@@ -187,7 +194,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         float* acc = (a.parity == 0) ? a.f1m : a.f1p;
 #pragma unroll
         for (int p = 0; p < PM; ++p) {
-            const int m = lane + 64 * p;
+            const int m = lane + TPT * p;
             if (m < M) {
                 const int t0 = 2 * m, t1 = 2 * m + 1;
                 const int s0 = t0 < M ? t0 : t0 - NT;
@@ -217,14 +224,14 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < PM; ++p) {
-            const int m = lane + 64 * p;
+            const int m = lane + TPT * p;
             if (m < M) z[m] = out[p];
         }
     } else if (MODE == TM_INIT) {
         const float* g = a.src + tbase;
 #pragma unroll
         for (int p = 0; p < PM; ++p) {
-            const int m = lane + 64 * p;
+            const int m = lane + TPT * p;
             if (m < M) {
                 // N_-1[t] = Gd[(nt - t) mod nt]
                 const float n0 = g[(NT - 2 * m) & (NT - 1)];
@@ -238,10 +245,10 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
             }
         }
     } else if (MODE == TM_GFWD) {
-        const bool minus = fo >= a.nf;
+        const bool minus = (fo & 1) != 0;
 #pragma unroll
         for (int p = 0; p < PM; ++p) {
-            const int m = lane + 64 * p;
+            const int m = lane + TPT * p;
             if (m < M) {
                 float2 v;
                 if (!minus) {
@@ -254,10 +261,10 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
             }
         }
     } else if (MODE == TM_GOUT) {
-        const bool plus = fo >= a.nf;
+        const bool plus = (fo & 1) != 0;
 #pragma unroll
         for (int p = 0; p < PM; ++p) {
-            const int m = lane + 64 * p;
+            const int m = lane + TPT * p;
             if (m < M && valid) {
                 const float2 zm = z[m];
                 const double rn0 = (double)(s * zm.x), rn1 = (double)(s * zm.y);
@@ -278,21 +285,77 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
 
     // ---- time -> spectrum (TM_INIT, TM_ITER, TM_GFWD) ---------------------
     __syncthreads();
-    fft_wave<NT, -1>(z, a.tw, lane);
-    float2* Xt = a.X + (size_t)fo * a.B * a.ns_pad + r;
-    for (int k = a.lo + lane; k <= hi; k += 64) {
-        float2 v = make_float2(0.f, 0.f);
-        if (k >= flo && k <= fhi) v = unpack_bin<NT>(z, a.tw, k);
-        if (valid) Xt[(size_t)(k - a.lo) * a.ns_pad] = v;
+    fft_lds<NT, -1, TPT>(z, a.tw, lane);
+    const int kend = a.skip_outband ? fhi : hi;
+    const size_t xoff = (size_t)fo * a.B * a.ns_pad + r;
+    if (a.xprec == XP_F32) {
+        float2* Xt = reinterpret_cast<float2*>(a.X) + xoff;
+        for (int k = a.lo + lane; k <= kend; k += TPT) {
+            float2 v = make_float2(0.f, 0.f);
+            if (k >= flo && k <= fhi) v = unpack_bin<NT>(z, a.tw, k);
+            if (valid) Xt[(size_t)(k - a.lo) * a.ns_pad] = v;
+        }
+    } else {
+        // 16-bit X scaled per focal point by the RMS trace norm of the previous field
+        const double nrm = a.xs_in ? a.xs_in[f] : 0.0;
+        float xs = (float)(nrm / sqrt((double)a.nr));
+        if (!(xs > 0.f) || !isfinite(xs)) xs = 1.f;
+        const float inv = 1.f / xs;
+        uint32_t* Xt = reinterpret_cast<uint32_t*>(a.X) + xoff;
+        for (int k = a.lo + lane; k <= kend; k += TPT) {
+            float2 v = make_float2(0.f, 0.f);
+            if (k >= flo && k <= fhi) v = unpack_bin<NT>(z, a.tw, k);
+            uint32_t u;
+            if (a.xprec == XP_F16) {
+                const _Float16 lo = (_Float16)(v.x * inv), hh = (_Float16)(v.y * inv);
+                u = (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hh) << 16);
+            } else {
+                uint32_t ux = __float_as_uint(v.x * inv), uy = __float_as_uint(v.y * inv);
+                ux += 0x7FFFu + ((ux >> 16) & 1u);
+                uy += 0x7FFFu + ((uy >> 16) & 1u);
+                u = (ux >> 16) | (uy & 0xFFFF0000u);
+            }
+            if (valid) Xt[(size_t)(k - a.lo) * a.ns_pad] = u;
+        }
+        if (valid && r == 0 && lane == 0) a.xs_out[fo] = xs;
     }
-    if (MODE == TM_INIT || MODE == TM_ITER) {
+    if (MODE == TM_ITER) {
         nacc = wave_sum_d(nacc);
+        if (TPT > 64) {                      // combine the block's waves in a fixed order
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nacc;
+            __syncthreads();
+            nacc = red[0] + red[1] + red[2] + red[3];
+        }
         if (valid && lane == 0) a.npart[(size_t)fo * a.nr + r] = nacc;
     }
 }
 
+// Sum of squares of each trace (FP64), one wave per trace: the norm of G_d.
+__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ x, int ntr, int nt,
+                                               double* __restrict__ npart) {
+    const int lane = threadIdx.x & 63;
+    const int trace = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (trace >= ntr) return;
+    const float* p = x + (size_t)trace * nt;
+    double acc = 0.0;
+    for (int t = lane; t < nt; t += 64) acc += (double)p[t] * p[t];
+    acc = wave_sum_d(acc);
+    if (lane == 0) npart[trace] = acc;
+}
+
+// dst[j] = src[perm[j]] for blocks of `per` floats.
+__global__ void k_gather(const float* __restrict__ src, float* __restrict__ dst,
+                         const int* __restrict__ perm, int nf, int64_t per) {
+    const int64_t total = (int64_t)nf * per;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(i / per);
+        dst[i] = src[(int64_t)perm[j] * per + (i - (int64_t)j * per)];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_norm_reduce(const double* __restrict__ npart, int nr,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, double* __restrict__ out2) {
     __shared__ double sh[256];
     const double* p = npart + (size_t)blockIdx.x * nr;
     double acc = 0.0;
@@ -303,21 +366,35 @@ __global__ __launch_bounds__(256) void k_norm_reduce(const double* __restrict__ 
         if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(sh[0]);
+    if (threadIdx.x == 0) {
+        const double v = sqrt(sh[0]);
+        out[blockIdx.x] = v;
+        if (out2) out2[blockIdx.x] = v;
+    }
 }
 
-template <int NT>
-hipError_t launch_trace_nt(int mode, const TraceArgs& a, hipStream_t s) {
+template <int NT, int TPT>
+hipError_t launch_trace_tpt(int mode, const TraceArgs& a, hipStream_t s) {
     const int ntr = a.nfo * a.nr;
-    const dim3 grid((ntr + 3) / 4), block(256);
+    constexpr int TPB = 256 / TPT;
+    const dim3 grid((ntr + TPB - 1) / TPB), block(256);
     switch (mode) {
-        case TM_INIT: hipLaunchKernelGGL((k_trace<NT, TM_INIT>), grid, block, 0, s, a); break;
-        case TM_ITER: hipLaunchKernelGGL((k_trace<NT, TM_ITER>), grid, block, 0, s, a); break;
-        case TM_GFWD: hipLaunchKernelGGL((k_trace<NT, TM_GFWD>), grid, block, 0, s, a); break;
-        case TM_GOUT: hipLaunchKernelGGL((k_trace<NT, TM_GOUT>), grid, block, 0, s, a); break;
+        case TM_INIT: hipLaunchKernelGGL((k_trace<NT, TM_INIT, TPT>), grid, block, 0, s, a); break;
+        case TM_ITER: hipLaunchKernelGGL((k_trace<NT, TM_ITER, TPT>), grid, block, 0, s, a); break;
+        case TM_GFWD: hipLaunchKernelGGL((k_trace<NT, TM_GFWD, TPT>), grid, block, 0, s, a); break;
+        case TM_GOUT: hipLaunchKernelGGL((k_trace<NT, TM_GOUT, TPT>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Few traces (fewer than 8 per CU): a whole block per trace; otherwise one wave.
+constexpr int kWholeBlockTraces = 2048;
+
+template <int NT>
+hipError_t launch_trace_nt(int mode, const TraceArgs& a, hipStream_t s) {
+    if (a.nfo * a.nr < kWholeBlockTraces) return launch_trace_tpt<NT, 256>(mode, a, s);
+    return launch_trace_tpt<NT, 64>(mode, a, s);
 }
 
 }  // namespace
@@ -338,8 +415,25 @@ hipError_t launch_trace(int mode, int nt, const TraceArgs& a, hipStream_t s) {
     }
 }
 
-hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out, hipStream_t s) {
+hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out, double* out2,
+                              hipStream_t s) {
     if (nfo <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_norm_reduce, dim3(nfo), dim3(256), 0, s, npart, nr, out);
+    hipLaunchKernelGGL(k_norm_reduce, dim3(nfo), dim3(256), 0, s, npart, nr, out, out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const float* x, int ntr, int nt, double* npart, hipStream_t s) {
+    if (ntr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sumsq, dim3((ntr + 3) / 4), dim3(256), 0, s, x, ntr, nt, npart);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const float* src, float* dst, const int* perm, int nf, int64_t per,
+                         hipStream_t s) {
+    const int64_t total = (int64_t)nf * per;
+    if (total <= 0) return hipSuccess;
+    const int64_t blocks = (total + 255) / 256;
+    const unsigned g = (unsigned)(blocks < 16384 ? blocks : 16384);
+    hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, s, src, dst, perm, nf, per);
     return hipGetLastError();
 }

@@ -1,9 +1,15 @@
 // Host side of the C ABI declared in include/mk.h: plan validation, device
-// memory, the order of kernel launches for Algorithm 1, and status codes.
+// memory, the order of kernel launches for Algorithm 1, contraction
+// selection (heuristic, forced or autotuned) and status codes.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <numeric>
+#include <sstream>
 
 #include "mk_internal.h"
 
@@ -37,6 +43,12 @@ mk_status hip_fail(mk_plan_t p, hipError_t e, const char* where) {
         if (e_ != hipSuccess) return hip_fail((p), e_, #expr);    \
     } while (0)
 
+#define MK_TRY(expr)                          \
+    do {                                      \
+        mk_status st_ = (expr);               \
+        if (st_ != MK_OK) return st_;         \
+    } while (0)
+
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 template <typename T>
@@ -46,9 +58,17 @@ hipError_t dalloc(T** ptr, size_t count) {
     return hipMalloc(reinterpret_cast<void**>(ptr), count * sizeof(T));
 }
 
+void drop_graphs(mk_plan_t p) {
+    for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    p->graphs.clear();
+}
+
 void free_plan_memory(mk_plan_t p) {
-    void* bufs[] = {p->R, p->X, p->Y, p->f1p, p->f1m, p->gp, p->gm, p->itd, p->fband,
-                    p->npart, p->norm0, p->norms, p->tw, p->flag};
+    drop_graphs(p);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    void* bufs[] = {p->R, p->rscale, p->X, p->Y, p->f1p, p->f1m, p->gp, p->gm, p->stage, p->itd,
+                    p->fband, p->perm, p->iperm, p->ncols, p->npart, p->norm0, p->nlast, p->xscale,
+                    p->norms, p->tw, p->flag};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& pe : p->pending) {
@@ -105,6 +125,124 @@ hipError_t prof_resolve(mk_plan_t p) {
     return hipSuccess;
 }
 
+// --- contraction selection -------------------------------------------------
+
+constexpr int kGemvMaxCols = 4;
+
+int xprec_of(int rprec, int variant) {
+    if (variant == 0) return XP_F32;                     // GEMV keeps X in FP32
+    if (rprec == MK_R_F16S) return XP_F16;
+    if (rprec == MK_R_BF16S) return XP_BF16;
+    return XP_F32;
+}
+
+int heuristic_variant(int ncols) {
+    if (ncols <= kGemvMaxCols) return 0;
+    if (ncols <= 16) return 1 + 3;       // 32 focal-real rows x 128 receivers
+    if (ncols <= 32) return 1 + 1;       // 64 x 64
+    return 1 + 0;                        // 128 x 64
+}
+
+ContractArgs contract_args(mk_plan_t p, const void* X, int ncols, int ncols_mul) {
+    ContractArgs c{};
+    c.R = p->R;
+    c.rscale = p->rscale;
+    c.prec = p->d.rprec;
+    c.X = X;
+    c.Y = p->Y;
+    c.ncols_w = p->has_fband ? p->ncols : nullptr;
+    c.ncols_mul = ncols_mul;
+    c.nr = p->d.nr;
+    c.ns = p->d.ns;
+    c.ns_pad = p->ns_pad;
+    c.B = p->B;
+    c.ncols = ncols;
+    return c;
+}
+
+hipError_t launch_choice(const ContractArgs& c, int variant, hipStream_t s) {
+    if (variant == 0) return launch_contract_gemv(c, s);
+    return launch_contract_mfma(c, variant - 1, s);
+}
+
+std::string tune_key(mk_plan_t p, int ncols) {
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "gfx950 nr=%d ns_pad=%d B=%d prec=%d ncols=%d banded=%d",
+                  p->d.nr, p->ns_pad, p->B, p->d.rprec, ncols, p->has_fband ? 1 : 0);
+    return buf;
+}
+
+// Time every candidate that consumes the same X storage on the plan's
+// current X (the results are overwritten by the real launch that follows)
+// and keep the fastest.  The choice is cached in the plan and, when the
+// environment variable MK_TUNE_CACHE names a file, appended to that file.
+mk_status autotune(mk_plan_t p, const void* Xbuf, const float* xs, int ncols, int ncols_mul,
+                   int xprec, int* out) {
+    for (auto& kv : p->tuned)
+        if (kv.first == ncols) {
+            *out = kv.second;
+            return MK_OK;
+        }
+    const char* path = std::getenv("MK_TUNE_CACHE");
+    const std::string key = tune_key(p, ncols);
+    if (path) {
+        std::ifstream in(path);
+        std::string line;
+        while (std::getline(in, line)) {
+            const size_t bar = line.rfind('|');
+            if (bar != std::string::npos && line.substr(0, bar) == key) {
+                const int v = std::atoi(line.c_str() + bar + 1);
+                if (v >= 0 && v <= contract_mfma_variants() && xprec_of(p->d.rprec, v) == xprec) {
+                    p->tuned.push_back({ncols, v});
+                    *out = v;
+                    return MK_OK;
+                }
+            }
+        }
+    }
+    std::vector<int> cands;
+    if (xprec_of(p->d.rprec, 0) == xprec && ncols <= 2 * kGemvMaxCols) cands.push_back(0);
+    for (int v = 0; v < contract_mfma_variants(); ++v)
+        if (xprec_of(p->d.rprec, 1 + v) == xprec) cands.push_back(1 + v);
+    hipEvent_t e0, e1;
+    HIP_TRY(p, hipEventCreate(&e0));
+    HIP_TRY(p, hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_v = cands.empty() ? 0 : cands[0];
+    for (int v : cands) {
+        ContractArgs c = contract_args(p, Xbuf, ncols, ncols_mul);
+        c.xscale = xs;
+        HIP_TRY(p, launch_choice(c, v, p->stream));     // warm
+        HIP_TRY(p, hipEventRecord(e0, p->stream));
+        for (int rep = 0; rep < 2; ++rep) HIP_TRY(p, launch_choice(c, v, p->stream));
+        HIP_TRY(p, hipEventRecord(e1, p->stream));
+        HIP_TRY(p, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(p, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            best_v = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->tuned.push_back({ncols, best_v});
+    if (path) {
+        std::ofstream o(path, std::ios::app);
+        if (o) o << key << "|" << best_v << "\n";
+    }
+    *out = best_v;
+    return MK_OK;
+}
+
+// The contraction used for ncols columns; the X storage follows from it.
+ContractChoice choose(mk_plan_t p, int ncols) {
+    ContractChoice ch;
+    ch.variant = p->tune_mode >= 0 ? p->tune_mode : heuristic_variant(ncols);
+    ch.xprec = xprec_of(p->d.rprec, ch.variant);
+    return ch;
+}
+
 // --- pieces of the series -------------------------------------------------
 
 TraceArgs trace_args(mk_plan_t p, int nfo) {
@@ -119,6 +257,10 @@ TraceArgs trace_args(mk_plan_t p, int nfo) {
     a.fband = p->has_fband ? p->fband : nullptr;
     a.npart = p->npart;
     a.tw = p->tw;
+    a.xs_in = nullptr;
+    a.xs_out = p->xscale;
+    a.xprec = XP_F32;
+    a.skip_outband = 0;
     a.nr = p->d.nr;
     a.nf = p->nf;
     a.nfo = nfo;
@@ -130,12 +272,16 @@ TraceArgs trace_args(mk_plan_t p, int nfo) {
     return a;
 }
 
-mk_status run_contract(mk_plan_t p, int ncols) {
+mk_status run_contract(mk_plan_t p, const ContractChoice& ch, const void* Xbuf, const float* xs,
+                       int ncols, int ncols_mul, int kind) {
+    int variant = ch.variant;
+    if (p->tune_mode == -2) MK_TRY(autotune(p, Xbuf, xs, ncols, ncols_mul, ch.xprec, &variant));
+    ContractArgs c = contract_args(p, Xbuf, ncols, ncols_mul);
+    c.xscale = xs;
     hipEvent_t ev = nullptr;
     HIP_TRY(p, prof_begin(p, &ev));
-    HIP_TRY(p, launch_contract_c64(p->R, p->X, p->Y, p->d.nr, p->B, p->d.ns, p->ns_pad, ncols,
-                                   p->stream));
-    HIP_TRY(p, prof_end(p, ev, 0));
+    HIP_TRY(p, launch_choice(c, variant, p->stream));
+    HIP_TRY(p, prof_end(p, ev, kind));
     return MK_OK;
 }
 
@@ -150,7 +296,7 @@ mk_status run_trace(mk_plan_t p, int mode, const TraceArgs& a, int kind) {
 mk_status run_norms(mk_plan_t p, double* out) {
     hipEvent_t ev = nullptr;
     HIP_TRY(p, prof_begin(p, &ev));
-    HIP_TRY(p, launch_norm_reduce(p->npart, p->d.nr, p->nf, out, p->stream));
+    HIP_TRY(p, launch_norm_reduce(p->npart, p->d.nr, p->nf, out, p->nlast, p->stream));
     HIP_TRY(p, prof_end(p, ev, 2));
     return MK_OK;
 }
@@ -160,6 +306,7 @@ mk_status ensure_norm_cap(mk_plan_t p, int niter) {
     int cap = p->norm_cap > 0 ? p->norm_cap : 64;
     while (cap < niter) cap *= 2;
     HIP_TRY(p, hipStreamSynchronize(p->stream));
+    drop_graphs(p);                    // captured passes point into the old buffer
     if (p->norms) HIP_TRY(p, hipFree(p->norms));
     p->norms = nullptr;
     p->norm_cap = 0;
@@ -168,7 +315,6 @@ mk_status ensure_norm_cap(mk_plan_t p, int niter) {
     return MK_OK;
 }
 
-// Copy n elements of a host or device input into plan memory.
 template <typename T>
 mk_status copy_in(mk_plan_t p, T* dst, const T* src, size_t n, int on_device, const char* what) {
     if (n == 0) return MK_OK;
@@ -189,23 +335,22 @@ mk_status device_all_finite(mk_plan_t p, const float* x, int64_t n, bool* ok) {
     return MK_OK;
 }
 
-// G+ and G- from one batched synthesis of [f1+, f1-(-t)].  The spectra go to
-// X slabs [nf, 3 nf): slabs [0, nf) hold the spectrum of the last N_i, which
-// the next pass of the series still needs.
+// G+ and G- from one batched synthesis of the interleaved columns
+// [f1+[0], f1-(-t)[0], f1+[1], ...].  Their spectra go to X slabs
+// [nf, 3 nf): slabs [0, nf) hold the spectrum of the last N_i, which the
+// next pass of the series still needs.
 mk_status assemble_G(mk_plan_t p) {
     const int nf = p->nf;
     TraceArgs a = trace_args(p, 2 * nf);
     float2* Xg = p->X + (size_t)nf * p->B * p->ns_pad;
     a.X = Xg;
-    mk_status st = run_trace(p, TM_GFWD, a, 4);
-    if (st != MK_OK) return st;
-    hipEvent_t ev = nullptr;
-    HIP_TRY(p, prof_begin(p, &ev));
-    HIP_TRY(p, launch_contract_c64(p->R, Xg, p->Y, p->d.nr, p->B, p->d.ns, p->ns_pad, 2 * nf,
-                                   p->stream));
-    HIP_TRY(p, prof_end(p, ev, 4));
-    st = run_trace(p, TM_GOUT, a, 4);
-    if (st != MK_OK) return st;
+    a.xprec = p->g_choice.xprec;
+    a.xs_in = p->norm0;
+    a.xs_out = p->xscale + nf;
+    a.skip_outband = (p->g_choice.variant != 0 && p->has_fband) ? 1 : 0;
+    MK_TRY(run_trace(p, TM_GFWD, a, 4));
+    MK_TRY(run_contract(p, p->g_choice, Xg, p->xscale + nf, 2 * nf, 2, 4));
+    MK_TRY(run_trace(p, TM_GOUT, a, 4));
     p->g_valid = true;
     return MK_OK;
 }
@@ -242,15 +387,12 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     if (!(d.dt > 0.0) || !(d.dx > 0.0) || !std::isfinite(d.dt) || !std::isfinite(d.dx))
         return fail(nullptr, MK_ERR_ARG, "mk_plan: dt and dx must be finite and positive");
     if (std::isnan(d.div_factor)) return fail(nullptr, MK_ERR_ARG, "mk_plan: div_factor is NaN");
-    if (d.rprec != MK_R_C64) {
-        if (d.rprec == MK_R_F16S || d.rprec == MK_R_BF16S)
-            return fail(nullptr, MK_ERR_UNSUPPORTED, "mk_plan: reduced-precision R is not built");
+    if (d.rprec != MK_R_C64 && d.rprec != MK_R_F16S && d.rprec != MK_R_BF16S)
         return fail(nullptr, MK_ERR_ARG, "mk_plan: unknown rprec");
-    }
-    if (d.flags & ~(MK_FLAG_GRAPH | MK_FLAG_PROFILE))
+    if (d.rprec == MK_R_C64 && d.ns > 2048)
+        return fail(nullptr, MK_ERR_UNSUPPORTED, "mk_plan: complex64 R supports ns <= 2048");
+    if (d.flags & ~(MK_FLAG_GRAPH | MK_FLAG_PROFILE | MK_FLAG_AUTOTUNE))
         return fail(nullptr, MK_ERR_ARG, "mk_plan: unknown flag bits");
-    if (d.flags & MK_FLAG_GRAPH)
-        return fail(nullptr, MK_ERR_UNSUPPORTED, "mk_plan: graph replay is not built");
 
     mk_plan_t p = new (std::nothrow) mk_plan_s();
     if (!p) return fail(nullptr, MK_ERR_OOM, "mk_plan: host allocation failed");
@@ -258,8 +400,9 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     if (!(p->d.div_factor > 0.0)) p->d.div_factor = 1e3;
     p->B = d.iw_hi - d.iw_lo + 1;
     p->M = d.nt / 2;
-    p->ns_pad = (d.ns + 3) & ~3;
+    p->ns_pad = (d.ns + 15) & ~15;
     p->stream = reinterpret_cast<hipStream_t>(d.stream);
+    p->tune_mode = (d.flags & MK_FLAG_AUTOTUNE) ? -2 : -1;
 
     auto bail = [&](hipError_t e, const char* where) {
         std::string m = std::string("mk_plan: ") + where + ": " + hipGetErrorString(e);
@@ -269,25 +412,41 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     };
     hipError_t e;
     if ((e = hipGetDevice(&p->device)) != hipSuccess) return bail(e, "hipGetDevice");
+    if ((d.flags & MK_FLAG_GRAPH) && p->stream == nullptr) {
+        // stream capture needs a non-null stream; the graph still runs on the null stream
+        if ((e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+            return bail(e, "capture stream");
+    }
     const size_t nfm = (size_t)d.nf_max;
     const size_t trace = (size_t)d.nr * d.nt;
-    if ((e = dalloc(&p->R, (size_t)p->B * d.nr * p->ns_pad)) != hipSuccess) return bail(e, "R");
+    const size_t relem = d.rprec == MK_R_C64 ? sizeof(float2) : sizeof(uint32_t);
+    const size_t rbytes = (size_t)p->B * d.nr * p->ns_pad * relem;
+    if ((e = hipMalloc(&p->R, rbytes)) != hipSuccess) return bail(e, "R");
+    if ((e = dalloc(&p->rscale, (size_t)p->B)) != hipSuccess) return bail(e, "R scales");
     if ((e = dalloc(&p->X, 3 * nfm * p->B * p->ns_pad)) != hipSuccess) return bail(e, "X");
     if ((e = dalloc(&p->Y, 2 * nfm * p->B * d.nr)) != hipSuccess) return bail(e, "Y");
     if ((e = dalloc(&p->f1p, nfm * trace)) != hipSuccess) return bail(e, "f1+");
     if ((e = dalloc(&p->f1m, nfm * trace)) != hipSuccess) return bail(e, "f1-");
     if ((e = dalloc(&p->gp, nfm * trace)) != hipSuccess) return bail(e, "G+");
     if ((e = dalloc(&p->gm, nfm * trace)) != hipSuccess) return bail(e, "G-");
-    if ((e = dalloc(&p->itd, nfm * d.nr)) != hipSuccess) return bail(e, "itd");
+    if ((e = dalloc(&p->stage, nfm * trace)) != hipSuccess) return bail(e, "staging");
+    if ((e = dalloc(&p->itd, 2 * nfm * d.nr)) != hipSuccess) return bail(e, "itd");
     if ((e = dalloc(&p->fband, nfm * 2)) != hipSuccess) return bail(e, "band");
+    if ((e = dalloc(&p->perm, nfm)) != hipSuccess) return bail(e, "perm");
+    if ((e = dalloc(&p->iperm, nfm)) != hipSuccess) return bail(e, "iperm");
+    if ((e = dalloc(&p->ncols, (size_t)p->B)) != hipSuccess) return bail(e, "ncols");
     if ((e = dalloc(&p->npart, 2 * nfm * d.nr)) != hipSuccess) return bail(e, "norm partials");
     if ((e = dalloc(&p->norm0, nfm)) != hipSuccess) return bail(e, "norm0");
+    if ((e = dalloc(&p->nlast, nfm)) != hipSuccess) return bail(e, "nlast");
+    if ((e = dalloc(&p->xscale, 3 * nfm)) != hipSuccess) return bail(e, "X scales");
     if ((e = dalloc(&p->tw, (size_t)d.nt)) != hipSuccess) return bail(e, "twiddles");
     if ((e = dalloc(&p->flag, 1)) != hipSuccess) return bail(e, "flag");
     // the padding columns of X (s >= ns) must read as zero
     if ((e = hipMemsetAsync(p->X, 0, 3 * nfm * p->B * p->ns_pad * sizeof(float2), p->stream)) !=
         hipSuccess)
         return bail(e, "clear X");
+    if ((e = hipMemsetAsync(p->xscale, 0, 3 * nfm * sizeof(float), p->stream)) != hipSuccess)
+        return bail(e, "clear X scales");
     std::vector<float2> tw(d.nt);
     for (int k = 0; k < d.nt; ++k) {
         const double ang = -2.0 * M_PI * (double)k / (double)d.nt;
@@ -319,7 +478,14 @@ mk_status mk_load_R(mk_plan_t p, const float* R, int on_device) {
     }
     int h = 0;
     hipError_t e = hipMemsetAsync(p->flag, 0, sizeof(int), p->stream);
-    if (e == hipSuccess) e = launch_repack_c64(src, p->R, d.nr, p->B, d.ns, p->ns_pad, p->flag, p->stream);
+    if (e == hipSuccess) {
+        if (d.rprec == MK_R_C64)
+            e = launch_repack_c64(src, reinterpret_cast<float2*>(p->R), d.nr, p->B, d.ns, p->ns_pad,
+                                  p->flag, p->stream);
+        else
+            e = launch_quantize_R(d.rprec, src, p->R, p->rscale, d.nr, p->B, d.ns, p->ns_pad, p->flag,
+                                  p->stream);
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (staging) (void)hipFree(staging);
@@ -343,7 +509,6 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
     if (shift < 0) return fail(p, MK_ERR_ARG, "mk_set_focal: shift must be >= 0");
     if (!p->R_loaded) return fail(p, MK_ERR_STATE, "mk_set_focal: R has not been loaded");
     const size_t ntr = (size_t)nf * d.nr;
-    // band check on the host (device bands are copied back: 2 nf integers)
     std::vector<int32_t> hb;
     if (band) {
         hb.resize(2 * (size_t)nf);
@@ -362,62 +527,166 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
         for (size_t i = 0; i < ntr * d.nt; ++i)
             if (!std::isfinite(Gd[i])) return fail(p, MK_ERR_ARG, "mk_set_focal: Gd holds a non-finite value");
     }
-    // Gd goes to the G+ buffer, which is free until the G assembly
-    mk_status st = copy_in(p, p->gp, Gd, ntr * d.nt, on_device, "mk_set_focal: Gd");
-    if (st != MK_OK) return st;
+    // focal order: by band end, descending (stable), so that the focal points
+    // active at bin w are a prefix of the batch when all bands start at iw_lo
+    std::vector<int> perm(nf);
+    std::iota(perm.begin(), perm.end(), 0);
+    if (band)
+        std::stable_sort(perm.begin(), perm.end(),
+                         [&](int a, int b) { return hb[2 * a + 1] > hb[2 * b + 1]; });
+    std::vector<int> iperm(nf);
+    for (int j = 0; j < nf; ++j) iperm[perm[j]] = j;
+    HIP_TRY(p, hipMemcpyAsync(p->perm, perm.data(), nf * sizeof(int), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(p->iperm, iperm.data(), nf * sizeof(int), hipMemcpyHostToDevice, p->stream));
+    // G_d and itd in sorted order (G_d lands in the G+ buffer, free until the G assembly)
+    MK_TRY(copy_in(p, p->stage, Gd, ntr * d.nt, on_device, "mk_set_focal: Gd"));
     if (on_device) {
         bool ok = true;
-        st = device_all_finite(p, p->gp, (int64_t)(ntr * d.nt), &ok);
-        if (st != MK_OK) return st;
+        MK_TRY(device_all_finite(p, p->stage, (int64_t)(ntr * d.nt), &ok));
         if (!ok) return fail(p, MK_ERR_ARG, "mk_set_focal: Gd holds a non-finite value");
     }
-    st = copy_in(p, p->itd, itd, ntr, on_device, "mk_set_focal: itd");
-    if (st != MK_OK) return st;
+    HIP_TRY(p, launch_gather(p->stage, p->gp, p->perm, nf, (int64_t)d.nr * d.nt, p->stream));
+    int32_t* itd_stage = p->itd + (size_t)d.nf_max * d.nr;
+    MK_TRY(copy_in(p, itd_stage, itd, ntr, on_device, "mk_set_focal: itd"));
+    HIP_TRY(p, launch_gather(reinterpret_cast<const float*>(itd_stage), reinterpret_cast<float*>(p->itd),
+                             p->perm, nf, d.nr, p->stream));
     if (band) {
-        HIP_TRY(p, hipMemcpyAsync(p->fband, hb.data(), hb.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, p->stream));
+        std::vector<int32_t> sb(2 * (size_t)nf);
+        for (int j = 0; j < nf; ++j) {
+            sb[2 * j] = hb[2 * perm[j]];
+            sb[2 * j + 1] = hb[2 * perm[j] + 1];
+        }
+        std::vector<int32_t> nc(p->B, 0);
+        for (int w = 0; w < p->B; ++w) {
+            const int bin = d.iw_lo + w;
+            for (int j = nf - 1; j >= 0; --j)
+                if (sb[2 * j] <= bin && bin <= sb[2 * j + 1]) {
+                    nc[w] = j + 1;
+                    break;
+                }
+        }
+        HIP_TRY(p, hipMemcpyAsync(p->fband, sb.data(), sb.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  p->stream));
+        HIP_TRY(p, hipMemcpyAsync(p->ncols, nc.data(), nc.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  p->stream));
+        HIP_TRY(p, hipStreamSynchronize(p->stream));    // host vectors go out of scope
     }
     p->has_fband = band != nullptr;
+    drop_graphs(p);                    // captured passes depend on nf, bands and choices
+    p->perm_host = perm;
     p->nf = nf;
     p->shift = shift;
     p->passes = 0;
     p->g_valid = false;
+    p->series_choice = choose(p, nf);
+    p->g_choice = choose(p, 2 * nf);
+    // ||N_-1|| = ||G_d|| per focal point (also the scale of the first 16-bit X)
+    HIP_TRY(p, launch_sumsq(p->gp, (int)ntr, d.nt, p->npart, p->stream));
+    HIP_TRY(p, launch_norm_reduce(p->npart, d.nr, nf, p->norm0, p->nlast, p->stream));
     TraceArgs a = trace_args(p, nf);
     a.src = p->gp;
-    st = run_trace(p, TM_INIT, a, 3);
-    if (st != MK_OK) return st;
-    HIP_TRY(p, launch_norm_reduce(p->npart, d.nr, nf, p->norm0, p->stream));
-    p->norm0_host.assign(nf, 0.0);
-    HIP_TRY(p, hipMemcpyAsync(p->norm0_host.data(), p->norm0, nf * sizeof(double),
-                              hipMemcpyDeviceToHost, p->stream));
+    a.xprec = p->series_choice.xprec;
+    a.xs_in = p->norm0;
+    a.xs_out = p->xscale;
+    a.skip_outband = (p->series_choice.variant != 0 && p->has_fband) ? 1 : 0;
+    MK_TRY(run_trace(p, TM_INIT, a, 3));
+    std::vector<double> n0(nf);
+    HIP_TRY(p, hipMemcpyAsync(n0.data(), p->norm0, nf * sizeof(double), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
+    p->norm0_host.assign(nf, 0.0);
+    for (int j = 0; j < nf; ++j) p->norm0_host[perm[j]] = n0[j];
     p->focal_set = true;
     return MK_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Enqueue passes [i0, i0 + n) of one mk_iterate call; `parity0` is the
+// parity of pass i0 in the series.
+mk_status enqueue_passes(mk_plan_t p, int i0, int n, int parity0) {
+    for (int i = i0; i < i0 + n; ++i) {
+        MK_TRY(run_contract(p, p->series_choice, p->X, p->xscale, p->nf, 1, 0));
+        TraceArgs a = trace_args(p, p->nf);
+        a.parity = (parity0 + (i - i0)) & 1;
+        a.xprec = p->series_choice.xprec;
+        a.xs_in = p->nlast;
+        a.xs_out = p->xscale;
+        a.skip_outband = (p->series_choice.variant != 0 && p->has_fband) ? 1 : 0;
+        MK_TRY(run_trace(p, TM_ITER, a, 1));
+        MK_TRY(run_norms(p, p->norms + (size_t)i * p->nf));
+    }
+    return MK_OK;
+}
+
+// Passes [0, n) of one mk_iterate call as one HIP graph, captured on first
+// use and replayed afterwards.  The captured work holds kernel launches only
+// (no memset or copy nodes).
+mk_status replay_passes(mk_plan_t p, int n, int parity0) {
+    const int i0 = 0;
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : p->graphs)
+        if (g.niter == n && g.parity == parity0) exec = g.exec;
+    if (!exec) {
+        hipStream_t cs = p->capture_stream ? p->capture_stream : p->stream;
+        hipStream_t keep = p->stream;
+        p->stream = cs;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) {
+            p->stream = keep;
+            return hip_fail(p, e, "hipStreamBeginCapture");
+        }
+        mk_status st = enqueue_passes(p, i0, n, parity0);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cs, &graph);
+        p->stream = keep;
+        if (st != MK_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(p, e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(p, e, "hipGraphInstantiate");
+        p->graphs.push_back({n, parity0, exec});
+    }
+    hipError_t e = hipGraphLaunch(exec, p->stream);
+    if (e != hipSuccess) return hip_fail(p, e, "hipGraphLaunch");
+    return MK_OK;
+}
+
+bool tune_pending(mk_plan_t p) {
+    if (p->tune_mode != -2) return false;
+    for (auto& kv : p->tuned)
+        if (kv.first == p->nf) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
 
 mk_status mk_iterate(mk_plan_t p, int32_t niter, double* norms) {
     if (!p) return fail(nullptr, MK_ERR_ARG, "mk_iterate: plan is NULL");
     if (niter < 0) return fail(p, MK_ERR_ARG, "mk_iterate: niter must be >= 0");
     if (!p->focal_set) return fail(p, MK_ERR_STATE, "mk_iterate: no focal points set");
     if (niter == 0) return MK_OK;
-    mk_status st = ensure_norm_cap(p, niter);
-    if (st != MK_OK) return st;
+    MK_TRY(ensure_norm_cap(p, niter));
     p->g_valid = false;
-    for (int i = 0; i < niter; ++i) {
-        st = run_contract(p, p->nf);
-        if (st != MK_OK) return st;
-        TraceArgs a = trace_args(p, p->nf);
-        a.parity = p->passes & 1;
-        st = run_trace(p, TM_ITER, a, 1);
-        if (st != MK_OK) return st;
-        st = run_norms(p, p->norms + (size_t)i * p->nf);
-        if (st != MK_OK) return st;
-        p->passes += 1;
-    }
+    // graphs replay passes whose contraction is already chosen: while the
+    // autotuner still has to time this column count, the passes run eagerly
+    const bool graph = (p->d.flags & MK_FLAG_GRAPH) && !(p->d.flags & MK_FLAG_PROFILE) && !tune_pending(p);
+    if (graph) MK_TRY(replay_passes(p, niter, p->passes & 1));
+    else MK_TRY(enqueue_passes(p, 0, niter, p->passes & 1));
+    p->passes += niter;
     if (norms) {
-        HIP_TRY(p, hipMemcpyAsync(norms, p->norms, (size_t)niter * p->nf * sizeof(double),
-                                  hipMemcpyDeviceToHost, p->stream));
+        std::vector<double> h((size_t)niter * p->nf);
+        HIP_TRY(p, hipMemcpyAsync(h.data(), p->norms, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                  p->stream));
         HIP_TRY(p, hipStreamSynchronize(p->stream));
+        for (int i = 0; i < niter; ++i)
+            for (int j = 0; j < p->nf; ++j) norms[(size_t)i * p->nf + p->perm_host[j]] = h[(size_t)i * p->nf + j];
         for (int i = 0; i < niter; ++i)
             for (int f = 0; f < p->nf; ++f) {
                 const double v = norms[(size_t)i * p->nf + f];
@@ -445,12 +714,12 @@ mk_status mk_get(mk_plan_t p, int32_t field, float* out, int on_device) {
         case MK_GPLUS: src = p->gp; break;
         case MK_GMINUS: src = p->gm; break;
     }
-    if ((field == MK_GPLUS || field == MK_GMINUS) && !p->g_valid) {
-        mk_status st = assemble_G(p);
-        if (st != MK_OK) return st;
-    }
-    const size_t n = (size_t)p->nf * p->d.nr * p->d.nt;
-    HIP_TRY(p, hipMemcpyAsync(out, src, n * sizeof(float),
+    if ((field == MK_GPLUS || field == MK_GMINUS) && !p->g_valid) MK_TRY(assemble_G(p));
+    const size_t per = (size_t)p->d.nr * p->d.nt;
+    const size_t n = (size_t)p->nf * per;
+    // back to the caller's focal order
+    HIP_TRY(p, launch_gather(src, p->stage, p->iperm, p->nf, (int64_t)per, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(out, p->stage, n * sizeof(float),
                               on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream));
     if (!on_device) HIP_TRY(p, hipStreamSynchronize(p->stream));
     return MK_OK;
@@ -459,6 +728,30 @@ mk_status mk_get(mk_plan_t p, int32_t field, float* out, int on_device) {
 mk_status mk_passes(mk_plan_t p, int32_t* passes) {
     if (!p || !passes) return fail(p, MK_ERR_ARG, "mk_passes: NULL argument");
     *passes = p->passes;
+    return MK_OK;
+}
+
+mk_status mk_tune(mk_plan_t p, int32_t mode) {
+    if (!p) return fail(nullptr, MK_ERR_ARG, "mk_tune: plan is NULL");
+    if (mode < -2 || mode > contract_mfma_variants())
+        return fail(p, MK_ERR_ARG, "mk_tune: mode outside [-2, number of variants]");
+    p->tune_mode = mode;
+    p->tuned.clear();
+    drop_graphs(p);
+    // the X storage is fixed when the focal points are set: the caller sets them again
+    p->focal_set = false;
+    p->g_valid = false;
+    return MK_OK;
+}
+
+mk_status mk_contract_variant(mk_plan_t p, int32_t ncols, int32_t* variant) {
+    if (!p || !variant || ncols < 1) return fail(p, MK_ERR_ARG, "mk_contract_variant: bad argument");
+    for (auto& kv : p->tuned)
+        if (kv.first == ncols) {
+            *variant = kv.second;
+            return MK_OK;
+        }
+    *variant = choose(p, ncols).variant;
     return MK_OK;
 }
 

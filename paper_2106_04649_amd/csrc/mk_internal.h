@@ -13,9 +13,12 @@
 enum TraceMode : int {
     TM_INIT = 0,   // N_-1 = Gd(-t); f1+ = N_-1; f1- = 0; X = rfft(N_-1)
     TM_ITER = 1,   // RN = irfft(Y); N = mute(-RN(-t)); accumulate; X = rfft(N)
-    TM_GFWD = 2,   // X[f] = rfft(f1+[f]); X[nf + f] = rfft(f1-[f](-t))
-    TM_GOUT = 3    // G- = irfft(Y[f]) - f1-;  G+ = f1+(-t) - irfft(Y[nf + f])
+    TM_GFWD = 2,   // X[2f] = rfft(f1+[f]); X[2f+1] = rfft(f1-[f](-t))
+    TM_GOUT = 3    // G- = irfft(Y[2f]) - f1-;  G+ = f1+(-t) - irfft(Y[2f+1])
 };
+
+// Storage of the contraction input X.
+enum XPrec : int { XP_F32 = 0, XP_F16 = 1, XP_BF16 = 2 };
 
 // Arguments of the per-trace kernel.  Layouts (all row-major):
 //   Y   [nfo][B][nr]        complex, contraction output (unscaled sum over s)
@@ -26,7 +29,7 @@ enum TraceMode : int {
 //   tw  [nt] complex: exp(-2 pi i k / nt)
 struct TraceArgs {
     const float2* Y;
-    float2* X;
+    void* X;           // float2 (XP_F32) or 16-bit pairs (XP_F16 / XP_BF16)
     const float* src;
     float* f1p;
     float* f1m;
@@ -36,6 +39,10 @@ struct TraceArgs {
     const int32_t* fband;
     double* npart;
     const float2* tw;
+    const double* xs_in;   // [nf] norm setting the scale of 16-bit X (per focal point)
+    float* xs_out;         // [nfo] scale written next to 16-bit X (X = xs_out * stored)
+    int xprec;             // XPrec
+    int skip_outband;      // X above the focal band end is never read: do not write it
     int nr;
     int nf;        // focal points of the series
     int nfo;       // traces are nfo x nr (nf, or 2 nf for the G modes)
@@ -52,26 +59,39 @@ struct ProfileSlot {
     int64_t launches = 0;
 };
 
+// One contraction choice: the GEMV (variant 0) or an MFMA tile shape (1 + v).
+struct ContractChoice {
+    int variant = 0;
+    int xprec = XP_F32;   // storage of X this choice consumes
+};
+
 struct mk_plan_s {
     mk_plan_desc d{};
     int B = 0;          // stored bins
     int M = 0;          // nt / 2
-    int ns_pad = 0;     // padded row length of R and X (complex elements, multiple of 4)
+    int ns_pad = 0;     // padded row length of R and X (complex elements, multiple of 16)
     int device = 0;
     hipStream_t stream = nullptr;
 
     // device memory (plan-owned)
-    float2* R = nullptr;       // [B][nr][ns_pad] complex64
+    void* R = nullptr;         // [B][nr][ns_pad] complex64 or 16-bit pairs
+    float* rscale = nullptr;   // [B] per-frequency scale of 16-bit R
     float2* X = nullptr;       // [3 nf_max][B][ns_pad]: series slabs, then G-assembly slabs
     float2* Y = nullptr;       // [2 nf_max][B][nr]
-    float* f1p = nullptr;      // [nf_max][nr][nt]
+    float* f1p = nullptr;      // [nf_max][nr][nt]  (focal points in the plan's sorted order)
     float* f1m = nullptr;
     float* gp = nullptr;
     float* gm = nullptr;
+    float* stage = nullptr;    // [nf_max][nr][nt] staging for permuted inputs and outputs
     int32_t* itd = nullptr;    // [nf_max][nr]
     int32_t* fband = nullptr;  // [nf_max][2]
+    int32_t* perm = nullptr;   // [nf_max] sorted position -> caller's focal index
+    int32_t* iperm = nullptr;  // [nf_max] caller's focal index -> sorted position
+    int32_t* ncols = nullptr;  // [B] active focal count per bin (sorted order)
     double* npart = nullptr;   // [2 nf_max][nr]
     double* norm0 = nullptr;   // [nf_max]
+    double* nlast = nullptr;   // [nf_max] norm of the last N (scales 16-bit X)
+    float* xscale = nullptr;   // [3 nf_max] scale stored with 16-bit X
     double* norms = nullptr;   // [norm_cap][nf_max]
     int norm_cap = 0;
     float2* tw = nullptr;      // [nt]
@@ -86,6 +106,21 @@ struct mk_plan_s {
     bool focal_set = false;
     bool g_valid = false;
     std::vector<double> norm0_host;
+    std::vector<int> perm_host;
+    ContractChoice series_choice, g_choice;
+
+    // graph replay (MK_FLAG_GRAPH): one executable per (passes, start parity)
+    struct GraphEntry {
+        int niter;
+        int parity;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t capture_stream = nullptr;   // private stream used when the plan stream is NULL
+
+    // contraction selection: -1 heuristic, -2 autotune, >= 0 forced variant
+    int tune_mode = -1;
+    std::vector<std::pair<int, int>> tuned;   // (ncols, variant) chosen by the autotuner
 
     // profiling (MK_FLAG_PROFILE)
     struct Pending {
@@ -99,11 +134,35 @@ struct mk_plan_s {
     std::string err;
 };
 
+// Arguments of the contraction kernels (GEMV and MFMA).
+//   R  [B][nr][ns_pad] complex64 or 16-bit pairs, rscale [B] (16-bit only)
+//   X  [ncols][B][ns_pad] complex64 (GEMV, MFMA-f32) or 16-bit pairs (MFMA-16)
+//   xscale [ncols] (MFMA-16 only), Y [ncols][B][nr] complex64
+//   ncols_w [B]: active columns per bin (times ncols_mul), or null for all
+struct ContractArgs {
+    const void* R;
+    const float* rscale;
+    int prec;              // mk_rprec of R
+    const void* X;
+    const float* xscale;
+    float2* Y;
+    const int* ncols_w;
+    int ncols_mul;
+    int nr, ns, ns_pad, B, ncols;
+};
+
 // kernel launchers (return hipSuccess or the launch error)
 hipError_t launch_trace(int mode, int nt, const TraceArgs& a, hipStream_t s);
-hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out, hipStream_t s);
-hipError_t launch_contract_c64(const float2* R, const float2* X, float2* Y, int nr, int B,
-                               int ns, int ns_pad, int ncols, hipStream_t s);
+hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out, double* out2,
+                              hipStream_t s);
+hipError_t launch_sumsq(const float* x, int ntr, int nt, double* npart, hipStream_t s);
+hipError_t launch_gather(const float* src, float* dst, const int* perm, int nf, int64_t per,
+                         hipStream_t s);
+hipError_t launch_contract_gemv(const ContractArgs& c, hipStream_t s);
+hipError_t launch_contract_mfma(const ContractArgs& c, int variant, hipStream_t s);
+int contract_mfma_variants();
 hipError_t launch_repack_c64(const float* Rin, float2* Rout, int nr, int B, int ns, int ns_pad,
                              int* flag, hipStream_t s);
+hipError_t launch_quantize_R(int prec, const float* Rin, void* Rout, float* rscale, int nr, int B,
+                             int ns, int ns_pad, int* flag, hipStream_t s);
 hipError_t launch_check_finite(const float* x, int64_t n, int* flag, hipStream_t s);

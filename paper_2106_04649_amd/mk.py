@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libmk.so")
 MK_OK, MK_ERR_ARG, MK_ERR_STATE, MK_ERR_OOM, MK_ERR_HIP, MK_ERR_UNSUPPORTED, MK_ERR_DIVERGED = range(7)
 MK_R_C64, MK_R_F16S, MK_R_BF16S = 0, 1, 2
 MK_F1PLUS, MK_F1MINUS, MK_GPLUS, MK_GMINUS = 0, 1, 2, 3
-MK_FLAG_GRAPH, MK_FLAG_PROFILE = 0x1, 0x2
+MK_FLAG_GRAPH, MK_FLAG_PROFILE, MK_FLAG_AUTOTUNE = 0x1, 0x2, 0x4
 FIELDS = {"f1plus": MK_F1PLUS, "f1minus": MK_F1MINUS, "Gplus": MK_GPLUS, "Gminus": MK_GMINUS}
 KERNEL_KINDS = {"contract": 0, "epilogue": 1, "norms": 2, "init": 3, "gassembly": 4}
 
@@ -71,6 +71,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mk_iterate": (i32, [P, i32, P]),
         "mk_get": (i32, [P, i32, P, ctypes.c_int]),
         "mk_passes": (i32, [P, ctypes.POINTER(i32)]),
+        "mk_tune": (i32, [P, i32]),
+        "mk_contract_variant": (i32, [P, i32, ctypes.POINTER(i32)]),
         "mk_profile": (i32, [P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                              ctypes.c_int]),
         "mk_destroy": (i32, [P]),
@@ -212,6 +214,17 @@ def mk_get(plan: Plan, field, out=None):
 def mk_passes(plan: Plan) -> int:
     v = ctypes.c_int32()
     _check(load_library().mk_passes(plan.handle, ctypes.byref(v)), plan.handle)
+    return v.value
+
+
+def mk_tune(plan: Plan, mode: int) -> None:
+    """-1 heuristic, -2 autotune, 0 GEMV, v >= 1 MFMA tile shape v - 1."""
+    _check(load_library().mk_tune(plan.handle, int(mode)), plan.handle)
+
+
+def mk_contract_variant(plan: Plan, ncols: int) -> int:
+    v = ctypes.c_int32()
+    _check(load_library().mk_contract_variant(plan.handle, int(ncols), ctypes.byref(v)), plan.handle)
     return v.value
 
 

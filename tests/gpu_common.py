@@ -28,7 +28,7 @@ def say(msg):
 
 
 def run_gpu(p, niter=None, fbands=None, R=None, flags=0, nf_max=None, on_device=False,
-            chunks=None):
+            chunks=None, rprec=0, tune=None):
     """Full solve through the C ABI; returns dict of numpy fields + norms."""
     import torch
 
@@ -36,14 +36,18 @@ def run_gpu(p, niter=None, fbands=None, R=None, flags=0, nf_max=None, on_device=
     niter = p.niter if niter is None else niter
     nr, nt = p.Rhat.shape[0], p.geom.nt
     plan = mk.mk_plan(nr, nr, nt, p.geom.dt, p.geom.dx, band=p.band, nf_max=nf_max or p.nf,
-                      flags=flags)
+                      flags=flags, rprec=rprec)
     Rin = p.Rhat if R is None else R
     if on_device:
         mk.mk_load_R(plan, torch.from_numpy(np.ascontiguousarray(Rin)).cuda())
+    else:
+        mk.mk_load_R(plan, Rin)
+    if tune is not None:
+        mk.mk_tune(plan, tune)
+    if on_device:
         mk.mk_set_focal(plan, torch.from_numpy(p.Gd).cuda(), torch.from_numpy(p.itd).cuda(), p.shift,
                         None if fbands is None else torch.from_numpy(fbands).cuda())
     else:
-        mk.mk_load_R(plan, Rin)
         mk.mk_set_focal(plan, p.Gd, p.itd, p.shift, fbands)
     norms = []
     for n in (chunks or [niter]):
@@ -58,6 +62,7 @@ def run_gpu(p, niter=None, fbands=None, R=None, flags=0, nf_max=None, on_device=
         out[name] = buf
     out["norms"] = np.concatenate(norms) if norms else np.zeros((0, p.nf))
     out["passes"] = mk.mk_passes(plan)
+    out["variant"] = mk.mk_contract_variant(plan, p.nf)
     mk.mk_destroy(plan)
     return out
 

@@ -1,0 +1,78 @@
+"""Batched focal points on the matrix cores, reduced-precision R, per-focal
+bands and the contraction autotuner, each against the FP64 oracle.
+
+Bars: 1e-5 relative L2 for complex64 R (every contraction variant the
+autotuner may pick), 1e-3 for FP16 R, 1e-2 for BF16 R.  BF16's unit
+roundoff is 3.9e-3, and G- nearly cancels (it is S f1+ - f1- of two much
+larger fields), so its relative error reaches a few 1e-3; the measured
+errors are printed.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_common import TOL_FP32, assert_parity, require_gpu, run_gpu, run_oracle, say
+from mkgen.layered import make_config, small_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: TOL_FP32, 1: 1e-3, 2: 1e-2}
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("n,nt,nf", [(70, 64, 6), (37, 128, 40)])
+def test_every_contraction_variant_fp32(variant, n, nt, nf):
+    say(f"variant {variant} n={n} nt={nt} nf={nf}")
+    p = small_problem(seed=20 + nf, n=n, nt=nt, nf=nf, niter=6)
+    g = run_gpu(p, tune=variant)
+    assert g["variant"] == variant
+    assert_parity(g, run_oracle(p), label=f"v{variant}")
+
+
+@pytest.mark.parametrize("rprec", [1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 4])
+def test_reduced_precision_R(rprec, variant):
+    say(f"rprec {rprec} variant {variant}")
+    p = small_problem(seed=31, n=48, nt=128, nf=20, niter=8)
+    g = run_gpu(p, rprec=rprec, tune=variant)
+    assert_parity(g, run_oracle(p), tol=TOL[rprec], label=f"prec{rprec}-v{variant}")
+
+
+@pytest.mark.parametrize("rprec,variant", [(0, 1), (0, 0), (1, 1), (2, 5)])
+def test_per_focal_bands_batched(rprec, variant):
+    say(f"bands rprec {rprec} variant {variant}")
+    p = small_problem(seed=41, n=50, nt=128, nf=24, niter=6)
+    rng = np.random.default_rng(3)
+    hi = rng.integers(10, 65, size=p.nf)
+    lo = np.where(rng.random(p.nf) < 0.3, rng.integers(0, 8, size=p.nf), 0)
+    fb = np.stack([lo, hi], axis=1).astype(np.int32)
+    g = run_gpu(p, fbands=fb, rprec=rprec, tune=variant)
+    assert_parity(g, run_oracle(p, fbands=fb), tol=TOL[rprec], label=f"bands{rprec}-{variant}")
+
+
+def test_autotuner_choice_passes_parity(tmp_path, monkeypatch):
+    mk = require_gpu()
+    say("autotune")
+    monkeypatch.setenv("MK_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    p = small_problem(seed=51, n=64, nt=128, nf=12, niter=5)
+    g = run_gpu(p, flags=mk.MK_FLAG_AUTOTUNE)
+    assert 0 <= g["variant"] <= 5
+    assert_parity(g, run_oracle(p), label="autotune")
+    text = (tmp_path / "tune.txt").read_text()
+    assert "ncols=12" in text and "ncols=24" in text
+    g2 = run_gpu(p, flags=mk.MK_FLAG_AUTOTUNE)        # choices now come from the cache file
+    assert g2["variant"] == g["variant"]
+    for k in ("f1plus", "Gplus"):
+        assert np.array_equal(g[k], g2[k])
+
+
+def test_medium_focal_line_batched():
+    """601 x 601, nt 2048, 64 focal points: FP32 and FP16 batched, first 2 passes."""
+    say("medium nf=64 batched")
+    p = make_config("medium", nf=64)
+    r = run_oracle(p, niter=2)
+    g = run_gpu(p, niter=2)
+    assert g["variant"] != 0
+    assert_parity(g, r, label="medium64-fp32")
+    g16 = run_gpu(p, niter=2, rprec=1)
+    assert_parity(g16, r, tol=1e-3, label="medium64-fp16")
