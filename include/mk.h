@@ -201,6 +201,93 @@ mk_status mk_passes(mk_plan_t plan, int32_t* passes);
 mk_status mk_profile(mk_plan_t plan, int32_t kind, double* total_ms, int64_t* launches,
                      int reset);
 
+/*
+ * Series-tail network (learned extension of the Neumann series; not in the
+ * paper).  A fixed 3-layer dilated 1D convolution maps the first k iterates
+ * N_0 .. N_{k-1} of one trace (k channels over a window of T samples centred
+ * on t = 0, normalised per trace) to two channels: the even-pass and the
+ * odd-pass sums of the remaining terms of the series.
+ *   conv(k -> 64, 5 taps, dilation 1), ReLU, conv(64 -> 64, 5, dilation 4),
+ *   ReLU, conv(64 -> 2, 5, dilation 16); zero padding outside the window.
+ * Parameters: one FP32 vector, W1 [64][k][5], b1 [64], W2 [64][64][5],
+ * b2 [64], W3 [2][64][5], b3 [2].  The forward pass is meant to run on
+ * BF16-rounded parameters (mk_net_round / the wq output of mk_net_adam).
+ * Every pointer below is device memory owned by the caller; work is
+ * enqueued on `stream` (hipStream_t, NULL = null stream) and not
+ * synchronised.  Errors: MK_ERR_ARG (NULL, bad sizes), MK_ERR_HIP; the
+ * message is in mk_net_last_error().
+ */
+int32_t mk_net_param_count(int32_t k);   /* -1 when k is outside [1, 16] */
+const char* mk_net_last_error(void);
+
+/* Forward pass: x [N][k][T] -> y [N][2][T]; work [2][N][64][T] keeps the
+ * hidden activations for mk_net_backward. */
+mk_status mk_net_forward(const float* params, const float* x, int32_t N, int32_t k, int32_t T,
+                         float* work, float* y, void* stream);
+
+/* Gradient of sum(gy * y) with respect to every parameter -> grads (same
+ * layout as params); work as left by mk_net_forward; work2 holds
+ * 2 N 64 T + 64 * 64 * 5 floats of scratch. */
+mk_status mk_net_backward(const float* params, const float* x, const float* work, const float* gy,
+                          int32_t N, int32_t k, int32_t T, float* grads, float* work2, void* stream);
+
+/* Masked mean squared error over both output channels: loss (one double)
+ * = sum(((y - target) mask)^2) / count, gy = 2 (y - target) mask / count;
+ * mask [N][T]; part holds nparts doubles of scratch (fixed-order sum). */
+mk_status mk_net_loss(const float* y, const float* target, const float* mask, int32_t N, int32_t T,
+                      float count, float* gy, double* loss, double* part, int32_t nparts, void* stream);
+
+/* One Adam step (Kingma and Ba) with bias correction on FP32 master weights
+ * w with moments m, v; writes the BF16-rounded weights to wq. */
+mk_status mk_net_adam(float* w, float* wq, const float* g, float* m, float* v, int32_t n, int32_t step,
+                      float lr, float b1, float b2, float eps, void* stream);
+
+/* wq = BF16 rounding (nearest, ties to even) of w. */
+mk_status mk_net_round(const float* w, float* wq, int32_t n, void* stream);
+
+/*
+ * mk_tail_record -- record the first k iterates N_0 .. N_{k-1} of each new
+ * series (after mk_set_focal) on the window of T samples centred on t = 0
+ * (sample u holds t = u - T/2).  Needed by mk_tail_apply and for building
+ * the tail network's training set.  Errors: MK_ERR_ARG (k outside [1, 16],
+ * T odd or above nt), MK_ERR_OOM, MK_ERR_HIP.
+ */
+mk_status mk_tail_record(mk_plan_t plan, int32_t k, int32_t T);
+
+/*
+ * mk_tail_load -- load the tail network's parameters (host FP32, layout of
+ * mk_net_param_count(k) for the recorded k); they are rounded to BF16.
+ * Errors: MK_ERR_ARG (NULL, wrong count, non-finite), MK_ERR_STATE (no
+ * mk_tail_record), MK_ERR_OOM, MK_ERR_HIP.
+ */
+mk_status mk_tail_load(mk_plan_t plan, const float* params, int32_t count);
+
+/*
+ * mk_tail_history -- copy the recorded iterates, float [nf][nr][k][T] in
+ * the caller's focal order.  Errors: MK_ERR_ARG, MK_ERR_STATE (nothing
+ * recorded), MK_ERR_HIP.
+ */
+mk_status mk_tail_history(mk_plan_t plan, float* out, int on_device);
+
+/*
+ * mk_tail_apply -- after exactly k passes of a fresh series: add an estimate
+ * of the rest of the series, T_even = sum_{i>=k even} N_i and
+ * T_odd = sum_{i>=k odd} N_i, inside the mute window (f1- -= T_even(-t),
+ * f1+ += T_odd, the rule of Algorithm 1 loop 2), then judge it with plain
+ * synthesis: one fixed-point step f1- <- theta S f1+, f1+ <- G_d(-t) +
+ * A^2 f1+ (A = theta Rev S; two syntheses, counted as two passes), whose
+ * residual rho starts a new series carrying the remaining error; later
+ * mk_iterate calls continue that series.  mode 0: the loaded network
+ * (inputs normalised by the RMS of N_0 per trace); 1: geometric
+ * extrapolation of the last two iterates of each parity (needs an even
+ * k >= 4); 2: no estimate (exactly two more passes of the plain series).
+ * rel_resid: host double [nf] receiving ||rho|| / ||G_d|| per focal point
+ * (the judge's verdict), or NULL.  Synchronises.
+ * Errors: MK_ERR_ARG (mode), MK_ERR_STATE (not exactly k recorded passes
+ * since mk_set_focal, already applied, no network for mode 0), MK_ERR_HIP.
+ */
+mk_status mk_tail_apply(mk_plan_t plan, int32_t mode, double* rel_resid);
+
 /* mk_destroy -- free the plan and its device memory (NULL is a no-op). */
 mk_status mk_destroy(mk_plan_t plan);
 

@@ -386,6 +386,23 @@ def make_config(name: str, nf: int = 1, n: Optional[int] = None, nt: Optional[in
                         rho_target=rho_target, fbands=fbands, threads=threads)
 
 
+def tail_problem(seed: int, rho_target: Optional[float] = 0.7, threads: Optional[int] = None,
+                 n: int = 301, nt: int = 1024) -> Problem:
+    """One model of the series-tail workload: 301 x 301 at 10 m, nt 1024 at 4 ms,
+    4-12 flat layers at 100-1400 m, half of the models with 1-2 dipping
+    reflectors, one focal point at a seeded position below the third interface."""
+    rng = np.random.default_rng(seed)
+    geom = Geometry(n=n, dx=10.0 * 300 / max(1, n - 1), nt=nt, dt=0.004 * 1024 / nt)
+    L = (geom.n - 1) * geom.dx
+    nl = int(rng.integers(4, 13))
+    ndips = int(rng.integers(1, 3)) if rng.random() < 0.5 else 0
+    model = random_layer_model(rng, nl, (100.0, 1400.0), ndips=ndips, xrange=(0.3 * L, 0.7 * L))
+    zf = float(rng.uniform(max(300.0, model.z[min(2, nl - 1)] + 20.0), 1500.0))
+    xf = float(rng.uniform(0.3 * L, 0.7 * L))
+    return make_problem(f"tail{seed}", geom, model, [xf], [zf], 32, rho_target=rho_target,
+                        threads=threads)
+
+
 def small_problem(n: int = 8, nt: int = 64, nf: int = 1, seed: int = 0,
                   rho_target: Optional[float] = 0.5, nlayers: int = 3,
                   band: Optional[Tuple[int, int]] = None, ndips: int = 1,

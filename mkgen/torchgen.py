@@ -1,0 +1,93 @@
+"""GPU (torch) evaluation of the layered-earth reflection response.
+
+Same formulas as ``mkgen.layered.reflection_response`` (flat layers through
+an offset table, dipping planes through image sources, zero-phase Ricker),
+evaluated on the GPU so that the tail network's training set (hundreds of
+models) can be built in seconds.  Values agree with the numpy version to
+float32 rounding, not bit for bit; inputs that the FP64 oracle checks are
+always built with the numpy version.  Holds none of the Marchenko method's
+arithmetic.
+"""
+
+from __future__ import annotations
+
+import math
+from typing import Optional, Tuple
+
+import numpy as np
+
+from .layered import (Geometry, LayerModel, Problem, _dip_tables, _flat_offset_table, direct_arrivals,
+                      random_layer_model, ricker_spectrum)
+
+
+def reflection_response_gpu(geom: Geometry, model: LayerModel, band: Tuple[int, int], device="cuda"):
+    import torch
+
+    lo, hi = band
+    w = np.arange(lo, hi + 1)
+    freqs = w / (geom.nt * geom.dt)
+    tmax = 0.45 * geom.nt * geom.dt
+    wav = ricker_spectrum(freqs, geom.fpeak) / geom.dt
+    flat = _flat_offset_table(geom, model, freqs, tmax) * wav[None, :]            # [h][B] complex128
+    n = geom.n
+    idx = torch.arange(n, device=device)
+    absd = (idx[:, None] - idx[None, :]).abs()                                      # [r][s]
+    tab = torch.from_numpy(flat.astype(np.complex64)).to(device)                    # [h][B]
+    R = tab[absd].permute(0, 2, 1).contiguous()                                     # [r][B][s]
+    f_t = torch.from_numpy(freqs).to(device=device, dtype=torch.float64)
+    wav_t = torch.from_numpy(wav).to(device=device, dtype=torch.float32)
+    for tau, amp in _dip_tables(geom, model, tmax):
+        tau_t = torch.from_numpy(tau).to(device)                                   # [r][s] float64
+        amp_t = torch.from_numpy(amp).to(device=device, dtype=torch.float32)
+        for r0 in range(0, n, 64):
+            r1 = min(n, r0 + 64)
+            ph = torch.remainder(2.0 * math.pi * f_t[None, :, None] * tau_t[r0:r1, None, :], 2.0 * math.pi)
+            ph = ph.to(torch.float32)
+            mag = wav_t[None, :, None] * amp_t[r0:r1, None, :]
+            R[r0:r1] += torch.complex(mag * torch.cos(ph), -mag * torch.sin(ph))
+    if lo == 0:
+        R[:, 0, :] = R[:, 0, :].real.to(torch.complex64)
+    if hi == geom.nt // 2:
+        R[:, -1, :] = R[:, -1, :].real.to(torch.complex64)
+    return R
+
+
+def sigma_max_gpu(R, iters: int = 30, seed: int = 7) -> float:
+    """max over frequencies of the largest singular value (batched power iteration)."""
+    import torch
+
+    A = R.permute(1, 0, 2).contiguous()                                             # [B][r][s]
+    g = torch.Generator(device=R.device).manual_seed(seed)
+    v = torch.randn(A.shape[0], A.shape[2], 1, device=R.device, generator=g, dtype=torch.float32)
+    v = torch.complex(v, torch.zeros_like(v))
+    v = v / torch.linalg.vector_norm(v, dim=1, keepdim=True)
+    AH = A.conj().transpose(1, 2).contiguous()
+    s = None
+    for _ in range(iters):
+        u = torch.bmm(A, v)
+        v = torch.bmm(AH, u)
+        nv = torch.linalg.vector_norm(v, dim=1, keepdim=True)
+        s = torch.sqrt(nv.squeeze())
+        v = v / torch.clamp(nv, min=1e-30)
+    return float(s.max().item())
+
+
+def tail_problem_gpu(seed: int, rho_target: float = 0.7, n: int = 301, nt: int = 1024, device="cuda") -> Problem:
+    """``layered.tail_problem`` with R built on the GPU (Rhat is a CUDA complex64 tensor)."""
+    rng = np.random.default_rng(seed)
+    geom = Geometry(n=n, dx=10.0 * 300 / max(1, n - 1), nt=nt, dt=0.004 * 1024 / nt)
+    L = (geom.n - 1) * geom.dx
+    nl = int(rng.integers(4, 13))
+    ndips = int(rng.integers(1, 3)) if rng.random() < 0.5 else 0
+    model = random_layer_model(rng, nl, (100.0, 1400.0), ndips=ndips, xrange=(0.3 * L, 0.7 * L))
+    zf = float(rng.uniform(max(300.0, model.z[min(2, nl - 1)] + 20.0), 1500.0))
+    xf = float(rng.uniform(0.3 * L, 0.7 * L))
+    band = (0, nt // 2)
+    R = reflection_response_gpu(geom, model, band, device)
+    rho = geom.c * sigma_max_gpu(R)
+    scale = rho_target / rho if rho > 0 else 1.0
+    R *= scale
+    Gd, itd = direct_arrivals(geom, model, np.array([xf]), np.array([zf]))
+    shift = int(math.ceil(1.0 / (geom.fpeak * geom.dt)))
+    return Problem(name=f"tail{seed}", geom=geom, model=model, Rhat=R, band=band, Gd=Gd, itd=itd, shift=shift,
+                   niter=32, xf=np.array([xf]), zf=np.array([zf]), rho=rho_target, rscale=scale)

@@ -20,7 +20,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmk.so")
-SOURCES = ["k_contract.hip", "k_mfma.hip", "k_quant.hip", "k_trace.hip", "mk_api.hip"]
+SOURCES = ["k_contract.hip", "k_mfma.hip", "k_quant.hip", "k_trace.hip", "k_net.hip", "k_tail.hip", "mk_api.hip",
+           "mk_net_api.hip"]
 ARCH = "gfx950"
 
 

@@ -1,0 +1,102 @@
+// Series-tail application: the recorded first k iterates of each trace ->
+// an estimate of the remaining even-pass and odd-pass sums, added to f1- and
+// f1+ inside the mute window.  One wave per trace.
+//
+// Window convention: recorded sample u of a trace holds time t = u - T/2
+// (periodic index t mod nt).  T_even feeds f1- -= T_even(-t) (even passes),
+// T_odd feeds f1+ += T_odd (odd passes), as in the series itself.
+#include "mk_internal.h"
+
+namespace {
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// x[tr][c][u] = hist[tr][c][u] / s_tr with s_tr the RMS of the first iterate
+// over the window (0 for a silent trace, which the network then skips).
+__global__ __launch_bounds__(256) void k_tail_prep(const float* __restrict__ hist, int ntr, int k, int T,
+                                                   float* __restrict__ x, float* __restrict__ scale) {
+    const int lane = threadIdx.x & 63;
+    const int tr = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tr >= ntr) return;
+    const float* h = hist + (size_t)tr * k * T;
+    float ss = 0.f;
+    for (int u = lane; u < T; u += 64) ss += h[u] * h[u];
+    ss = wave_sum_f(ss);
+    const float s = sqrtf(ss / (float)T);
+    const float inv = s > 1e-30f ? 1.f / s : 0.f;
+    float* xo = x + (size_t)tr * k * T;
+    for (int i = lane; i < k * T; i += 64) xo[i] = h[i] * inv;
+    if (lane == 0) scale[tr] = inv > 0.f ? s : 0.f;
+}
+
+// mode 0: tails from the network output y[tr][2][T] (channel 0 even, 1 odd)
+// mode 1: geometric extrapolation of the last two iterates of each parity
+__global__ __launch_bounds__(256) void k_tail_apply(const float* __restrict__ hist, const float* __restrict__ y,
+                                                    const float* __restrict__ scale, const int32_t* __restrict__ itd,
+                                                    int shift, int ntr, int k, int T, int nt, int mode,
+                                                    float* __restrict__ f1p, float* __restrict__ f1m) {
+    const int lane = threadIdx.x & 63;
+    const int tr = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tr >= ntr) return;
+    const float* h = hist + (size_t)tr * k * T;
+    const int L = itd[tr] - shift;
+    const int hT = T >> 1;
+    float ge = 0.f, go = 0.f, se = 0.f;
+    if (mode == 1) {
+        // ratio of the norms of the last two iterates of each parity
+        float n[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int u = lane; u < T; u += 64)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float v = h[(size_t)(k - 4 + c) * T + u];
+                n[c] += v * v;
+            }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) n[c] = sqrtf(wave_sum_f(n[c]));
+        // k even: channels k-4, k-2 are even passes; k-3, k-1 odd passes
+        const float qe = n[0] > 0.f ? fminf(n[2] / n[0], 0.9f) : 0.f;
+        const float qo = n[1] > 0.f ? fminf(n[3] / n[1], 0.9f) : 0.f;
+        ge = qe / (1.f - qe);
+        go = qo / (1.f - qo);
+    } else {
+        se = scale[tr];
+    }
+    float* fp = f1p + (size_t)tr * nt;
+    float* fm = f1m + (size_t)tr * nt;
+    for (int u = lane; u < T; u += 64) {
+        const int t = u - hT;
+        if (!(t < L && -t < L) || t == nt / 2 || -t == nt / 2) continue;
+        float te, to;
+        if (mode == 1) {
+            te = ge * h[(size_t)(k - 2) * T + u];
+            to = go * h[(size_t)(k - 1) * T + u];
+        } else {
+            te = se * y[((size_t)tr * 2 + 0) * T + u];
+            to = se * y[((size_t)tr * 2 + 1) * T + u];
+        }
+        const int ip = ((t % nt) + nt) % nt;
+        const int im = ((-t % nt) + nt) % nt;
+        fp[ip] += to;                         // odd passes feed f1+
+        fm[im] -= te;                         // even passes feed f1- -= N(-t)
+    }
+}
+
+}  // namespace
+
+hipError_t launch_tail_prep(const float* hist, int ntr, int k, int T, float* x, float* scale, hipStream_t s) {
+    if (ntr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tail_prep, dim3((ntr + 3) / 4), dim3(256), 0, s, hist, ntr, k, T, x, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_apply(const float* hist, const float* y, const float* scale, const int32_t* itd, int shift,
+                             int ntr, int k, int T, int nt, int mode, float* f1p, float* f1m, hipStream_t s) {
+    if (ntr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tail_apply, dim3((ntr + 3) / 4), dim3(256), 0, s, hist, y, scale, itd, shift, ntr, k, T,
+                       nt, mode, f1p, f1m);
+    return hipGetLastError();
+}

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     const float s = a.scale;
 
     // ---- spectrum -> time (TM_ITER, TM_GOUT) --------------------------------
-    if (MODE == TM_ITER || MODE == TM_GOUT) {
+    if (MODE == TM_ITER || MODE == TM_GOUT || MODE == TM_RST1 || MODE == TM_RST2) {
         const float2* Yt = a.Y + (size_t)fo * a.B * a.nr + r;
         for (int k = lane; k < M; k += TPT) {
             const int km = M - k;
@@ -189,9 +189,13 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     double nacc = 0.0;
     float2 out[PM];
 
-    if (MODE == TM_ITER) {
+    if (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2) {
         const int L = a.itd[f * a.nr + r] - a.shift;        // keep |t| < L
         float* acc = (a.parity == 0) ? a.f1m : a.f1p;
+        const int hT = a.hist_T >> 1;
+        float* hrow = (MODE == TM_ITER && a.hist && a.rec_slot >= 0)
+                          ? a.hist + (((size_t)f * a.nr + r) * a.hist_k + a.rec_slot) * a.hist_T
+                          : nullptr;
 #pragma unroll
         for (int p = 0; p < PM; ++p) {
             const int m = lane + TPT * p;
@@ -204,21 +208,45 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
                 // N[t] = -RN[(nt - t) mod nt] inside the window
                 const float n0 = k0 ? -s * z[(M - m) & (M - 1)].x : 0.f;
                 const float n1 = k1 ? -s * z[M - 1 - m].y : 0.f;
-                nacc += (double)n0 * n0 + (double)n1 * n1;
-                if (valid && (k0 || k1)) {
-                    float2* pa = reinterpret_cast<float2*>(acc + tbase) + m;
-                    float2 o = *pa;
-                    if (a.parity == 0) {             // f1- -= N(-t)  ==  f1- += theta RN
-                        const float2 zm = z[m];
-                        if (k0) o.x += s * zm.x;
-                        if (k1) o.y += s * zm.y;
-                    } else {                          // f1+ += N
-                        o.x += n0;
-                        o.y += n1;
+                if (MODE == TM_ITER) {
+                    nacc += (double)n0 * n0 + (double)n1 * n1;
+                    if (valid && (k0 || k1)) {
+                        float2* pa = reinterpret_cast<float2*>(acc + tbase) + m;
+                        float2 o = *pa;
+                        if (a.parity == 0) {             // f1- -= N(-t)  ==  f1- += theta RN
+                            const float2 zm = z[m];
+                            if (k0) o.x += s * zm.x;
+                            if (k1) o.y += s * zm.y;
+                        } else {                          // f1+ += N
+                            o.x += n0;
+                            o.y += n1;
+                        }
+                        *pa = o;
                     }
-                    *pa = o;
+                    if (hrow && valid) {                  // record N_i on the window |t| < T/2
+                        if (s0 < hT && -s0 <= hT) hrow[s0 + hT] = n0;
+                        if (s1 < hT && -s1 <= hT) hrow[s1 + hT] = n1;
+                    }
+                    out[p] = make_float2(n0, n1);
+                } else if (MODE == TM_RST1) {
+                    // f1- := theta S f1+ (overwrite); the field fed on is N' = -(theta RN)(-t)
+                    nacc += (double)n0 * n0 + (double)n1 * n1;
+                    if (valid) {
+                        const float2 zm = z[m];
+                        reinterpret_cast<float2*>(a.f1m + tbase)[m] =
+                            make_float2(k0 ? s * zm.x : 0.f, k1 ? s * zm.y : 0.f);
+                    }
+                    out[p] = make_float2(n0, n1);
+                } else {
+                    // N'' = A^2 f1+; rho = N_-1 + N'' - f1+; f1+ := N_-1 + N''
+                    const float2 b0 = reinterpret_cast<const float2*>(a.n0 + tbase)[m];
+                    const float2 fp = reinterpret_cast<const float2*>(a.f1p + tbase)[m];
+                    const float2 nf2 = make_float2(b0.x + n0, b0.y + n1);
+                    const float2 rho = make_float2(nf2.x - fp.x, nf2.y - fp.y);
+                    nacc += (double)rho.x * rho.x + (double)rho.y * rho.y;
+                    if (valid) reinterpret_cast<float2*>(a.f1p + tbase)[m] = nf2;
+                    out[p] = rho;
                 }
-                out[p] = make_float2(n0, n1);
             }
         }
         __syncthreads();
@@ -240,9 +268,16 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
                 if (valid) {
                     reinterpret_cast<float2*>(a.f1p + tbase)[m] = make_float2(n0, n1);
                     reinterpret_cast<float2*>(a.f1m + tbase)[m] = make_float2(0.f, 0.f);
+                    if (a.n0) reinterpret_cast<float2*>(a.n0 + tbase)[m] = make_float2(n0, n1);
                 }
                 z[m] = make_float2(n0, n1);
             }
+        }
+    } else if (MODE == TM_FWDF) {
+#pragma unroll
+        for (int p = 0; p < PM; ++p) {
+            const int m = lane + TPT * p;
+            if (m < M) z[m] = reinterpret_cast<const float2*>(a.f1p + tbase)[m];
         }
     } else if (MODE == TM_GFWD) {
         const bool minus = (fo & 1) != 0;
@@ -319,7 +354,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         }
         if (valid && r == 0 && lane == 0) a.xs_out[fo] = xs;
     }
-    if (MODE == TM_ITER) {
+    if (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2) {
         nacc = wave_sum_d(nacc);
         if (TPT > 64) {                      // combine the block's waves in a fixed order
             if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nacc;
@@ -383,6 +418,9 @@ hipError_t launch_trace_tpt(int mode, const TraceArgs& a, hipStream_t s) {
         case TM_ITER: hipLaunchKernelGGL((k_trace<NT, TM_ITER, TPT>), grid, block, 0, s, a); break;
         case TM_GFWD: hipLaunchKernelGGL((k_trace<NT, TM_GFWD, TPT>), grid, block, 0, s, a); break;
         case TM_GOUT: hipLaunchKernelGGL((k_trace<NT, TM_GOUT, TPT>), grid, block, 0, s, a); break;
+        case TM_FWDF: hipLaunchKernelGGL((k_trace<NT, TM_FWDF, TPT>), grid, block, 0, s, a); break;
+        case TM_RST1: hipLaunchKernelGGL((k_trace<NT, TM_RST1, TPT>), grid, block, 0, s, a); break;
+        case TM_RST2: hipLaunchKernelGGL((k_trace<NT, TM_RST2, TPT>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -68,7 +68,8 @@ void free_plan_memory(mk_plan_t p) {
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     void* bufs[] = {p->R, p->rscale, p->X, p->Y, p->f1p, p->f1m, p->gp, p->gm, p->stage, p->itd,
                     p->fband, p->perm, p->iperm, p->ncols, p->npart, p->norm0, p->nlast, p->xscale,
-                    p->norms, p->tw, p->flag};
+                    p->norms, p->tw, p->flag, p->n0, p->hist, p->tail_w, p->tail_x, p->tail_work,
+                    p->tail_y, p->tail_scale};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& pe : p->pending) {
@@ -261,6 +262,11 @@ TraceArgs trace_args(mk_plan_t p, int nfo) {
     a.xs_out = p->xscale;
     a.xprec = XP_F32;
     a.skip_outband = 0;
+    a.n0 = p->n0;
+    a.hist = nullptr;
+    a.hist_k = p->hist_k;
+    a.hist_T = p->hist_T;
+    a.rec_slot = -1;
     a.nr = p->d.nr;
     a.nf = p->nf;
     a.nfo = nfo;
@@ -441,6 +447,7 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     if ((e = dalloc(&p->xscale, 3 * nfm)) != hipSuccess) return bail(e, "X scales");
     if ((e = dalloc(&p->tw, (size_t)d.nt)) != hipSuccess) return bail(e, "twiddles");
     if ((e = dalloc(&p->flag, 1)) != hipSuccess) return bail(e, "flag");
+    if ((e = dalloc(&p->n0, nfm * trace)) != hipSuccess) return bail(e, "N_-1");
     // the padding columns of X (s >= ns) must read as zero
     if ((e = hipMemsetAsync(p->X, 0, 3 * nfm * p->B * p->ns_pad * sizeof(float2), p->stream)) !=
         hipSuccess)
@@ -577,6 +584,8 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
     p->nf = nf;
     p->shift = shift;
     p->passes = 0;
+    p->pass_base = 0;
+    p->tail_applied = false;
     p->g_valid = false;
     p->series_choice = choose(p, nf);
     p->g_choice = choose(p, 2 * nf);
@@ -595,6 +604,7 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
     HIP_TRY(p, hipStreamSynchronize(p->stream));
     p->norm0_host.assign(nf, 0.0);
     for (int j = 0; j < nf; ++j) p->norm0_host[perm[j]] = n0[j];
+    p->gd_norm_host = p->norm0_host;
     p->focal_set = true;
     return MK_OK;
 }
@@ -610,6 +620,11 @@ mk_status enqueue_passes(mk_plan_t p, int i0, int n, int parity0) {
         MK_TRY(run_contract(p, p->series_choice, p->X, p->xscale, p->nf, 1, 0));
         TraceArgs a = trace_args(p, p->nf);
         a.parity = (parity0 + (i - i0)) & 1;
+        const int idx = p->passes + (i - i0);          // pass index since mk_set_focal
+        if (p->hist && !p->tail_applied && idx < p->hist_k) {
+            a.hist = p->hist;
+            a.rec_slot = idx;
+        }
         a.xprec = p->series_choice.xprec;
         a.xs_in = p->nlast;
         a.xs_out = p->xscale;
@@ -676,9 +691,13 @@ mk_status mk_iterate(mk_plan_t p, int32_t niter, double* norms) {
     p->g_valid = false;
     // graphs replay passes whose contraction is already chosen: while the
     // autotuner still has to time this column count, the passes run eagerly
-    const bool graph = (p->d.flags & MK_FLAG_GRAPH) && !(p->d.flags & MK_FLAG_PROFILE) && !tune_pending(p);
-    if (graph) MK_TRY(replay_passes(p, niter, p->passes & 1));
-    else MK_TRY(enqueue_passes(p, 0, niter, p->passes & 1));
+    // (and while the first passes are being recorded for the series tail)
+    const bool recording = p->hist && !p->tail_applied && p->passes < p->hist_k;
+    const bool graph = (p->d.flags & MK_FLAG_GRAPH) && !(p->d.flags & MK_FLAG_PROFILE) && !tune_pending(p) &&
+                       !recording;
+    const int parity0 = (p->passes - p->pass_base) & 1;
+    if (graph) MK_TRY(replay_passes(p, niter, parity0));
+    else MK_TRY(enqueue_passes(p, 0, niter, parity0));
     p->passes += niter;
     if (norms) {
         std::vector<double> h((size_t)niter * p->nf);
@@ -752,6 +771,128 @@ mk_status mk_contract_variant(mk_plan_t p, int32_t ncols, int32_t* variant) {
             return MK_OK;
         }
     *variant = choose(p, ncols).variant;
+    return MK_OK;
+}
+
+
+mk_status mk_tail_record(mk_plan_t p, int32_t k, int32_t T) {
+    if (!p) return fail(nullptr, MK_ERR_ARG, "mk_tail_record: plan is NULL");
+    if (k < 1 || k > 16 || T < 2 || (T & 1) || T > p->d.nt)
+        return fail(p, MK_ERR_ARG, "mk_tail_record: need 1 <= k <= 16 and an even T <= nt");
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    if (p->hist) HIP_TRY(p, hipFree(p->hist));
+    p->hist = nullptr;
+    if (p->tail_w && k != p->hist_k) {
+        HIP_TRY(p, hipFree(p->tail_w));
+        p->tail_w = nullptr;
+        p->tail_nw = 0;
+    }
+    const size_t n = (size_t)p->d.nf_max * p->d.nr * k * T;
+    HIP_TRY(p, dalloc(&p->hist, n));
+    HIP_TRY(p, hipMemsetAsync(p->hist, 0, n * sizeof(float), p->stream));
+    p->hist_k = k;
+    p->hist_T = T;
+    drop_graphs(p);
+    return MK_OK;
+}
+
+mk_status mk_tail_load(mk_plan_t p, const float* params, int32_t count) {
+    if (!p) return fail(nullptr, MK_ERR_ARG, "mk_tail_load: plan is NULL");
+    if (!params) return fail(p, MK_ERR_ARG, "mk_tail_load: params is NULL");
+    if (!p->hist) return fail(p, MK_ERR_STATE, "mk_tail_load: call mk_tail_record first");
+    if (count != net_param_count(p->hist_k))
+        return fail(p, MK_ERR_ARG, "mk_tail_load: parameter count does not match k");
+    for (int i = 0; i < count; ++i)
+        if (!std::isfinite(params[i])) return fail(p, MK_ERR_ARG, "mk_tail_load: non-finite parameter");
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    if (!p->tail_w) HIP_TRY(p, dalloc(&p->tail_w, (size_t)count));
+    HIP_TRY(p, hipMemcpyAsync(p->tail_w, params, count * sizeof(float), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(p, net_round_bf16(p->tail_w, p->tail_w, count, p->stream));
+    p->tail_nw = count;
+    if (!p->tail_x) {
+        const int ntr = p->d.nf_max * p->d.nr;
+        p->tail_chunk = std::min(ntr, 4096);
+        const size_t c = (size_t)p->tail_chunk, T = (size_t)p->hist_T, k = (size_t)p->hist_k;
+        HIP_TRY(p, dalloc(&p->tail_x, c * 16 * T));                 // room for k <= 16
+        HIP_TRY(p, dalloc(&p->tail_work, 2 * c * kNetHidden * T));
+        HIP_TRY(p, dalloc(&p->tail_y, c * 2 * T));
+        HIP_TRY(p, dalloc(&p->tail_scale, (size_t)ntr));
+        (void)k;
+    }
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return MK_OK;
+}
+
+mk_status mk_tail_history(mk_plan_t p, float* out, int on_device) {
+    if (!p || !out) return fail(p, MK_ERR_ARG, "mk_tail_history: NULL argument");
+    if (!p->hist || !p->focal_set) return fail(p, MK_ERR_STATE, "mk_tail_history: nothing recorded");
+    const size_t per = (size_t)p->d.nr * p->hist_k * p->hist_T;
+    const size_t n = per * p->nf;
+    float* dst = out;
+    float* tmp = nullptr;
+    if (!on_device) {
+        HIP_TRY(p, dalloc(&tmp, n));
+        dst = tmp;
+    }
+    hipError_t e = launch_gather(p->hist, dst, p->iperm, p->nf, (int64_t)per, p->stream);
+    if (e == hipSuccess && !on_device)
+        e = hipMemcpyAsync(out, tmp, n * sizeof(float), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess && !on_device) e = hipStreamSynchronize(p->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(p, e, "mk_tail_history");
+    return MK_OK;
+}
+
+mk_status mk_tail_apply(mk_plan_t p, int32_t mode, double* rel_resid) {
+    if (!p) return fail(nullptr, MK_ERR_ARG, "mk_tail_apply: plan is NULL");
+    if (mode < 0 || mode > 2) return fail(p, MK_ERR_ARG, "mk_tail_apply: mode must be 0, 1 or 2");
+    if (!p->focal_set || !p->hist || p->tail_applied || p->passes - p->pass_base != p->hist_k)
+        return fail(p, MK_ERR_STATE, "mk_tail_apply: needs exactly k recorded passes of a fresh series");
+    if (mode == 0 && !p->tail_w) return fail(p, MK_ERR_STATE, "mk_tail_apply: no network loaded");
+    if (mode == 1 && (p->hist_k < 4 || (p->hist_k & 1)))
+        return fail(p, MK_ERR_ARG, "mk_tail_apply: geometric extrapolation needs an even k >= 4");
+    const int nr = p->d.nr, nt = p->d.nt, k = p->hist_k, T = p->hist_T;
+    const int ntr = p->nf * nr;
+    if (mode == 0) {
+        const size_t act = (size_t)p->tail_chunk * kNetHidden * T;
+        for (int c0 = 0; c0 < ntr; c0 += p->tail_chunk) {
+            const int n = std::min(p->tail_chunk, ntr - c0);
+            const float* h = p->hist + (size_t)c0 * k * T;
+            HIP_TRY(p, launch_tail_prep(h, n, k, T, p->tail_x, p->tail_scale + c0, p->stream));
+            HIP_TRY(p, net_forward(p->tail_w, p->tail_x, n, k, T, p->tail_work, p->tail_work + act, p->tail_y,
+                                   p->stream));
+            HIP_TRY(p, launch_tail_apply(h, p->tail_y, p->tail_scale + c0, p->itd + c0, p->shift, n, k, T, nt, 0,
+                                         p->f1p + (size_t)c0 * nt, p->f1m + (size_t)c0 * nt, p->stream));
+        }
+    } else if (mode == 1) {
+        HIP_TRY(p, launch_tail_apply(p->hist, nullptr, nullptr, p->itd, p->shift, ntr, k, T, nt, 1, p->f1p, p->f1m,
+                                     p->stream));
+    }
+    // the judge: one fixed-point step f1+ <- G_d(-t) + A^2 f1+ (two syntheses),
+    // whose residual starts a new Neumann series for the remaining error
+    TraceArgs a = trace_args(p, p->nf);
+    a.xprec = p->series_choice.xprec;
+    a.xs_in = p->norm0;
+    a.xs_out = p->xscale;
+    a.skip_outband = (p->series_choice.variant != 0 && p->has_fband) ? 1 : 0;
+    MK_TRY(run_trace(p, TM_FWDF, a, 1));
+    MK_TRY(run_contract(p, p->series_choice, p->X, p->xscale, p->nf, 1, 0));
+    MK_TRY(run_trace(p, TM_RST1, a, 1));
+    MK_TRY(run_contract(p, p->series_choice, p->X, p->xscale, p->nf, 1, 0));
+    MK_TRY(run_trace(p, TM_RST2, a, 1));
+    HIP_TRY(p, launch_norm_reduce(p->npart, nr, p->nf, p->norm0, p->nlast, p->stream));
+    std::vector<double> rn(p->nf);
+    HIP_TRY(p, hipMemcpyAsync(rn.data(), p->norm0, p->nf * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    for (int j = 0; j < p->nf; ++j) {
+        const int f = p->perm_host[j];
+        p->norm0_host[f] = rn[j];
+        if (rel_resid) rel_resid[f] = p->gd_norm_host[f] > 0.0 ? rn[j] / p->gd_norm_host[f] : rn[j];
+    }
+    p->passes += 2;
+    p->pass_base = p->passes;
+    p->tail_applied = true;
+    p->g_valid = false;
     return MK_OK;
 }
 

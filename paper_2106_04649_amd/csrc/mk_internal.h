@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -14,7 +15,10 @@ enum TraceMode : int {
     TM_INIT = 0,   // N_-1 = Gd(-t); f1+ = N_-1; f1- = 0; X = rfft(N_-1)
     TM_ITER = 1,   // RN = irfft(Y); N = mute(-RN(-t)); accumulate; X = rfft(N)
     TM_GFWD = 2,   // X[2f] = rfft(f1+[f]); X[2f+1] = rfft(f1-[f](-t))
-    TM_GOUT = 3    // G- = irfft(Y[2f]) - f1-;  G+ = f1+(-t) - irfft(Y[2f+1])
+    TM_GOUT = 3,   // G- = irfft(Y[2f]) - f1-;  G+ = f1+(-t) - irfft(Y[2f+1])
+    TM_FWDF = 4,   // X[f] = rfft(f1+[f])                      (restart, first synthesis)
+    TM_RST1 = 5,   // RN = irfft(Y); f1- := theta RN; N' = -RN(-t) windowed; X = rfft(N')
+    TM_RST2 = 6    // N'' = mute(-RN(-t)); rho = N_-1 + N'' - f1+; f1+ := N_-1 + N''; X = rfft(rho)
 };
 
 // Storage of the contraction input X.
@@ -43,6 +47,10 @@ struct TraceArgs {
     float* xs_out;         // [nfo] scale written next to 16-bit X (X = xs_out * stored)
     int xprec;             // XPrec
     int skip_outband;      // X above the focal band end is never read: do not write it
+    float* n0;             // [nf][nr][nt] N_-1 = G_d(-t), kept for the restart
+    float* hist;           // [nf][nr][hist_k][hist_T] recorded iterates (or null)
+    int hist_k, hist_T;
+    int rec_slot;          // iterate index this pass records, or -1
     int nr;
     int nf;        // focal points of the series
     int nfo;       // traces are nfo x nr (nf, or 2 nf for the G modes)
@@ -96,6 +104,21 @@ struct mk_plan_s {
     int norm_cap = 0;
     float2* tw = nullptr;      // [nt]
     int* flag = nullptr;       // device scratch flag (non-finite input detection)
+    float* n0 = nullptr;       // [nf_max][nr][nt] N_-1 = G_d(-t)
+
+    // series tail: recorded iterates and the network
+    float* hist = nullptr;     // [nf_max][nr][hist_k][hist_T]
+    int hist_k = 0, hist_T = 0;
+    float* tail_w = nullptr;   // BF16-rounded parameters
+    int tail_nw = 0;
+    float* tail_x = nullptr;   // [chunk][k][T] normalised input
+    float* tail_work = nullptr;   // [2][chunk][64][T]
+    float* tail_y = nullptr;   // [chunk][2][T]
+    float* tail_scale = nullptr;  // [nf_max][nr]
+    int tail_chunk = 0;
+    int pass_base = 0;         // passes before the current series (a restart starts a new one)
+    bool tail_applied = false;
+    std::vector<double> gd_norm_host;   // ||G_d|| per focal point (caller order)
 
     // series state
     int nf = 0;
@@ -166,3 +189,20 @@ hipError_t launch_repack_c64(const float* Rin, float2* Rout, int nr, int B, int 
 hipError_t launch_quantize_R(int prec, const float* Rin, void* Rout, float* rscale, int nr, int B,
                              int ns, int ns_pad, int* flag, hipStream_t s);
 hipError_t launch_check_finite(const float* x, int64_t n, int* flag, hipStream_t s);
+hipError_t launch_tail_prep(const float* hist, int ntr, int k, int T, float* x, float* scale, hipStream_t s);
+hipError_t launch_tail_apply(const float* hist, const float* y, const float* scale, const int32_t* itd, int shift,
+                             int ntr, int k, int T, int nt, int mode, float* f1p, float* f1m, hipStream_t s);
+
+// series-tail network (fixed architecture: k -> 64 -> 64 -> 2 channels, 5 taps)
+constexpr int kNetHidden = 64;
+constexpr int kNetDil[3] = {1, 4, 16};
+int net_param_count(int k);
+hipError_t net_forward(const float* P, const float* x, int N, int k, int T, float* a1, float* a2,
+                       float* y, hipStream_t s);
+hipError_t net_backward(const float* P, const float* x, const float* a1, const float* a2, const float* gy,
+                        int N, int k, int T, float* G, float* g1, float* g2, float* wt, hipStream_t s);
+hipError_t net_mse(const float* y, const float* tgt, const float* mask, int N, int T, float* gy,
+                   double* part, int nparts, double* loss, float count, hipStream_t s);
+hipError_t net_adam(float* w, float* wq, const float* g, float* m, float* v, int n, int step, float lr,
+                    float b1, float b2, float eps, hipStream_t s);
+hipError_t net_round_bf16(const float* w, float* wq, int n, hipStream_t s);

@@ -76,6 +76,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mk_profile": (i32, [P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                              ctypes.c_int]),
         "mk_destroy": (i32, [P]),
+        "mk_tail_record": (i32, [P, i32, i32]),
+        "mk_tail_load": (i32, [P, P, i32]),
+        "mk_tail_history": (i32, [P, P, ctypes.c_int]),
+        "mk_tail_apply": (i32, [P, i32, P]),
+        "mk_net_param_count": (i32, [i32]),
+        "mk_net_last_error": (ctypes.c_char_p, []),
+        "mk_net_forward": (i32, [P, P, i32, i32, i32, P, P, P]),
+        "mk_net_backward": (i32, [P, P, P, P, i32, i32, i32, P, P, P]),
+        "mk_net_loss": (i32, [P, P, P, i32, i32, ctypes.c_float, P, P, P, i32, P]),
+        "mk_net_adam": (i32, [P, P, P, P, P, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, P]),
+        "mk_net_round": (i32, [P, P, i32, P]),
         "mk_strerror": (ctypes.c_char_p, [i32]),
         "mk_last_error": (ctypes.c_char_p, [P]),
     }
@@ -241,3 +253,89 @@ def mk_destroy(plan: Plan) -> None:
     if plan.handle:
         _check(load_library().mk_destroy(plan.handle), None)
         plan.handle = None
+
+
+# --- series tail ------------------------------------------------------------
+
+TAIL_NET, TAIL_GEOMETRIC, TAIL_NONE = 0, 1, 2
+
+
+def mk_tail_record(plan: Plan, k: int, T: int) -> None:
+    _check(load_library().mk_tail_record(plan.handle, int(k), int(T)), plan.handle)
+    plan.tail_kT = (int(k), int(T))
+
+
+def mk_tail_load(plan: Plan, params) -> None:
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(load_library().mk_tail_load(plan.handle, a.ctypes.data, a.size), plan.handle)
+
+
+def mk_tail_history(plan: Plan, out=None):
+    k, T = plan.tail_kT
+    shape = (plan.nf, plan.desc.nr, k, T)
+    if out is None:
+        out = np.zeros(shape, np.float32)
+    if _is_torch(out):
+        ptr, dev, _ = _ptr(out, "float32")
+    else:
+        ptr, dev = out.ctypes.data, 0
+    _check(load_library().mk_tail_history(plan.handle, ptr, dev), plan.handle)
+    return out
+
+
+def mk_tail_apply(plan: Plan, mode: int = TAIL_NET) -> np.ndarray:
+    res = np.zeros(plan.nf, np.float64)
+    _check(load_library().mk_tail_apply(plan.handle, int(mode), res.ctypes.data), plan.handle)
+    return res
+
+
+# --- series-tail network (device tensors only) --------------------------------
+
+
+def _dev(t, dtype="float32"):
+    import torch
+
+    want = {"float32": torch.float32, "float64": torch.float64}[dtype]
+    if not (t.is_cuda and t.dtype == want and t.is_contiguous()):
+        raise TypeError(f"expected a contiguous CUDA {dtype} tensor")
+    return t.data_ptr()
+
+
+def _net_check(status: int) -> None:
+    if status != MK_OK:
+        raise MKError(status, load_library().mk_net_last_error().decode())
+
+
+def mk_net_param_count(k: int) -> int:
+    return int(load_library().mk_net_param_count(int(k)))
+
+
+def mk_net_forward(params, x, work, y, stream=None) -> None:
+    N, k, T = x.shape
+    s = _current_stream() if stream is None else stream
+    _net_check(load_library().mk_net_forward(_dev(params), _dev(x), N, k, T, _dev(work), _dev(y), s))
+
+
+def mk_net_backward(params, x, work, gy, grads, work2, stream=None) -> None:
+    N, k, T = x.shape
+    s = _current_stream() if stream is None else stream
+    _net_check(load_library().mk_net_backward(_dev(params), _dev(x), _dev(work), _dev(gy), N, k, T,
+                                              _dev(grads), _dev(work2), s))
+
+
+def mk_net_loss(y, target, mask, count, gy, loss, part, stream=None) -> None:
+    N, _, T = y.shape
+    s = _current_stream() if stream is None else stream
+    _net_check(load_library().mk_net_loss(_dev(y), _dev(target), _dev(mask), N, T, float(count), _dev(gy),
+                                          _dev(loss, "float64"), _dev(part, "float64"), part.numel(), s))
+
+
+def mk_net_adam(w, wq, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None) -> None:
+    s = _current_stream() if stream is None else stream
+    _net_check(load_library().mk_net_adam(_dev(w), _dev(wq), _dev(g), _dev(m), _dev(v), w.numel(), int(step),
+                                          float(lr), float(b1), float(b2), float(eps), s))
+
+
+def mk_net_round(w, wq, stream=None) -> None:
+    s = _current_stream() if stream is None else stream
+    _net_check(load_library().mk_net_round(_dev(w), _dev(wq), w.numel(), s))

@@ -1,0 +1,307 @@
+"""Train and evaluate the series-tail network on the GPU.
+
+    python -m paper_2106_04649_amd.tailtrain --train 384 --holdout 64 \\
+        --out paper_2106_04649_amd/tailnet_k4.npz
+
+Data: the method's own iterate sequences.  For each seeded layered model
+(301 x 301 at 10 m, nt 1024 at 4 ms, 4-12 layers, half of them with dipping
+reflectors, one focal point) a plain solve through the library records
+N_0 .. N_{k-1} on a window of T samples around t = 0; the targets are the
+parity-split sums of the remaining passes up to pass 32, read off f1+ and
+f1- after k and after 32 passes:
+    T_odd  = f1+_32 - f1+_k,        T_even = -(f1-_32 - f1-_k)(-t).
+Inputs and targets are divided by the RMS of N_0 on the window (per trace),
+as the library does at inference; the loss is masked to the mute window.
+
+Training runs on the library's own kernels (mk_net_forward / backward /
+loss / adam): FP32 master weights with Adam, BF16-rounded weights in the
+forward pass (the stored form of the network).
+
+Evaluation on held-out models against the 32-pass plain solve (the judge):
+relative L2 error of f1+, f1-, G+, G- for the plain series truncated at k
+and at k + 2 passes, and for the geometric and the learned tail after the
+two judging syntheses (k + 2 syntheses in all).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import mk
+
+K_DEFAULT, T_DEFAULT = 4, 512
+FIELDS = ("f1plus", "f1minus", "Gplus", "Gminus")
+
+
+def log(msg):
+    print(f"[tail] {msg}", file=sys.stderr, flush=True)
+
+
+def _window_idx(T, nt, device):
+    import torch
+
+    return (torch.arange(T, device=device) - T // 2) % nt
+
+
+def _rev(x):
+    import torch
+
+    nt = x.shape[-1]
+    return x[..., (-torch.arange(nt, device=x.device)) % nt]
+
+
+class Solver:
+    """One plan reused for every model of the tail workload (same geometry)."""
+
+    def __init__(self, geom, k, T, rprec=0):
+        self.k, self.T, self.nt, self.n = k, T, geom.nt, geom.n
+        self.plan = mk.mk_plan(geom.n, geom.n, geom.nt, geom.dt, geom.dx, nf_max=1, rprec=rprec)
+        mk.mk_tail_record(self.plan, k, T)
+
+    def load(self, p):
+        import torch
+
+        mk.mk_load_R(self.plan, p.Rhat)
+        self.p = p
+        self.Gd = torch.from_numpy(p.Gd).cuda()
+        self.itd = torch.from_numpy(p.itd).cuda()
+
+    def fields(self):
+        import torch
+
+        return {f: mk.mk_get(self.plan, f, torch.empty((1, self.n, self.nt), device="cuda")) for f in FIELDS}
+
+    def run_plain(self, passes):
+        mk.mk_set_focal(self.plan, self.Gd, self.itd, self.p.shift)
+        mk.mk_iterate(self.plan, passes, want_norms=False)
+        return self.fields()
+
+    def run_tail(self, mode):
+        mk.mk_set_focal(self.plan, self.Gd, self.itd, self.p.shift)
+        mk.mk_iterate(self.plan, self.k, want_norms=False)
+        res = mk.mk_tail_apply(self.plan, mode)
+        return self.fields(), float(res[0])
+
+    def sample(self, niter=32):
+        """(hist [nr][k][T], targets [nr][2][T], mask [nr][T]) of the current model."""
+        import torch
+
+        mk.mk_set_focal(self.plan, self.Gd, self.itd, self.p.shift)
+        mk.mk_iterate(self.plan, self.k, want_norms=False)
+        hist = mk.mk_tail_history(self.plan, torch.empty((1, self.n, self.k, self.T), device="cuda"))[0]
+        f4 = self.fields()
+        mk.mk_iterate(self.plan, niter - self.k, want_norms=False)
+        f32 = self.fields()
+        idx = _window_idx(self.T, self.nt, "cuda")
+        t_odd = (f32["f1plus"] - f4["f1plus"])[0][:, idx]
+        t_even = -_rev(f32["f1minus"] - f4["f1minus"])[0][:, idx]
+        t = torch.arange(self.T, device="cuda") - self.T // 2
+        L = (self.itd[0] - self.p.shift)[:, None]
+        mask = ((t[None, :] < L) & (-t[None, :] < L) & (t[None, :] != self.nt // 2)).float()
+        return hist.contiguous(), torch.stack([t_even, t_odd], dim=1).contiguous(), mask
+
+    def destroy(self):
+        mk.mk_destroy(self.plan)
+
+
+def normalise(hist, tgt, mask):
+    import torch
+
+    s = torch.sqrt((hist[:, 0, :] ** 2).mean(dim=-1))
+    ok = s > 1e-30
+    inv = torch.where(ok, 1.0 / torch.where(ok, s, torch.ones_like(s)), torch.zeros_like(s))
+    return hist * inv[:, None, None], tgt * inv[:, None, None], mask * ok[:, None].float()
+
+
+def build_dataset(seeds, k, T, gen):
+    import torch
+
+    xs, ys, ms = [], [], []
+    solver = None
+    t0 = time.perf_counter()
+    for i, seed in enumerate(seeds):
+        p = gen(seed)
+        if solver is None:
+            solver = Solver(p.geom, k, T)
+        solver.load(p)
+        h, y, m = solver.sample()
+        x, y, m = normalise(h, y, m)
+        xs.append(x)
+        ys.append(y)
+        ms.append(m)
+        if (i + 1) % 32 == 0:
+            log(f"dataset {i + 1}/{len(seeds)} models ({time.perf_counter() - t0:.1f} s)")
+    solver.destroy()
+    return torch.cat(xs), torch.cat(ys), torch.cat(ms)
+
+
+def init_params_flat(k, seed=0):
+    """He initialisation (last layer scaled down), flattened in the library's layout."""
+    rng = np.random.default_rng(seed)
+    H, Kt = 64, 5
+
+    def w(o, c, scale):
+        return rng.standard_normal((o, c, Kt)) * scale
+
+    parts = [w(H, k, math.sqrt(2.0 / (k * Kt))), np.zeros(H), w(H, H, math.sqrt(2.0 / (H * Kt))), np.zeros(H),
+             w(2, H, 0.1 * math.sqrt(1.0 / (H * Kt))), np.zeros(2)]
+    return np.concatenate([q.ravel() for q in parts]).astype(np.float32)
+
+
+def fit(X, Y, Mk, k, T, steps, batch, lr, seed=0, val=None):
+    import torch
+
+    n = mk.mk_net_param_count(k)
+    w = torch.from_numpy(init_params_flat(k, seed)).cuda()
+    wq = torch.empty_like(w)
+    mk.mk_net_round(w, wq)
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    g = torch.zeros_like(w)
+    N = X.shape[0]
+    work = torch.empty(2 * batch * 64 * T, device="cuda")
+    work2 = torch.empty(2 * batch * 64 * T + 64 * 64 * 5, device="cuda")
+    yb = torch.empty((batch, 2, T), device="cuda")
+    gy = torch.empty_like(yb)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    part = torch.zeros(256, dtype=torch.float64, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    curve = []
+    t0 = time.perf_counter()
+    for step in range(1, steps + 1):
+        idx = torch.randint(0, N, (batch,), device="cuda", generator=gen)
+        xb, tb, mb = X[idx].contiguous(), Y[idx].contiguous(), Mk[idx].contiguous()
+        cnt = float(mb.sum().item()) * 2.0
+        if cnt <= 0:
+            continue
+        mk.mk_net_forward(wq, xb, work, yb)
+        mk.mk_net_loss(yb, tb, mb, cnt, gy, loss, part)
+        mk.mk_net_backward(wq, xb, work, gy, g, work2)
+        lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * step / steps))      # cosine decay
+        mk.mk_net_adam(w, wq, g, m, v, step, lr=lr_t)
+        if step % 200 == 0 or step == steps:
+            rec = {"step": step, "loss": float(loss.item())}
+            if val is not None:
+                rec["val_loss"] = evaluate_loss(wq, *val, T, batch)
+            curve.append(rec)
+            log(f"step {step}: {rec} ({time.perf_counter() - t0:.1f} s)")
+    assert n == w.numel()
+    return w.cpu().numpy(), curve
+
+
+def evaluate_loss(wq, X, Y, Mk, T, batch):
+    import torch
+
+    tot, cnt = 0.0, 0.0
+    work = torch.empty(2 * batch * 64 * T, device="cuda")
+    yb = torch.empty((batch, 2, T), device="cuda")
+    for i in range(0, X.shape[0] - batch + 1, batch):
+        xb = X[i:i + batch].contiguous()
+        mk.mk_net_forward(wq, xb, work, yb)
+        r = (yb - Y[i:i + batch]) * Mk[i:i + batch][:, None, :]
+        tot += float((r * r).sum().item())
+        cnt += float(Mk[i:i + batch].sum().item()) * 2
+    return tot / max(cnt, 1.0)
+
+
+def rel(a, b):
+    import torch
+
+    nb = torch.linalg.vector_norm(b).item()
+    return torch.linalg.vector_norm(a - b).item() / nb if nb > 0 else 0.0
+
+
+def evaluate(params, seeds, k, T, gen, rprec=0):
+    """Errors against the 32-pass plain solve on held-out models."""
+    rows = []
+    solver = None
+    for seed in seeds:
+        p = gen(seed)
+        if solver is None:
+            solver = Solver(p.geom, k, T, rprec=rprec)
+            if params is not None:
+                mk.mk_tail_load(solver.plan, params)
+        solver.load(p)
+        ref = solver.run_plain(32)
+        row = {"seed": int(seed)}
+        runs = [("plain_k", lambda: (solver.run_plain(k), None)),
+                ("plain_k2", lambda: (solver.run_plain(k + 2), None)),
+                ("geometric", lambda: solver.run_tail(1))]
+        if params is not None:
+            runs.append(("learned", lambda: solver.run_tail(0)))
+        for name, fn in runs:
+            out, res = fn()
+            row[name] = {f: rel(out[f], ref[f]) for f in FIELDS}
+            if res is not None:
+                row[name]["judge_residual"] = res
+        rows.append(row)
+    solver.destroy()
+    return rows
+
+
+def summarise(rows):
+    out = {}
+    for name in ("plain_k", "plain_k2", "geometric", "learned"):
+        if name not in rows[0]:
+            continue
+        out[name] = {f: float(np.median([r[name][f] for r in rows])) for f in FIELDS}
+    if "learned" in out:
+        for base in ("plain_k", "plain_k2", "geometric"):
+            out[f"gain_vs_{base}"] = {
+                f: float(np.median([r[base][f] / max(r["learned"][f], 1e-300) for r in rows])) for f in FIELDS}
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=384)
+    ap.add_argument("--holdout", type=int, default=64)
+    ap.add_argument("--k", type=int, default=K_DEFAULT)
+    ap.add_argument("--T", type=int, default=T_DEFAULT)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "tailnet_k4.npz"))
+    ap.add_argument("--report", default=None)
+    args = ap.parse_args(argv)
+
+    import torch
+
+    from mkgen.torchgen import tail_problem_gpu
+
+    torch.cuda.set_device(0)
+    gen = lambda s: tail_problem_gpu(int(s))          # noqa: E731
+    train_seeds = list(range(args.train))
+    hold_seeds = list(range(10000, 10000 + args.holdout))
+    log(f"building the training set ({args.train} models)")
+    X, Y, M = build_dataset(train_seeds, args.k, args.T, gen)
+    log(f"training set: {X.shape[0]} traces")
+    nval = min(len(hold_seeds), 16)
+    Xv, Yv, Mv = build_dataset(hold_seeds[:nval], args.k, args.T, gen)
+    params, curve = fit(X, Y, M, args.k, args.T, args.steps, args.batch, args.lr,
+                        val=(Xv, Yv, Mv))
+    np.savez(args.out, params=params, k=args.k, T=args.T, train_models=args.train, steps=args.steps,
+             curve=json.dumps(curve))
+    log(f"saved {args.out}")
+    del X, Y, M
+    torch.cuda.empty_cache()
+    rows = evaluate(params, hold_seeds, args.k, args.T, gen)
+    summary = summarise(rows)
+    report = {"train_models": args.train, "holdout_models": len(hold_seeds), "k": args.k, "T": args.T,
+              "steps": args.steps, "curve": curve, "summary": summary}
+    if args.report:
+        with open(args.report, "w") as fh:
+            json.dump({"report": report, "rows": rows}, fh)
+    print(json.dumps(report), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "mk.h")
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:mk_status|const char\*)\s+(mk_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:mk_status|const char\*|int32_t)\s+(mk_\w+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -26,7 +26,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ["mk_plan", "mk_load_R", "mk_set_focal", "mk_iterate", "mk_get", "mk_destroy",
-                 "mk_strerror", "mk_last_error"]:
+                 "mk_strerror", "mk_last_error", "mk_net_forward", "mk_net_backward", "mk_net_adam",
+                 "mk_net_param_count"]:
         assert want in names
 
 
@@ -86,3 +87,8 @@ def test_null_arguments(lib):
     assert lib.mk_passes(None, None) == mk.MK_ERR_ARG
     assert lib.mk_profile(None, 0, None, None, 0) == mk.MK_ERR_ARG
     assert lib.mk_destroy(None) == mk.MK_OK
+
+
+def test_net_param_count(lib):
+    assert lib.mk_net_param_count(4) == 64 * 4 * 5 + 64 + 64 * 64 * 5 + 64 + 2 * 64 * 5 + 2
+    assert lib.mk_net_param_count(0) == -1
