@@ -91,3 +91,25 @@ def tail_problem_gpu(seed: int, rho_target: float = 0.7, n: int = 301, nt: int =
     shift = int(math.ceil(1.0 / (geom.fpeak * geom.dt)))
     return Problem(name=f"tail{seed}", geom=geom, model=model, Rhat=R, band=band, Gd=Gd, itd=itd, shift=shift,
                    niter=32, xf=np.array([xf]), zf=np.array([zf]), rho=rho_target, rscale=scale)
+
+
+def medium_problem_gpu(seed: int, nf: int = 64, rho_target: float = 0.7, n: int = 601, nt: int = 2048,
+                       device="cuda") -> Problem:
+    """A model of the 601 x 601, nt 2048 workload family (8 layers + 2 dips)
+    with nf focal points at random positions and depths 200-1200 m; R on the GPU."""
+    rng = np.random.default_rng(seed)
+    geom = Geometry(n=n, dx=5.0 * 600 / max(1, n - 1), nt=nt, dt=0.002 * 2048 / nt)
+    L = (geom.n - 1) * geom.dx
+    model = random_layer_model(rng, 8, (150.0, 1400.0), ndips=2, xrange=(0.3 * L, 0.7 * L), nabove=3,
+                               zsplit=500.0)
+    xf = rng.uniform(0.2 * L, 0.8 * L, size=nf)
+    zf = rng.uniform(200.0, 1200.0, size=nf)
+    band = (0, nt // 2)
+    R = reflection_response_gpu(geom, model, band, device)
+    rho = geom.c * sigma_max_gpu(R)
+    scale = rho_target / rho if rho > 0 else 1.0
+    R *= scale
+    Gd, itd = direct_arrivals(geom, model, xf, zf)
+    shift = int(math.ceil(1.0 / (geom.fpeak * geom.dt)))
+    return Problem(name=f"medium{seed}", geom=geom, model=model, Rhat=R, band=band, Gd=Gd, itd=itd, shift=shift,
+                   niter=32, xf=xf, zf=zf, rho=rho_target, rscale=scale)

@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     constexpr int PM = (M + TPT - 1) / TPT;
     constexpr bool GMODE = MODE == TM_GFWD || MODE == TM_GOUT;
     __shared__ float2 lds[TPB * M];
-    __shared__ double red[4];
+    __shared__ double red[TPT > 64 ? 4 : 1];
     const int wv = threadIdx.x / TPT;       // trace slot in the block
     const int lane = threadIdx.x % TPT;     // thread within the trace
     float2* z = lds + wv * M;

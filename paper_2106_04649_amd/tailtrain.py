@@ -58,11 +58,11 @@ def _rev(x):
 
 
 class Solver:
-    """One plan reused for every model of the tail workload (same geometry)."""
+    """One plan reused for every model of a workload family (same geometry)."""
 
-    def __init__(self, geom, k, T, rprec=0):
-        self.k, self.T, self.nt, self.n = k, T, geom.nt, geom.n
-        self.plan = mk.mk_plan(geom.n, geom.n, geom.nt, geom.dt, geom.dx, nf_max=1, rprec=rprec)
+    def __init__(self, geom, k, T, rprec=0, nf=1):
+        self.k, self.T, self.nt, self.n, self.nf = k, T, geom.nt, geom.n, nf
+        self.plan = mk.mk_plan(geom.n, geom.n, geom.nt, geom.dt, geom.dx, nf_max=nf, rprec=rprec)
         mk.mk_tail_record(self.plan, k, T)
 
     def load(self, p):
@@ -76,7 +76,8 @@ class Solver:
     def fields(self):
         import torch
 
-        return {f: mk.mk_get(self.plan, f, torch.empty((1, self.n, self.nt), device="cuda")) for f in FIELDS}
+        return {f: mk.mk_get(self.plan, f, torch.empty((self.nf, self.n, self.nt), device="cuda"))
+                for f in FIELDS}
 
     def run_plain(self, passes):
         mk.mk_set_focal(self.plan, self.Gd, self.itd, self.p.shift)
@@ -87,25 +88,28 @@ class Solver:
         mk.mk_set_focal(self.plan, self.Gd, self.itd, self.p.shift)
         mk.mk_iterate(self.plan, self.k, want_norms=False)
         res = mk.mk_tail_apply(self.plan, mode)
-        return self.fields(), float(res[0])
+        return self.fields(), float(np.median(res))
 
     def sample(self, niter=32):
-        """(hist [nr][k][T], targets [nr][2][T], mask [nr][T]) of the current model."""
+        """(hist [nf nr][k][T], targets [nf nr][2][T], mask [nf nr][T]) of the current model."""
         import torch
 
         mk.mk_set_focal(self.plan, self.Gd, self.itd, self.p.shift)
         mk.mk_iterate(self.plan, self.k, want_norms=False)
-        hist = mk.mk_tail_history(self.plan, torch.empty((1, self.n, self.k, self.T), device="cuda"))[0]
+        hist = mk.mk_tail_history(self.plan, torch.empty((self.nf, self.n, self.k, self.T), device="cuda"))
         f4 = self.fields()
         mk.mk_iterate(self.plan, niter - self.k, want_norms=False)
         f32 = self.fields()
         idx = _window_idx(self.T, self.nt, "cuda")
-        t_odd = (f32["f1plus"] - f4["f1plus"])[0][:, idx]
-        t_even = -_rev(f32["f1minus"] - f4["f1minus"])[0][:, idx]
+        t_odd = (f32["f1plus"] - f4["f1plus"])[..., idx]
+        t_even = -_rev(f32["f1minus"] - f4["f1minus"])[..., idx]
         t = torch.arange(self.T, device="cuda") - self.T // 2
-        L = (self.itd[0] - self.p.shift)[:, None]
-        mask = ((t[None, :] < L) & (-t[None, :] < L) & (t[None, :] != self.nt // 2)).float()
-        return hist.contiguous(), torch.stack([t_even, t_odd], dim=1).contiguous(), mask
+        L = (self.itd - self.p.shift)[..., None]
+        mask = ((t < L) & (-t < L) & (t != self.nt // 2)).float()
+        flat = self.nf * self.n
+        return (hist.reshape(flat, self.k, self.T).contiguous(),
+                torch.stack([t_even, t_odd], dim=2).reshape(flat, 2, self.T).contiguous(),
+                mask.reshape(flat, self.T).contiguous())
 
     def destroy(self):
         mk.mk_destroy(self.plan)
@@ -120,7 +124,7 @@ def normalise(hist, tgt, mask):
     return hist * inv[:, None, None], tgt * inv[:, None, None], mask * ok[:, None].float()
 
 
-def build_dataset(seeds, k, T, gen):
+def build_dataset(seeds, k, T, gen, rprec=0):
     import torch
 
     xs, ys, ms = [], [], []
@@ -129,14 +133,14 @@ def build_dataset(seeds, k, T, gen):
     for i, seed in enumerate(seeds):
         p = gen(seed)
         if solver is None:
-            solver = Solver(p.geom, k, T)
+            solver = Solver(p.geom, k, T, rprec=rprec, nf=p.nf)
         solver.load(p)
         h, y, m = solver.sample()
         x, y, m = normalise(h, y, m)
         xs.append(x)
         ys.append(y)
         ms.append(m)
-        if (i + 1) % 32 == 0:
+        if (i + 1) % 16 == 0:
             log(f"dataset {i + 1}/{len(seeds)} models ({time.perf_counter() - t0:.1f} s)")
     solver.destroy()
     return torch.cat(xs), torch.cat(ys), torch.cat(ms)
@@ -212,20 +216,23 @@ def evaluate_loss(wq, X, Y, Mk, T, batch):
 
 
 def rel(a, b):
+    """Median over focal points of the relative L2 error."""
     import torch
 
-    nb = torch.linalg.vector_norm(b).item()
-    return torch.linalg.vector_norm(a - b).item() / nb if nb > 0 else 0.0
+    nb = torch.linalg.vector_norm(b.reshape(b.shape[0], -1), dim=1)
+    na = torch.linalg.vector_norm((a - b).reshape(b.shape[0], -1), dim=1)
+    r = torch.where(nb > 0, na / torch.clamp(nb, min=1e-300), torch.zeros_like(na))
+    return float(r.median().item())
 
 
 def evaluate(params, seeds, k, T, gen, rprec=0):
-    """Errors against the 32-pass plain solve on held-out models."""
+    """Errors against the 32-pass plain solve on held-out models (median over focal points)."""
     rows = []
     solver = None
     for seed in seeds:
         p = gen(seed)
         if solver is None:
-            solver = Solver(p.geom, k, T, rprec=rprec)
+            solver = Solver(p.geom, k, T, rprec=rprec, nf=p.nf)
             if params is not None:
                 mk.mk_tail_load(solver.plan, params)
         solver.load(p)
@@ -261,6 +268,9 @@ def summarise(rows):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=["tail", "medium"], default="tail")
+    ap.add_argument("--nf", type=int, default=64, help="focal points per medium model")
+    ap.add_argument("--rprec", type=int, default=0)
     ap.add_argument("--train", type=int, default=384)
     ap.add_argument("--holdout", type=int, default=64)
     ap.add_argument("--k", type=int, default=K_DEFAULT)
@@ -274,27 +284,33 @@ def main(argv=None):
 
     import torch
 
-    from mkgen.torchgen import tail_problem_gpu
+    from mkgen.torchgen import medium_problem_gpu, tail_problem_gpu
 
     torch.cuda.set_device(0)
-    gen = lambda s: tail_problem_gpu(int(s))          # noqa: E731
-    train_seeds = list(range(args.train))
-    hold_seeds = list(range(10000, 10000 + args.holdout))
+    if args.workload == "tail":
+        gen = lambda s: tail_problem_gpu(int(s))                    # noqa: E731
+        train_seeds = list(range(args.train))
+        hold_seeds = list(range(10000, 10000 + args.holdout))
+    else:
+        gen = lambda s: medium_problem_gpu(int(s), nf=args.nf)     # noqa: E731
+        train_seeds = list(range(5000, 5000 + args.train))
+        hold_seeds = list(range(15000, 15000 + args.holdout))
     log(f"building the training set ({args.train} models)")
-    X, Y, M = build_dataset(train_seeds, args.k, args.T, gen)
+    X, Y, M = build_dataset(train_seeds, args.k, args.T, gen, args.rprec)
     log(f"training set: {X.shape[0]} traces")
-    nval = min(len(hold_seeds), 16)
-    Xv, Yv, Mv = build_dataset(hold_seeds[:nval], args.k, args.T, gen)
+    nval = min(len(hold_seeds), 16 if args.workload == "tail" else 2)
+    Xv, Yv, Mv = build_dataset(hold_seeds[:nval], args.k, args.T, gen, args.rprec)
     params, curve = fit(X, Y, M, args.k, args.T, args.steps, args.batch, args.lr,
                         val=(Xv, Yv, Mv))
     np.savez(args.out, params=params, k=args.k, T=args.T, train_models=args.train, steps=args.steps,
-             curve=json.dumps(curve))
+             workload=args.workload, curve=json.dumps(curve))
     log(f"saved {args.out}")
     del X, Y, M
     torch.cuda.empty_cache()
-    rows = evaluate(params, hold_seeds, args.k, args.T, gen)
+    rows = evaluate(params, hold_seeds, args.k, args.T, gen, args.rprec)
     summary = summarise(rows)
-    report = {"train_models": args.train, "holdout_models": len(hold_seeds), "k": args.k, "T": args.T,
+    report = {"workload": args.workload, "rprec": args.rprec,
+              "train_models": args.train, "holdout_models": len(hold_seeds), "k": args.k, "T": args.T,
               "steps": args.steps, "curve": curve, "summary": summary}
     if args.report:
         with open(args.report, "w") as fh:
