@@ -71,6 +71,9 @@ typedef enum {
 #define MK_FLAG_GRAPH    0x1u  /* replay the per-pass kernels as a HIP graph   */
 #define MK_FLAG_PROFILE  0x2u  /* time every kernel with HIP events            */
 #define MK_FLAG_AUTOTUNE 0x4u  /* time the contraction variants on first use   */
+#define MK_FLAG_FAST_X   0x8u  /* 16-bit R on matrix cores: one 16-bit plane of X
+                                  instead of the default hi + lo planes (half the
+                                  products, about 2x the rounding error)        */
 
 typedef struct {
     int32_t nr;          /* receivers (output positions x_R)                    */

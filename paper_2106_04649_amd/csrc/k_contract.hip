@@ -32,6 +32,13 @@ __device__ __forceinline__ float wave_sum_to63(float v) {
     return v;
 }
 
+// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run
+// of row chunks, so the frequencies (and their X) it touches stay in its L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t per_xcd) {
+    const int64_t b = blockIdx.x;
+    return (b & 7) * per_xcd + (b >> 3);
+}
+
 // (re, im) of one 16-bit complex pair
 template <int PREC>
 __device__ __forceinline__ float2 unpack16(uint32_t u) {
@@ -48,9 +55,9 @@ __device__ __forceinline__ float2 unpack16(uint32_t u) {
 template <int J, int NF>
 __global__ __launch_bounds__(kWaves * 64) void k_contract_c64(
     const v4f* __restrict__ R, const v4f* __restrict__ X, float2* __restrict__ Y,
-    int nr, int n4, int nload4, int64_t nrows, int64_t xstride4, int64_t ystride) {
+    int nr, int n4, int nload4, int64_t nrows, int64_t xstride4, int64_t ystride, int64_t per_xcd) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int64_t wave = xcd_block(per_xcd) * kWaves + (threadIdx.x >> 6);
     const int64_t q0 = wave * kRowsPerWave;
     if (q0 >= nrows) return;
     const int64_t q1 = q0 + kRowsPerWave < nrows ? q0 + kRowsPerWave : nrows;
@@ -120,9 +127,9 @@ template <int J, int NF, int PREC>
 __global__ __launch_bounds__(kWaves * 64) void k_contract_q16(
     const v4u* __restrict__ R, const v4f* __restrict__ X, const float* __restrict__ rscale,
     float2* __restrict__ Y, int nr, int n16, int nload16, int n4, int64_t nrows, int64_t xstride4,
-    int64_t ystride) {
+    int64_t ystride, int64_t per_xcd) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int64_t wave = xcd_block(per_xcd) * kWaves + (threadIdx.x >> 6);
     const int64_t q0 = wave * kRowsPerWave;
     if (q0 >= nrows) return;
     const int64_t q1 = q0 + kRowsPerWave < nrows ? q0 + kRowsPerWave : nrows;
@@ -197,22 +204,24 @@ __global__ __launch_bounds__(kWaves * 64) void k_contract_q16(
 
 template <int J, int NF>
 void launch_one(const ContractArgs& c, const float2* X, float2* Yc, dim3 grid, dim3 block,
-                hipStream_t s) {
+                int64_t per_xcd, hipStream_t s) {
     const int64_t nrows = (int64_t)c.B * c.nr;
     const int64_t xstride4 = (int64_t)c.B * (c.ns_pad / 2);
     const int64_t ystride = (int64_t)c.B * c.nr;
     if (c.prec == MK_R_C64) {
         hipLaunchKernelGGL((k_contract_c64<J, NF>), grid, block, 0, s,
                            reinterpret_cast<const v4f*>(c.R), reinterpret_cast<const v4f*>(X), Yc, c.nr,
-                           c.ns_pad / 2, (c.ns + 1) / 2, nrows, xstride4, ystride);
+                           c.ns_pad / 2, (c.ns + 1) / 2, nrows, xstride4, ystride, per_xcd);
     } else if (c.prec == MK_R_F16S) {
         hipLaunchKernelGGL((k_contract_q16<J, NF, MK_R_F16S>), grid, block, 0, s,
                            reinterpret_cast<const v4u*>(c.R), reinterpret_cast<const v4f*>(X), c.rscale,
-                           Yc, c.nr, c.ns_pad / 4, (c.ns + 3) / 4, c.ns_pad / 2, nrows, xstride4, ystride);
+                           Yc, c.nr, c.ns_pad / 4, (c.ns + 3) / 4, c.ns_pad / 2, nrows, xstride4, ystride,
+                           per_xcd);
     } else {
         hipLaunchKernelGGL((k_contract_q16<J, NF, MK_R_BF16S>), grid, block, 0, s,
                            reinterpret_cast<const v4u*>(c.R), reinterpret_cast<const v4f*>(X), c.rscale,
-                           Yc, c.nr, c.ns_pad / 4, (c.ns + 3) / 4, c.ns_pad / 2, nrows, xstride4, ystride);
+                           Yc, c.nr, c.ns_pad / 4, (c.ns + 3) / 4, c.ns_pad / 2, nrows, xstride4, ystride,
+                           per_xcd);
     }
 }
 
@@ -220,7 +229,9 @@ template <int J>
 hipError_t launch_j(const ContractArgs& c, hipStream_t s) {
     const int64_t nrows = (int64_t)c.B * c.nr;
     const int64_t waves = (nrows + kRowsPerWave - 1) / kRowsPerWave;
-    const dim3 grid((unsigned)((waves + kWaves - 1) / kWaves)), block(kWaves * 64);
+    const int64_t blocks = (waves + kWaves - 1) / kWaves;
+    const int64_t per_xcd = (blocks + 7) / 8;
+    const dim3 grid((unsigned)(8 * per_xcd)), block(kWaves * 64);
     const int64_t xslab = (int64_t)c.B * c.ns_pad;     // complex elements per focal slab
     const int64_t yslab = (int64_t)c.B * c.nr;
     for (int c0 = 0; c0 < c.ncols;) {
@@ -228,13 +239,13 @@ hipError_t launch_j(const ContractArgs& c, hipStream_t s) {
         const float2* X = reinterpret_cast<const float2*>(c.X) + c0 * xslab;
         float2* Yc = c.Y + c0 * yslab;
         if (left >= 4) {
-            launch_one<J, 4>(c, X, Yc, grid, block, s);
+            launch_one<J, 4>(c, X, Yc, grid, block, per_xcd, s);
             c0 += 4;
         } else if (left >= 2) {
-            launch_one<J, 2>(c, X, Yc, grid, block, s);
+            launch_one<J, 2>(c, X, Yc, grid, block, per_xcd, s);
             c0 += 2;
         } else {
-            launch_one<J, 1>(c, X, Yc, grid, block, s);
+            launch_one<J, 1>(c, X, Yc, grid, block, per_xcd, s);
             c0 += 1;
         }
         hipError_t e = hipGetLastError();

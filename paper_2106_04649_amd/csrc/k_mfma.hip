@@ -46,7 +46,7 @@ __device__ __forceinline__ v4u a_row_16(v4u x, int c) {
     return (x >> 16) | (x << 16);
 }
 
-template <int PREC, int WM, int WN>
+template <int PREC, int WM, int WN, bool SPLIT>
 __global__ __launch_bounds__(256) void k_contract_mfma(
     const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
     const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
@@ -133,6 +133,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
         }
         // 16 complex shots per step: lane group g covers shots s + 4g .. s + 4g + 3
         const int nsteps = ns_pad >> 4;
+        const int64_t xlo4 = ((int64_t)nfc * B * ns_pad) >> 2;      // low plane, in 16-byte units
         for (int st = 0; st < nsteps; ++st) {
             const int idx = 4 * st + g;
             v4u av[WM], bv[WN];
@@ -151,6 +152,22 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
                         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                             __builtin_bit_cast(b8, av[a]), __builtin_bit_cast(b8, bv[b]), acc[a][b], 0, 0, 0);
                 }
+            if constexpr (SPLIT) {
+                // the low plane of X: x = hi + lo recovers about twice the 16-bit precision
+#pragma unroll
+                for (int a = 0; a < WM; ++a) av[a] = xok[a] ? a_row_16(Xp[a][idx + xlo4], cfl[a]) : v4u{0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int a = 0; a < WM; ++a)
+#pragma unroll
+                    for (int b = 0; b < WN; ++b) {
+                        if constexpr (PREC == MK_R_F16S)
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                __builtin_bit_cast(h8, av[a]), __builtin_bit_cast(h8, bv[b]), acc[a][b], 0, 0, 0);
+                        else
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(b8, av[a]), __builtin_bit_cast(b8, bv[b]), acc[a][b], 0, 0, 0);
+                    }
+            }
         }
     }
 
@@ -174,27 +191,27 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
     }
 }
 
-template <int PREC, int WM, int WN>
+template <int PREC, int WM, int WN, bool SPLIT>
 hipError_t launch_v(const ContractArgs& c, hipStream_t s) {
     constexpr int FT = 32 * WM, RT = 32 * WN;
     const int ftiles = (2 * c.ncols + FT - 1) / FT;
     const int rtiles = (c.nr + RT - 1) / RT;
     const int64_t ntiles = (int64_t)ftiles * rtiles * c.B;
     const int64_t per_xcd = (ntiles + 7) / 8;
-    hipLaunchKernelGGL((k_contract_mfma<PREC, WM, WN>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_contract_mfma<PREC, WM, WN, SPLIT>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s,
                        c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B, c.ncols,
                        ftiles, rtiles, ntiles, per_xcd);
     return hipGetLastError();
 }
 
-template <int PREC>
+template <int PREC, bool SPLIT>
 hipError_t launch_p(const ContractArgs& c, int variant, hipStream_t s) {
     switch (variant) {
-        case 0: return launch_v<PREC, 4, 2>(c, s);
-        case 1: return launch_v<PREC, 2, 2>(c, s);
-        case 2: return launch_v<PREC, 2, 4>(c, s);
-        case 3: return launch_v<PREC, 1, 4>(c, s);
-        case 4: return launch_v<PREC, 4, 1>(c, s);
+        case 0: return launch_v<PREC, 4, 2, SPLIT>(c, s);
+        case 1: return launch_v<PREC, 2, 2, SPLIT>(c, s);
+        case 2: return launch_v<PREC, 2, 4, SPLIT>(c, s);
+        case 3: return launch_v<PREC, 1, 4, SPLIT>(c, s);
+        case 4: return launch_v<PREC, 4, 1, SPLIT>(c, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -207,9 +224,11 @@ hipError_t launch_contract_mfma(const ContractArgs& c, int variant, hipStream_t 
     if (c.ncols <= 0) return hipSuccess;
     if (c.ns_pad % 16 != 0) return hipErrorInvalidValue;
     switch (c.prec) {
-        case MK_R_C64: return launch_p<MK_R_C64>(c, variant, s);
-        case MK_R_F16S: return launch_p<MK_R_F16S>(c, variant, s);
-        case MK_R_BF16S: return launch_p<MK_R_BF16S>(c, variant, s);
+        case MK_R_C64: return launch_p<MK_R_C64, false>(c, variant, s);
+        case MK_R_F16S:
+            return c.xsplit ? launch_p<MK_R_F16S, true>(c, variant, s) : launch_p<MK_R_F16S, false>(c, variant, s);
+        case MK_R_BF16S:
+            return c.xsplit ? launch_p<MK_R_BF16S, true>(c, variant, s) : launch_p<MK_R_BF16S, false>(c, variant, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -38,8 +38,10 @@ __global__ __launch_bounds__(256) void k_rmax(const float2* __restrict__ in, int
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        // a slice whose largest value is below 2^-100 quantises to zero with unit scale
+        // (its scale would underflow FP32 and make the quotient infinite)
         const float mx = sh[0];
-        rmax[w] = (mx > 0.f && isfinite(mx)) ? mx * (1.0f / 16384.0f) : 1.0f;
+        rmax[w] = (mx >= 0x1p-100f && isfinite(mx)) ? mx * (1.0f / 16384.0f) : 1.0f;
     }
 }
 

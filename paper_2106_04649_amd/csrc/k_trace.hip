@@ -334,23 +334,43 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         // 16-bit X scaled per focal point by the RMS trace norm of the previous field
         const double nrm = a.xs_in ? a.xs_in[f] : 0.0;
         float xs = (float)(nrm / sqrt((double)a.nr));
-        if (!(xs > 0.f) || !isfinite(xs)) xs = 1.f;
+        if (!(xs >= 0x1p-100f) || !isfinite(xs)) xs = 1.f;
         const float inv = 1.f / xs;
         uint32_t* Xt = reinterpret_cast<uint32_t*>(a.X) + xoff;
+        const bool bf = a.xprec == XP_BF16 || a.xprec == XP_BF16X2;
+        const bool split = a.xprec == XP_F16X2 || a.xprec == XP_BF16X2;
+        const size_t lo_off = (size_t)a.nfo * a.B * a.ns_pad;       // second plane
         for (int k = a.lo + lane; k <= kend; k += TPT) {
             float2 v = make_float2(0.f, 0.f);
             if (k >= flo && k <= fhi) v = unpack_bin<NT>(z, a.tw, k);
-            uint32_t u;
-            if (a.xprec == XP_F16) {
-                const _Float16 lo = (_Float16)(v.x * inv), hh = (_Float16)(v.y * inv);
-                u = (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hh) << 16);
+            v.x *= inv;
+            v.y *= inv;
+            uint32_t u, ul = 0;
+            if (!bf) {
+                const _Float16 hx = (_Float16)v.x, hy = (_Float16)v.y;
+                u = (uint32_t)__builtin_bit_cast(uint16_t, hx) | ((uint32_t)__builtin_bit_cast(uint16_t, hy) << 16);
+                if (split) {
+                    const _Float16 lx = (_Float16)(v.x - (float)hx), ly = (_Float16)(v.y - (float)hy);
+                    ul = (uint32_t)__builtin_bit_cast(uint16_t, lx) |
+                         ((uint32_t)__builtin_bit_cast(uint16_t, ly) << 16);
+                }
             } else {
-                uint32_t ux = __float_as_uint(v.x * inv), uy = __float_as_uint(v.y * inv);
-                ux += 0x7FFFu + ((ux >> 16) & 1u);
-                uy += 0x7FFFu + ((uy >> 16) & 1u);
-                u = (ux >> 16) | (uy & 0xFFFF0000u);
+                uint32_t ux = __float_as_uint(v.x), uy = __float_as_uint(v.y);
+                ux = (ux + 0x7FFFu + ((ux >> 16) & 1u)) & 0xFFFF0000u;
+                uy = (uy + 0x7FFFu + ((uy >> 16) & 1u)) & 0xFFFF0000u;
+                u = (ux >> 16) | uy;
+                if (split) {
+                    uint32_t lx = __float_as_uint(v.x - __uint_as_float(ux));
+                    uint32_t ly = __float_as_uint(v.y - __uint_as_float(uy));
+                    lx += 0x7FFFu + ((lx >> 16) & 1u);
+                    ly += 0x7FFFu + ((ly >> 16) & 1u);
+                    ul = (lx >> 16) | (ly & 0xFFFF0000u);
+                }
             }
-            if (valid) Xt[(size_t)(k - a.lo) * a.ns_pad] = u;
+            if (valid) {
+                Xt[(size_t)(k - a.lo) * a.ns_pad] = u;
+                if (split) Xt[lo_off + (size_t)(k - a.lo) * a.ns_pad] = ul;
+            }
         }
         if (valid && r == 0 && lane == 0) a.xs_out[fo] = xs;
     }

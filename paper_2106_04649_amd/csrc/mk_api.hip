@@ -130,10 +130,10 @@ hipError_t prof_resolve(mk_plan_t p) {
 
 constexpr int kGemvMaxCols = 4;
 
-int xprec_of(int rprec, int variant) {
+int xprec_of(int rprec, int variant, bool fast_x = false) {
     if (variant == 0) return XP_F32;                     // GEMV keeps X in FP32
-    if (rprec == MK_R_F16S) return XP_F16;
-    if (rprec == MK_R_BF16S) return XP_BF16;
+    if (rprec == MK_R_F16S) return fast_x ? XP_F16 : XP_F16X2;
+    if (rprec == MK_R_BF16S) return fast_x ? XP_BF16 : XP_BF16X2;
     return XP_F32;
 }
 
@@ -153,6 +153,7 @@ ContractArgs contract_args(mk_plan_t p, const void* X, int ncols, int ncols_mul)
     c.Y = p->Y;
     c.ncols_w = p->has_fband ? p->ncols : nullptr;
     c.ncols_mul = ncols_mul;
+    c.xsplit = 0;
     c.nr = p->d.nr;
     c.ns = p->d.ns;
     c.ns_pad = p->ns_pad;
@@ -161,7 +162,7 @@ ContractArgs contract_args(mk_plan_t p, const void* X, int ncols, int ncols_mul)
     return c;
 }
 
-hipError_t launch_choice(const ContractArgs& c, int variant, hipStream_t s) {
+hipError_t launch_choice(ContractArgs c, int variant, hipStream_t s) {
     if (variant == 0) return launch_contract_gemv(c, s);
     return launch_contract_mfma(c, variant - 1, s);
 }
@@ -193,7 +194,8 @@ mk_status autotune(mk_plan_t p, const void* Xbuf, const float* xs, int ncols, in
             const size_t bar = line.rfind('|');
             if (bar != std::string::npos && line.substr(0, bar) == key) {
                 const int v = std::atoi(line.c_str() + bar + 1);
-                if (v >= 0 && v <= contract_mfma_variants() && xprec_of(p->d.rprec, v) == xprec) {
+                if (v >= 0 && v <= contract_mfma_variants() &&
+                    xprec_of(p->d.rprec, v, (p->d.flags & MK_FLAG_FAST_X) != 0) == xprec) {
                     p->tuned.push_back({ncols, v});
                     *out = v;
                     return MK_OK;
@@ -202,9 +204,10 @@ mk_status autotune(mk_plan_t p, const void* Xbuf, const float* xs, int ncols, in
         }
     }
     std::vector<int> cands;
-    if (xprec_of(p->d.rprec, 0) == xprec && ncols <= 2 * kGemvMaxCols) cands.push_back(0);
+    const bool fast = (p->d.flags & MK_FLAG_FAST_X) != 0;
+    if (xprec_of(p->d.rprec, 0, fast) == xprec && ncols <= 2 * kGemvMaxCols) cands.push_back(0);
     for (int v = 0; v < contract_mfma_variants(); ++v)
-        if (xprec_of(p->d.rprec, 1 + v) == xprec) cands.push_back(1 + v);
+        if (xprec_of(p->d.rprec, 1 + v, fast) == xprec) cands.push_back(1 + v);
     hipEvent_t e0, e1;
     HIP_TRY(p, hipEventCreate(&e0));
     HIP_TRY(p, hipEventCreate(&e1));
@@ -213,6 +216,7 @@ mk_status autotune(mk_plan_t p, const void* Xbuf, const float* xs, int ncols, in
     for (int v : cands) {
         ContractArgs c = contract_args(p, Xbuf, ncols, ncols_mul);
         c.xscale = xs;
+        c.xsplit = (xprec == XP_F16X2 || xprec == XP_BF16X2) ? 1 : 0;
         HIP_TRY(p, launch_choice(c, v, p->stream));     // warm
         HIP_TRY(p, hipEventRecord(e0, p->stream));
         for (int rep = 0; rep < 2; ++rep) HIP_TRY(p, launch_choice(c, v, p->stream));
@@ -240,7 +244,7 @@ mk_status autotune(mk_plan_t p, const void* Xbuf, const float* xs, int ncols, in
 ContractChoice choose(mk_plan_t p, int ncols) {
     ContractChoice ch;
     ch.variant = p->tune_mode >= 0 ? p->tune_mode : heuristic_variant(ncols);
-    ch.xprec = xprec_of(p->d.rprec, ch.variant);
+    ch.xprec = xprec_of(p->d.rprec, ch.variant, (p->d.flags & MK_FLAG_FAST_X) != 0);
     return ch;
 }
 
@@ -284,6 +288,7 @@ mk_status run_contract(mk_plan_t p, const ContractChoice& ch, const void* Xbuf, 
     if (p->tune_mode == -2) MK_TRY(autotune(p, Xbuf, xs, ncols, ncols_mul, ch.xprec, &variant));
     ContractArgs c = contract_args(p, Xbuf, ncols, ncols_mul);
     c.xscale = xs;
+    c.xsplit = (ch.xprec == XP_F16X2 || ch.xprec == XP_BF16X2) ? 1 : 0;
     hipEvent_t ev = nullptr;
     HIP_TRY(p, prof_begin(p, &ev));
     HIP_TRY(p, launch_choice(c, variant, p->stream));
@@ -397,7 +402,7 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
         return fail(nullptr, MK_ERR_ARG, "mk_plan: unknown rprec");
     if (d.rprec == MK_R_C64 && d.ns > 2048)
         return fail(nullptr, MK_ERR_UNSUPPORTED, "mk_plan: complex64 R supports ns <= 2048");
-    if (d.flags & ~(MK_FLAG_GRAPH | MK_FLAG_PROFILE | MK_FLAG_AUTOTUNE))
+    if (d.flags & ~(MK_FLAG_GRAPH | MK_FLAG_PROFILE | MK_FLAG_AUTOTUNE | MK_FLAG_FAST_X))
         return fail(nullptr, MK_ERR_ARG, "mk_plan: unknown flag bits");
 
     mk_plan_t p = new (std::nothrow) mk_plan_s();

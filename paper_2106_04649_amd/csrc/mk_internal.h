@@ -21,8 +21,9 @@ enum TraceMode : int {
     TM_RST2 = 6    // N'' = mute(-RN(-t)); rho = N_-1 + N'' - f1+; f1+ := N_-1 + N''; X = rfft(rho)
 };
 
-// Storage of the contraction input X.
-enum XPrec : int { XP_F32 = 0, XP_F16 = 1, XP_BF16 = 2 };
+// Storage of the contraction input X.  The X2 forms keep a 16-bit "hi" plane
+// and a 16-bit "lo" plane (x ~ hi + lo) for two matrix-core products.
+enum XPrec : int { XP_F32 = 0, XP_F16 = 1, XP_BF16 = 2, XP_F16X2 = 3, XP_BF16X2 = 4 };
 
 // Arguments of the per-trace kernel.  Layouts (all row-major):
 //   Y   [nfo][B][nr]        complex, contraction output (unscaled sum over s)
@@ -171,6 +172,7 @@ struct ContractArgs {
     float2* Y;
     const int* ncols_w;
     int ncols_mul;
+    int xsplit;            // 16-bit X held as hi and lo planes (two products)
     int nr, ns, ns_pad, B, ncols;
 };
 

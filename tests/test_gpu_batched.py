@@ -38,6 +38,16 @@ def test_reduced_precision_R(rprec, variant):
     assert_parity(g, run_oracle(p), tol=TOL[rprec], label=f"prec{rprec}-v{variant}")
 
 
+@pytest.mark.parametrize("rprec", [1, 2])
+def test_single_plane_16bit_X(rprec):
+    """MK_FLAG_FAST_X: one 16-bit plane of X (half the products, about twice the error)."""
+    mk = require_gpu()
+    say(f"fast X rprec {rprec}")
+    p = small_problem(seed=31, n=48, nt=128, nf=20, niter=8)
+    g = run_gpu(p, rprec=rprec, tune=1, flags=mk.MK_FLAG_FAST_X)
+    assert_parity(g, run_oracle(p), tol=2 * TOL[rprec], label=f"fastx{rprec}")
+
+
 @pytest.mark.parametrize("rprec,variant", [(0, 1), (0, 0), (1, 1), (2, 5)])
 def test_per_focal_bands_batched(rprec, variant):
     say(f"bands rprec {rprec} variant {variant}")
