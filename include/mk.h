@@ -172,10 +172,13 @@ mk_status mk_get(mk_plan_t plan, int32_t field, float* out, int on_device);
  * heuristic; -2: autotune (time every variant once per column count at its
  * first use and keep the fastest; with the environment variable
  * MK_TUNE_CACHE naming a file, choices are read from and appended to it);
- * 0: the streaming GEMV; v >= 1: MFMA tile shape v - 1.  The storage of X
- * follows from the choice, so the focal points must be set again after
+ * 0: the streaming GEMV; 1..5: matrix-core tiles loaded straight from
+ * memory (focal-real rows x receivers per block: 128x64, 64x64, 64x128,
+ * 32x128, 128x32); 6..8: matrix-core tiles with X staged through LDS
+ * (128, 64, 32 focal-real rows x 256 receivers per block).  The storage of
+ * X follows from the choice, so the focal points must be set again after
  * this call (MK_ERR_STATE otherwise).
- * Errors: MK_ERR_ARG (null plan, mode outside [-2, 5]).
+ * Errors: MK_ERR_ARG (null plan, mode outside [-2, 8]).
  */
 mk_status mk_tune(mk_plan_t plan, int32_t mode);
 

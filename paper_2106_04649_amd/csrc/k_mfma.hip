@@ -191,6 +191,212 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
     }
 }
 
+// LDS-staged variant for wide focal batches.  A block of 4 waves owns
+// 16*RA focal-real rows (8*RA focal columns) x 256 receivers of one bin;
+// wave v owns all of the block's rows x receivers [64 v, 64 v + 64), that is
+// RA x 4 accumulator tiles.
+//
+// X for the block's focal columns goes through LDS in chunks of kChunk
+// complex shots, double-buffered: chunk c + 1 is loaded into registers when
+// chunk c starts and stored into the other buffer when it ends, one barrier
+// per chunk, so its latency hides behind a whole chunk of matrix-core work.
+//
+// R, the streamed operand, goes straight from memory into registers, each R
+// byte to exactly one wave, PD K steps ahead of its use (a shift register of
+// PD fragments).  The K order is permuted so that a lane's two consecutive
+// K steps read 32 contiguous bytes (lane group g holds bytes [32 g, 32 g + 32)
+// of each 128-byte super-step, K step h of the pair the h-th half; a final
+// lone K step keeps the plain order), and the four lane groups cover whole
+// 128-byte lines; A is read from LDS in the same order, which leaves the sum
+// unchanged.
+constexpr int kChunk = 64;          // complex shots per staged chunk
+constexpr int kLdsRcv = 256;        // receivers per block
+
+template <int PREC, int RA, bool SPLIT, int PD>
+__global__ __launch_bounds__(256, 2) void k_contract_lds(
+    const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
+    const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
+    int ncols_mul, int nr, int ns_pad, int B, int nfc, int ftiles, int rtiles, int64_t ntiles,
+    int64_t per_xcd) {
+    constexpr bool C64 = PREC == MK_R_C64;
+    constexpr int PLANES = SPLIT ? 2 : 1;
+    constexpr int NFB = 8 * RA;                   // focal columns per block
+    constexpr int ROWS = NFB * PLANES;            // staged X rows
+    constexpr int EB = C64 ? 8 : 4;               // bytes per complex element
+    constexpr int ROWB = kChunk * EB + 16;        // padded LDS row: rows 4 banks apart
+    constexpr int KS = C64 ? 8 : 16;              // complex shots per K step (64 bytes of a row)
+    constexpr int SPC = kChunk / KS;              // K steps per full chunk
+    constexpr int VPR = kChunk * EB / 16;         // 16-byte vectors per full chunk row
+    constexpr int NV = (ROWS * VPR + 255) / 256;  // staging vectors per thread per chunk
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2][ROWS * ROWB];
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t bid = blockIdx.x;
+    const int64_t t = (bid & 7) * per_xcd + (bid >> 3);
+    if (t >= ntiles) return;
+    const int ft = (int)(t % ftiles);
+    const int64_t t2 = t / ftiles;
+    const int rt = (int)(t2 % rtiles);
+    const int w = (int)(t2 / rtiles);
+    const int nact = ncols_w ? min(ncols_w[w] * ncols_mul, nfc) : nfc;
+    const int fbase = ft * NFB;
+    if (fbase >= nact) return;                    // uniform over the block
+
+    const int i16 = lane & 15, g = lane >> 4;
+    const int r0 = rt * kLdsRcv + wv * 64;
+    const bool active = r0 < nr;                  // waves past nr only help stage X
+    const int nsteps = ns_pad / KS;
+    const int nch = (ns_pad + kChunk - 1) / kChunk;
+    const int64_t lo_bytes = (int64_t)nfc * B * ns_pad * EB;
+    const bool odd = (nsteps & 1) != 0;
+
+    // byte offset of this lane's 16 bytes of K step st inside a row (or a chunk row)
+    auto koff = [&](int st, bool lone) { return (st >> 1) * 128 + (lone ? g * 16 : g * 32 + (st & 1) * 16); };
+
+    // ---- X staging: chunk c -> registers -> LDS buffer -------------------
+    v4u xr[NV];
+    auto stage_load = [&](int c) {
+        const int sb = c * kChunk;
+        const int vpr = (min(kChunk, ns_pad - sb) * EB) >> 4;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int v = threadIdx.x + 256 * i;
+            const int row = v / VPR, col = v % VPR;
+            const int f = fbase + row % NFB;
+            xr[i] = v4u{0u, 0u, 0u, 0u};
+            if (row < ROWS && col < vpr && f < nact)
+                xr[i] = *reinterpret_cast<const v4u*>(reinterpret_cast<const unsigned char*>(Xv) +
+                                                      (row / NFB) * lo_bytes +
+                                                      (((int64_t)f * B + w) * ns_pad + sb) * EB + col * 16);
+        }
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int v = threadIdx.x + 256 * i;
+            const int row = v / VPR, col = v % VPR;
+            if (row < ROWS) *reinterpret_cast<v4u*>(&lds[buf][row * ROWB + col * 16]) = xr[i];
+        }
+    };
+
+    // ---- R rows of this wave ----------------------------------------------
+    const unsigned char* Rrow[4];
+    bool rok[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int r = r0 + 16 * b + i16;
+        rok[b] = active && r < nr;
+        Rrow[b] = reinterpret_cast<const unsigned char*>(Rv) + ((int64_t)w * nr + (rok[b] ? r : 0)) * ns_pad * EB;
+    }
+    auto load_b = [&](int st, v4u (&bv)[4]) {
+        const int off = koff(st, odd && st == nsteps - 1);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            bv[b] = rok[b] ? *reinterpret_cast<const v4u*>(Rrow[b] + off) : v4u{0u, 0u, 0u, 0u};
+    };
+
+    v4f acc[RA][4];
+#pragma unroll
+    for (int a = 0; a < RA; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    // one K step: A from LDS (row pair 8a + i16/2 of buffer buf at byte offset off), B from bv
+    auto kstep = [&](const unsigned char* buf, int off, const v4u (&bv)[4]) {
+        const int c = i16 & 1;
+#pragma unroll
+        for (int a = 0; a < RA; ++a) {
+            const int rl = 8 * a + (i16 >> 1);
+            const v4u xa = *reinterpret_cast<const v4u*>(buf + rl * ROWB + off);
+            if constexpr (C64) {
+                const v4f av = a_row_f32(__builtin_bit_cast(v4f, xa), c);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            av[e], __builtin_bit_cast(v4f, bv[b])[e], acc[a][b], 0, 0, 0);
+            } else {
+                v4u av[PLANES];
+                av[0] = a_row_16(xa, c);
+                if constexpr (SPLIT)
+                    av[1] = a_row_16(*reinterpret_cast<const v4u*>(buf + (NFB + rl) * ROWB + off), c);
+#pragma unroll
+                for (int pl = 0; pl < PLANES; ++pl)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        if constexpr (PREC == MK_R_F16S)
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                __builtin_bit_cast(h8, av[pl]), __builtin_bit_cast(h8, bv[b]), acc[a][b], 0, 0, 0);
+                        else
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(b8, av[pl]), __builtin_bit_cast(b8, bv[b]), acc[a][b], 0, 0, 0);
+                    }
+            }
+        }
+    };
+
+    stage_load(0);
+    stage_store(0);
+    v4u bq[PD][4];                                  // bq[0]: this K step; bq[p]: p steps ahead
+#pragma unroll
+    for (int p = 0; p < PD; ++p)
+        if (p < nsteps) load_b(p, bq[p]);
+    __syncthreads();
+    int c = 0, j = 0;                               // chunk, K step within the chunk
+    for (int st = 0; st < nsteps; ++st) {
+        if (j == 0 && c + 1 < nch) stage_load(c + 1);
+        if (active) kstep(lds[c & 1], koff(j, odd && st == nsteps - 1), bq[0]);
+#pragma unroll
+        for (int p = 0; p + 1 < PD; ++p)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bq[p][b] = bq[p + 1][b];
+        if (st + PD < nsteps) load_b(st + PD, bq[PD - 1]);
+        if (++j == SPC || st + 1 == nsteps) {       // end of chunk c
+            if (c + 1 < nch) {
+                stage_store((c + 1) & 1);
+                __syncthreads();
+            }
+            ++c;
+            j = 0;
+        }
+    }
+    if (!active) return;
+
+    // D rows 16a + 4g + v (v = 0..3) are (Re, Im) of focal fbase + 8a + 2g and the next one
+    const float rs = C64 ? 1.f : rscale[w];
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+        const int f0 = fbase + 8 * a + 2 * g;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int r = r0 + 16 * b + i16;
+            if (r >= nr) continue;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int f = f0 + h;
+                if (f >= nact) continue;
+                const float sc = C64 ? 1.f : rs * xscale[f];
+                Y[((int64_t)f * B + w) * nr + r] = make_float2(acc[a][b][2 * h] * sc, acc[a][b][2 * h + 1] * sc);
+            }
+        }
+    }
+}
+
+template <int PREC, int RA, bool SPLIT, int PD>
+hipError_t launch_l(const ContractArgs& c, hipStream_t s) {
+    constexpr int NFB = 8 * RA;
+    const int ftiles = (c.ncols + NFB - 1) / NFB;
+    const int rtiles = (c.nr + kLdsRcv - 1) / kLdsRcv;
+    const int64_t ntiles = (int64_t)ftiles * rtiles * c.B;
+    const int64_t per_xcd = (ntiles + 7) / 8;
+    hipLaunchKernelGGL((k_contract_lds<PREC, RA, SPLIT, PD>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s,
+                       c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B, c.ncols,
+                       ftiles, rtiles, ntiles, per_xcd);
+    return hipGetLastError();
+}
+
 template <int PREC, int WM, int WN, bool SPLIT>
 hipError_t launch_v(const ContractArgs& c, hipStream_t s) {
     constexpr int FT = 32 * WM, RT = 32 * WN;
@@ -212,13 +418,16 @@ hipError_t launch_p(const ContractArgs& c, int variant, hipStream_t s) {
         case 2: return launch_v<PREC, 2, 4, SPLIT>(c, s);
         case 3: return launch_v<PREC, 1, 4, SPLIT>(c, s);
         case 4: return launch_v<PREC, 4, 1, SPLIT>(c, s);
+        case 5: return launch_l<PREC, 8, SPLIT, 2>(c, s);
+        case 6: return launch_l<PREC, 4, SPLIT, 4>(c, s);
+        case 7: return launch_l<PREC, 2, SPLIT, 4>(c, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-int contract_mfma_variants() { return 5; }
+int contract_mfma_variants() { return 8; }
 
 hipError_t launch_contract_mfma(const ContractArgs& c, int variant, hipStream_t s) {
     if (c.ncols <= 0) return hipSuccess;

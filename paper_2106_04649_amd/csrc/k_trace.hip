@@ -30,10 +30,23 @@ __device__ __forceinline__ float2 twid(const float2* __restrict__ tw, int idx) {
     return t;
 }
 
+// Barrier among the threads that own one trace: the whole block, or one
+// wave, whose lanes run in lockstep and whose LDS accesses complete in
+// issue order, so that only the compiler has to be kept from reordering.
+template <int TPT>
+__device__ __forceinline__ void trace_sync() {
+    if constexpr (TPT > 64) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // In-place complex transform of M = NT/2 points held in LDS by the TPT
 // threads that own one trace (one wave, or the whole block).
 // DIR = -1: forward (exp(-i...)), DIR = +1: inverse, both unnormalised.
-// Barriers are block-wide; every thread of the block calls this with the same NT.
 template <int NT, int DIR, int TPT>
 __device__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
     constexpr int M = NT / 2;
@@ -54,7 +67,7 @@ __device__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
                 for (int q = 0; q < 4; ++q) v[p][q] = z[j + q * Q];
             }
         }
-        __syncthreads();
+        trace_sync<TPT>();
 #pragma unroll
         for (int p = 0; p < PER4; ++p) {
             const int j = lane + TPT * p;
@@ -84,7 +97,7 @@ __device__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
                 z[idxD + 3 * Ns] = y3;
             }
         }
-        __syncthreads();
+        trace_sync<TPT>();
     }
     if constexpr ((LOG2M & 1) != 0) {
         constexpr int H = M / 2;
@@ -100,7 +113,7 @@ __device__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
                 v[p][1] = z[j + H];
             }
         }
-        __syncthreads();
+        trace_sync<TPT>();
 #pragma unroll
         for (int p = 0; p < PER2; ++p) {
             const int j = lane + TPT * p;
@@ -113,7 +126,7 @@ __device__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
                 z[idxD + Ns] = make_float2(a0.x - a1.x, a0.y - a1.y);
             }
         }
-        __syncthreads();
+        trace_sync<TPT>();
     }
 }
 
@@ -150,8 +163,14 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     const int lane = threadIdx.x % TPT;     // thread within the trace
     float2* z = lds + wv * M;
 
+    // blocks are dealt to the 8 XCDs in contiguous runs, so that neighbouring
+    // receivers (which share cache lines of Y and X) meet in one L2
     const int ntr = a.nfo * a.nr;
-    int trace = blockIdx.x * TPB + wv;
+    const int nblk = (ntr + TPB - 1) / TPB;
+    const int per_xcd = (nblk + 7) >> 3;
+    const int blk = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    if (blk >= nblk) return;                // uniform over the block
+    int trace = blk * TPB + wv;
     const bool valid = trace < ntr;
     if (!valid) trace = ntr - 1;            // keep the wave in the barriers, store nothing
     const int fo = trace / a.nr;            // output column
@@ -169,19 +188,35 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     // ---- spectrum -> time (TM_ITER, TM_GOUT) --------------------------------
     if (MODE == TM_ITER || MODE == TM_GOUT || MODE == TM_RST1 || MODE == TM_RST2) {
         const float2* Yt = a.Y + (size_t)fo * a.B * a.nr + r;
+        auto ybin = [&](int k) {
+            return (k >= flo && k <= fhi) ? Yt[(size_t)(k - a.lo) * a.nr] : make_float2(0.f, 0.f);
+        };
+        // every stored bin is read once: slot k holds bin k, slot 0 the real
+        // parts of DC and Nyquist (both real: their imaginary parts are dropped)
         for (int k = lane; k < M; k += TPT) {
-            const int km = M - k;
-            float2 xk = make_float2(0.f, 0.f), xm = make_float2(0.f, 0.f);
-            if (k >= flo && k <= fhi) xk = Yt[(size_t)(k - a.lo) * a.nr];
-            if (km >= flo && km <= fhi) xm = Yt[(size_t)(km - a.lo) * a.nr];
-            if (k == 0) { xk.y = 0.f; xm.y = 0.f; }          // DC and Nyquist are real
+            float2 v = ybin(k);
+            if (k == 0) v.y = ybin(M).x;
+            z[k] = v;
+        }
+        trace_sync<TPT>();
+        // packed spectrum Z[k] = E[k] + i O[k] of the even/odd samples, from
+        // bins k and M - k; each thread rewrites its own pair in place
+        auto pack = [](float2 xk, float2 xm, float2 t) {
             const float2 e = make_float2(0.5f * (xk.x + xm.x), 0.5f * (xk.y - xm.y));
             const float2 d = make_float2(0.5f * (xk.x - xm.x), 0.5f * (xk.y + xm.y));
-            const float2 t = a.tw[k];
             const float2 o = make_float2(d.x * t.x + d.y * t.y, d.y * t.x - d.x * t.y);   // d * conj(W^k)
-            z[k] = make_float2(e.x - o.y, e.y + o.x);                                      // E + i O
+            return make_float2(e.x - o.y, e.y + o.x);
+        };
+        for (int k = lane; k <= M / 2; k += TPT) {
+            const float2 zk = z[k], zm = z[(M - k) & (M - 1)];
+            if (k == 0) {
+                z[0] = pack(make_float2(zk.x, 0.f), make_float2(zk.y, 0.f), a.tw[0]);
+            } else {
+                z[k] = pack(zk, zm, a.tw[k]);
+                if (k != M - k) z[M - k] = pack(zm, zk, a.tw[M - k]);
+            }
         }
-        __syncthreads();
+        trace_sync<TPT>();
         fft_lds<NT, +1, TPT>(z, a.tw, lane);
         // z[m] = (RN[2m], RN[2m+1]) / s
     }
@@ -249,7 +284,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
                 }
             }
         }
-        __syncthreads();
+        trace_sync<TPT>();
 #pragma unroll
         for (int p = 0; p < PM; ++p) {
             const int m = lane + TPT * p;
@@ -319,7 +354,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     }
 
     // ---- time -> spectrum (TM_INIT, TM_ITER, TM_GFWD) ---------------------
-    __syncthreads();
+    trace_sync<TPT>();
     fft_lds<NT, -1, TPT>(z, a.tw, lane);
     const int kend = a.skip_outband ? fhi : hi;
     const size_t xoff = (size_t)fo * a.B * a.ns_pad + r;
@@ -432,7 +467,8 @@ template <int NT, int TPT>
 hipError_t launch_trace_tpt(int mode, const TraceArgs& a, hipStream_t s) {
     const int ntr = a.nfo * a.nr;
     constexpr int TPB = 256 / TPT;
-    const dim3 grid((ntr + TPB - 1) / TPB), block(256);
+    const int nblk = (ntr + TPB - 1) / TPB;
+    const dim3 grid(8 * ((nblk + 7) / 8)), block(256);
     switch (mode) {
         case TM_INIT: hipLaunchKernelGGL((k_trace<NT, TM_INIT, TPT>), grid, block, 0, s, a); break;
         case TM_ITER: hipLaunchKernelGGL((k_trace<NT, TM_ITER, TPT>), grid, block, 0, s, a); break;

@@ -140,8 +140,8 @@ int xprec_of(int rprec, int variant, bool fast_x = false) {
 int heuristic_variant(int ncols) {
     if (ncols <= kGemvMaxCols) return 0;
     if (ncols <= 16) return 1 + 3;       // 32 focal-real rows x 128 receivers
-    if (ncols <= 32) return 1 + 1;       // 64 x 64
-    return 1 + 0;                        // 128 x 64
+    if (ncols <= 32) return 1 + 6;       // LDS-staged, 64 focal-real rows x 256 receivers
+    return 1 + 5;                        // LDS-staged, 128 x 256
 }
 
 ContractArgs contract_args(mk_plan_t p, const void* X, int ncols, int ncols_mul) {

@@ -19,8 +19,8 @@ pytestmark = pytest.mark.gpu
 TOL = {0: TOL_FP32, 1: 1e-3, 2: 1e-2}
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
-@pytest.mark.parametrize("n,nt,nf", [(70, 64, 6), (37, 128, 40)])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("n,nt,nf", [(70, 64, 6), (37, 128, 40), (300, 32, 20)])
 def test_every_contraction_variant_fp32(variant, n, nt, nf):
     say(f"variant {variant} n={n} nt={nt} nf={nf}")
     p = small_problem(seed=20 + nf, n=n, nt=nt, nf=nf, niter=6)
@@ -30,7 +30,7 @@ def test_every_contraction_variant_fp32(variant, n, nt, nf):
 
 
 @pytest.mark.parametrize("rprec", [1, 2])
-@pytest.mark.parametrize("variant", [0, 1, 4])
+@pytest.mark.parametrize("variant", [0, 1, 4, 6, 7, 8])
 def test_reduced_precision_R(rprec, variant):
     say(f"rprec {rprec} variant {variant}")
     p = small_problem(seed=31, n=48, nt=128, nf=20, niter=8)
@@ -39,16 +39,17 @@ def test_reduced_precision_R(rprec, variant):
 
 
 @pytest.mark.parametrize("rprec", [1, 2])
-def test_single_plane_16bit_X(rprec):
+@pytest.mark.parametrize("variant", [1, 6])
+def test_single_plane_16bit_X(rprec, variant):
     """MK_FLAG_FAST_X: one 16-bit plane of X (half the products, about twice the error)."""
     mk = require_gpu()
-    say(f"fast X rprec {rprec}")
+    say(f"fast X rprec {rprec} variant {variant}")
     p = small_problem(seed=31, n=48, nt=128, nf=20, niter=8)
-    g = run_gpu(p, rprec=rprec, tune=1, flags=mk.MK_FLAG_FAST_X)
-    assert_parity(g, run_oracle(p), tol=2 * TOL[rprec], label=f"fastx{rprec}")
+    g = run_gpu(p, rprec=rprec, tune=variant, flags=mk.MK_FLAG_FAST_X)
+    assert_parity(g, run_oracle(p), tol=2 * TOL[rprec], label=f"fastx{rprec}-v{variant}")
 
 
-@pytest.mark.parametrize("rprec,variant", [(0, 1), (0, 0), (1, 1), (2, 5)])
+@pytest.mark.parametrize("rprec,variant", [(0, 1), (0, 0), (1, 1), (2, 5), (0, 6), (1, 6), (2, 8)])
 def test_per_focal_bands_batched(rprec, variant):
     say(f"bands rprec {rprec} variant {variant}")
     p = small_problem(seed=41, n=50, nt=128, nf=24, niter=6)
@@ -66,7 +67,7 @@ def test_autotuner_choice_passes_parity(tmp_path, monkeypatch):
     monkeypatch.setenv("MK_TUNE_CACHE", str(tmp_path / "tune.txt"))
     p = small_problem(seed=51, n=64, nt=128, nf=12, niter=5)
     g = run_gpu(p, flags=mk.MK_FLAG_AUTOTUNE)
-    assert 0 <= g["variant"] <= 5
+    assert 0 <= g["variant"] <= 8
     assert_parity(g, run_oracle(p), label="autotune")
     text = (tmp_path / "tune.txt").read_text()
     assert "ncols=12" in text and "ncols=24" in text
@@ -86,3 +87,9 @@ def test_medium_focal_line_batched():
     assert_parity(g, r, label="medium64-fp32")
     g16 = run_gpu(p, niter=2, rprec=1)
     assert_parity(g16, r, tol=1e-3, label="medium64-fp16")
+    for v in (6, 1):                                  # both matrix-core kernel families at full size
+        gv = run_gpu(p, niter=2, rprec=1, tune=v)
+        assert gv["variant"] == v
+        assert_parity(gv, r, tol=1e-3, label=f"medium64-fp16-v{v}")
+    g32 = run_gpu(p, niter=2, tune=6)
+    assert_parity(g32, r, label="medium64-fp32-v6")
