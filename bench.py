@@ -178,11 +178,11 @@ class Runner:
         self.mk.mk_destroy(self.plan)
 
 
-def profile_contract(p, rprec, tune=None):
+def profile_contract(p, rprec, tune=None, flags=0):
     """Average duration of the per-pass contraction kernel from HIP events."""
     from paper_2106_04649_amd import mk
 
-    r = Runner(p, rprec=rprec, flags=mk.MK_FLAG_PROFILE, tune=tune)
+    r = Runner(p, rprec=rprec, flags=mk.MK_FLAG_PROFILE | flags, tune=tune)
     r.step()
     for kind in mk.KERNEL_KINDS:
         mk.mk_profile(r.plan, kind, reset=True)

@@ -74,6 +74,11 @@ typedef enum {
 #define MK_FLAG_FAST_X   0x8u  /* 16-bit R on matrix cores: one 16-bit plane of X
                                   instead of the default hi + lo planes (half the
                                   products, about 2x the rounding error)        */
+#define MK_FLAG_ROW_R    0x10u /* keep R frequency-major and row-major even when
+                                  nf_max > 4 (by default such plans store R in
+                                  the tiles of the LDS-staged matrix-core
+                                  contraction, variants 6..8, the only ones that
+                                  read that layout)                             */
 
 typedef struct {
     int32_t nr;          /* receivers (output positions x_R)                    */
@@ -175,10 +180,12 @@ mk_status mk_get(mk_plan_t plan, int32_t field, float* out, int on_device);
  * 0: the streaming GEMV; 1..5: matrix-core tiles loaded straight from
  * memory (focal-real rows x receivers per block: 128x64, 64x64, 64x128,
  * 32x128, 128x32); 6..8: matrix-core tiles with X staged through LDS
- * (128, 64, 32 focal-real rows x 256 receivers per block).  The storage of
- * X follows from the choice, so the focal points must be set again after
- * this call (MK_ERR_STATE otherwise).
- * Errors: MK_ERR_ARG (null plan, mode outside [-2, 8]).
+ * (128, 64, 32 focal-real rows x 256 receivers per block).  Plans with
+ * nf_max > 4 store R tiled for variants 6..8 (unless MK_FLAG_ROW_R) and
+ * accept only those.  The storage of X follows from the choice, so the
+ * focal points must be set again after this call (MK_ERR_STATE otherwise).
+ * Errors: MK_ERR_ARG (null plan, mode outside [-2, 8], or a variant that
+ * cannot read the plan's layout of R).
  */
 mk_status mk_tune(mk_plan_t plan, int32_t mode);
 

@@ -26,6 +26,8 @@
 // reuse one R tile run on the same XCD and hit its L2.  Bins whose active
 // focal count (uneven per-focal bands, focal points sorted by band end)
 // ends before a tile skip it.
+#include <type_traits>
+
 #include "mk_internal.h"
 
 namespace {
@@ -40,10 +42,38 @@ __device__ __forceinline__ v4f a_row_f32(v4f x, int c) {
     return c == 0 ? v4f{x.x, -x.y, x.z, -x.w} : v4f{x.y, x.x, x.w, x.z};
 }
 
+// Block barrier that orders LDS only: global loads in flight (prefetches)
+// stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ v4u a_row_16(v4u x, int c) {
     // each 32-bit word is (Re | Im << 16); c = 0: (Re, -Im); c = 1: (Im, Re)
     if (c == 0) return x ^ v4u{0x80000000u, 0x80000000u, 0x80000000u, 0x80000000u};
     return (x >> 16) | (x << 16);
+}
+
+// Branch-free form of a_row_16 for a lane-dependent c: rotate each word by
+// rot = 16 c and flip bit 31 when c = 0 (sgn = 0x80000000 (1 - c)).
+__device__ __forceinline__ v4u a_row_16_sel(v4u x, uint32_t rot, uint32_t sgn) {
+    v4u r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = __builtin_amdgcn_alignbit(x[e], x[e], rot) ^ sgn;
+    return r;
+}
+
+// Branch-free form of a_row_f32: c = 1 swaps each pair, c = 0 negates the odd entries.
+__device__ __forceinline__ v4f a_row_f32_sel(v4f x, bool c) {
+    const uint32_t sgn = c ? 0u : 0x80000000u;
+    v4f r;
+    r[0] = c ? x[1] : x[0];
+    r[1] = __uint_as_float(__float_as_uint(c ? x[0] : x[1]) ^ sgn);
+    r[2] = c ? x[3] : x[2];
+    r[3] = __uint_as_float(__float_as_uint(c ? x[2] : x[3]) ^ sgn);
+    return r;
 }
 
 template <int PREC, int WM, int WN, bool SPLIT>
@@ -196,24 +226,51 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
 // wave v owns all of the block's rows x receivers [64 v, 64 v + 64), that is
 // RA x 4 accumulator tiles.
 //
-// X for the block's focal columns goes through LDS in chunks of kChunk
-// complex shots, double-buffered: chunk c + 1 is loaded into registers when
-// chunk c starts and stored into the other buffer when it ends, one barrier
-// per chunk, so its latency hides behind a whole chunk of matrix-core work.
+// The shot axis is cut into chunks of 128 bytes of every row (32 complex
+// shots in 16 bits, 16 in complex64), two matrix-core K steps each.  At the
+// top of chunk c every wave issues its loads for chunk c + 2 -- its share of
+// the X slice (into registers, stored into LDS at the end of chunk c + 1)
+// and its own R fragments -- and only then runs chunk c's K steps; a barrier
+// that orders LDS only closes the chunk, so loads stay in flight across it
+// and each wave keeps two chunks of R in flight.  Three LDS buffers and three
+// register sets rotate with the chunk index; the chunk loop is unrolled by
+// three so that they rotate by name: no load is conditional or copied while
+// in flight, which keeps the compiler's wait counts exact.  Rows are whole
+// chunks: ns_pad is a multiple of 32 shots.
 //
-// R, the streamed operand, goes straight from memory into registers, each R
-// byte to exactly one wave, PD K steps ahead of its use (a shift register of
-// PD fragments).  The K order is permuted so that a lane's two consecutive
-// K steps read 32 contiguous bytes (lane group g holds bytes [32 g, 32 g + 32)
-// of each 128-byte super-step, K step h of the pair the h-th half; a final
-// lone K step keeps the plain order), and the four lane groups cover whole
-// 128-byte lines; A is read from LDS in the same order, which leaves the sum
-// unchanged.
-constexpr int kChunk = 64;          // complex shots per staged chunk
+// X is stored into LDS in both forms of the real embedding, (Re, -Im) and
+// (Im, Re), so a lane reads its A fragment ready to use; the 16 lanes of a
+// fragment read 16 different rows, 36 banks apart, without conflicts.
+//
+// Within a chunk the K order is permuted: lane group g holds bytes
+// [32 g, 32 g + 32) of the 128, K step h the h-th half, so that the four lane
+// groups read whole 128-byte lines of R; A is read from LDS in the same
+// order, which leaves the sum unchanged.
+//
+// Loads are unconditional: a receiver row past nr reads row nr - 1 and a
+// focal row past the active count reads the last active one.  Those values
+// only reach output columns or rows that are never stored (the product's
+// columns and rows are independent), so no masking or branching is needed
+// and every address stays inside the buffers.
+constexpr int kChunkBytes = 128;    // bytes of every row per chunk
 constexpr int kLdsRcv = 256;        // receivers per block
 
-template <int PREC, int RA, bool SPLIT, int PD>
-__global__ __launch_bounds__(256, 2) void k_contract_lds(
+// both embedding forms of a 16-byte X vector: form 0 (Re, -Im), form 1 (Im, Re)
+template <bool C64>
+__device__ __forceinline__ void x_forms(v4u x, v4u& f0, v4u& f1) {
+    if constexpr (C64) {        // two complex64 values (Re0, Im0, Re1, Im1)
+        f0 = v4u{x[0], x[1] ^ 0x80000000u, x[2], x[3] ^ 0x80000000u};
+        f1 = v4u{x[1], x[0], x[3], x[2]};
+    } else {                    // four (Re | Im << 16) words
+        f0 = x ^ v4u{0x80000000u, 0x80000000u, 0x80000000u, 0x80000000u};
+        f1 = (x >> 16) | (x << 16);
+    }
+}
+
+// RA = 8 needs more than half the register file (one wave per SIMD);
+// smaller tiles run two waves per SIMD.
+template <int PREC, int RA, bool SPLIT, bool TILED>
+__global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
     const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
     const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
     int ncols_mul, int nr, int ns_pad, int B, int nfc, int ftiles, int rtiles, int64_t ntiles,
@@ -221,14 +278,16 @@ __global__ __launch_bounds__(256, 2) void k_contract_lds(
     constexpr bool C64 = PREC == MK_R_C64;
     constexpr int PLANES = SPLIT ? 2 : 1;
     constexpr int NFB = 8 * RA;                   // focal columns per block
-    constexpr int ROWS = NFB * PLANES;            // staged X rows
+    constexpr int ROWS = NFB * PLANES;            // staged X rows (one form)
     constexpr int EB = C64 ? 8 : 4;               // bytes per complex element
-    constexpr int ROWB = kChunk * EB + 16;        // padded LDS row: rows 4 banks apart
-    constexpr int KS = C64 ? 8 : 16;              // complex shots per K step (64 bytes of a row)
-    constexpr int SPC = kChunk / KS;              // K steps per full chunk
-    constexpr int VPR = kChunk * EB / 16;         // 16-byte vectors per full chunk row
-    constexpr int NV = (ROWS * VPR + 255) / 256;  // staging vectors per thread per chunk
-    __shared__ __attribute__((aligned(16))) unsigned char lds[2][ROWS * ROWB];
+    constexpr int CB = kChunkBytes;
+    constexpr int ROWB = CB + 16;                 // padded LDS row: rows 36 banks apart
+    constexpr int BUFB = 2 * ROWS * ROWB;         // one buffer: both forms of every row
+    constexpr int VPR = CB / 16;                  // 16-byte vectors per chunk row
+    constexpr int NVEC = ROWS * VPR;              // staging vectors per chunk
+    constexpr int NV = (NVEC + 255) / 256;        // per thread
+    static_assert(NVEC % 256 == 0 || NVEC < 256, "staging vectors fill whole sweeps");
+    __shared__ __attribute__((aligned(16))) unsigned char lds[3 * BUFB];
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -245,55 +304,59 @@ __global__ __launch_bounds__(256, 2) void k_contract_lds(
 
     const int i16 = lane & 15, g = lane >> 4;
     const int r0 = rt * kLdsRcv + wv * 64;
-    const bool active = r0 < nr;                  // waves past nr only help stage X
-    const int nsteps = ns_pad / KS;
-    const int nch = (ns_pad + kChunk - 1) / kChunk;
-    const int64_t lo_bytes = (int64_t)nfc * B * ns_pad * EB;
-    const bool odd = (nsteps & 1) != 0;
+    const int rowbytes = ns_pad * EB;
+    const int nch = rowbytes / CB;                // rows are whole chunks (checked at launch)
+    const int64_t lo_bytes = (int64_t)nfc * B * rowbytes;
 
-    // byte offset of this lane's 16 bytes of K step st inside a row (or a chunk row)
-    auto koff = [&](int st, bool lone) { return (st >> 1) * 128 + (lone ? g * 16 : g * 32 + (st & 1) * 16); };
-
-    // ---- X staging: chunk c -> registers -> LDS buffer -------------------
-    v4u xr[NV];
-    auto stage_load = [&](int c) {
-        const int sb = c * kChunk;
-        const int vpr = (min(kChunk, ns_pad - sb) * EB) >> 4;
+    // ---- X staging: chunk c -> registers -> LDS buffer (both forms) --------
+    auto stage_load = [&](int c, v4u (&xr)[NV]) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const int v = threadIdx.x + 256 * i;
+            const int v = min((int)threadIdx.x + 256 * i, NVEC - 1);   // extra threads repeat the last vector
             const int row = v / VPR, col = v % VPR;
-            const int f = fbase + row % NFB;
-            xr[i] = v4u{0u, 0u, 0u, 0u};
-            if (row < ROWS && col < vpr && f < nact)
-                xr[i] = *reinterpret_cast<const v4u*>(reinterpret_cast<const unsigned char*>(Xv) +
-                                                      (row / NFB) * lo_bytes +
-                                                      (((int64_t)f * B + w) * ns_pad + sb) * EB + col * 16);
+            const int f = min(fbase + row % NFB, nact - 1);
+            xr[i] = *reinterpret_cast<const v4u*>(reinterpret_cast<const unsigned char*>(Xv) + (row / NFB) * lo_bytes +
+                                                  ((int64_t)f * B + w) * rowbytes + c * CB + col * 16);
         }
     };
-    auto stage_store = [&](int buf) {
+    // staged row `row` (plane row / NFB, focal row % NFB) -> LDS rows 2 row (form 0), 2 row + 1 (form 1)
+    auto stage_store = [&](int buf, const v4u (&xr)[NV]) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const int v = threadIdx.x + 256 * i;
+            const int v = min((int)threadIdx.x + 256 * i, NVEC - 1);   // same value, same place
             const int row = v / VPR, col = v % VPR;
-            if (row < ROWS) *reinterpret_cast<v4u*>(&lds[buf][row * ROWB + col * 16]) = xr[i];
+            v4u f0, f1;
+            x_forms<C64>(xr[i], f0, f1);
+            unsigned char* d = lds + buf * BUFB + (2 * row) * ROWB + col * 16;
+            *reinterpret_cast<v4u*>(d) = f0;
+            *reinterpret_cast<v4u*>(d + ROWB) = f1;
         }
     };
 
-    // ---- R rows of this wave ----------------------------------------------
-    const unsigned char* Rrow[4];
-    bool rok[4];
+    // ---- R fragments of this wave: 32-bit offsets from the bin's slab ------
+    // Row-major R: receiver row min(r, nr - 1), bytes c*128 + 32 g + 16 h.
+    // Tiled R: 16-receiver group min(r0 / 16 + b, ng - 1), tile c, half h --
+    // the same bytes, each wave load one contiguous kilobyte.
+    const int lane_off = g * 32;
+    const int ng = (nr + kTileRows - 1) / kTileRows;
+    const unsigned char* Rw = reinterpret_cast<const unsigned char*>(Rv) +
+                              (TILED ? (int64_t)w * ng * nch * 2048 : (int64_t)w * nr * rowbytes);
+    uint32_t ro[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        const int r = r0 + 16 * b + i16;
-        rok[b] = active && r < nr;
-        Rrow[b] = reinterpret_cast<const unsigned char*>(Rv) + ((int64_t)w * nr + (rok[b] ? r : 0)) * ns_pad * EB;
+        if constexpr (TILED)
+            ro[b] = (uint32_t)min(r0 / kTileRows + b, ng - 1) * (uint32_t)(nch * 2048) + (uint32_t)lane * 16u;
+        else
+            ro[b] = (uint32_t)min(r0 + 16 * b + i16, nr - 1) * (uint32_t)rowbytes + (uint32_t)lane_off;
     }
-    auto load_b = [&](int st, v4u (&bv)[4]) {
-        const int off = koff(st, odd && st == nsteps - 1);
+    // both K steps of chunk c
+    auto load_chunk = [&](int c, v4u (&bv)[2][4]) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-            bv[b] = rok[b] ? *reinterpret_cast<const v4u*>(Rrow[b] + off) : v4u{0u, 0u, 0u, 0u};
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t off = TILED ? (uint32_t)(c * 2048 + h * 1024) : (uint32_t)(c * CB + 16 * h);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[h][b] = *reinterpret_cast<const v4u*>(Rw + (ro[b] + off));
+        }
     };
 
     v4f acc[RA][4];
@@ -302,67 +365,90 @@ __global__ __launch_bounds__(256, 2) void k_contract_lds(
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    // one K step: A from LDS (row pair 8a + i16/2 of buffer buf at byte offset off), B from bv
-    auto kstep = [&](const unsigned char* buf, int off, const v4u (&bv)[4]) {
-        const int c = i16 & 1;
+    // one K step: lane (i16, g) reads LDS row 16 a + i16 of each plane (focal
+    // 8 a + i16 / 2 in form i16 % 2) at byte offset off; B from bv.  All A
+    // fragments are read first and the products run plane by plane (or K
+    // element by K element), so that updates of one accumulator are RA x 4
+    // instructions apart.
+    auto kstep = [&](int buf, int off, const v4u (&bv)[4]) {
+        const unsigned char* base = lds + buf * BUFB + i16 * ROWB + off;
+        v4u av[PLANES][RA];
 #pragma unroll
-        for (int a = 0; a < RA; ++a) {
-            const int rl = 8 * a + (i16 >> 1);
-            const v4u xa = *reinterpret_cast<const v4u*>(buf + rl * ROWB + off);
-            if constexpr (C64) {
-                const v4f av = a_row_f32(__builtin_bit_cast(v4f, xa), c);
+        for (int pl = 0; pl < PLANES; ++pl)
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
+            for (int a = 0; a < RA; ++a)
+                av[pl][a] = *reinterpret_cast<const v4u*>(base + (2 * pl * NFB + 16 * a) * ROWB);
+        if constexpr (C64) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int a = 0; a < RA; ++a)
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            av[e], __builtin_bit_cast(v4f, bv[b])[e], acc[a][b], 0, 0, 0);
-            } else {
-                v4u av[PLANES];
-                av[0] = a_row_16(xa, c);
-                if constexpr (SPLIT)
-                    av[1] = a_row_16(*reinterpret_cast<const v4u*>(buf + (NFB + rl) * ROWB + off), c);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(__builtin_bit_cast(v4f, av[0][a])[e],
+                                                                         __builtin_bit_cast(v4f, bv[b])[e],
+                                                                         acc[a][b], 0, 0, 0);
+        } else {
 #pragma unroll
-                for (int pl = 0; pl < PLANES; ++pl)
+            for (int pl = 0; pl < PLANES; ++pl)
+#pragma unroll
+                for (int a = 0; a < RA; ++a)
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
                         if constexpr (PREC == MK_R_F16S)
                             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                                __builtin_bit_cast(h8, av[pl]), __builtin_bit_cast(h8, bv[b]), acc[a][b], 0, 0, 0);
+                                __builtin_bit_cast(h8, av[pl][a]), __builtin_bit_cast(h8, bv[b]), acc[a][b], 0, 0, 0);
                         else
                             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                __builtin_bit_cast(b8, av[pl]), __builtin_bit_cast(b8, bv[b]), acc[a][b], 0, 0, 0);
+                                __builtin_bit_cast(b8, av[pl][a]), __builtin_bit_cast(b8, bv[b]), acc[a][b], 0, 0, 0);
                     }
-            }
         }
     };
 
-    stage_load(0);
-    stage_store(0);
-    v4u bq[PD][4];                                  // bq[0]: this K step; bq[p]: p steps ahead
-#pragma unroll
-    for (int p = 0; p < PD; ++p)
-        if (p < nsteps) load_b(p, bq[p]);
-    __syncthreads();
-    int c = 0, j = 0;                               // chunk, K step within the chunk
-    for (int st = 0; st < nsteps; ++st) {
-        if (j == 0 && c + 1 < nch) stage_load(c + 1);
-        if (active) kstep(lds[c & 1], koff(j, odd && st == nsteps - 1), bq[0]);
-#pragma unroll
-        for (int p = 0; p + 1 < PD; ++p)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) bq[p][b] = bq[p + 1][b];
-        if (st + PD < nsteps) load_b(st + PD, bq[PD - 1]);
-        if (++j == SPC || st + 1 == nsteps) {       // end of chunk c
-            if (c + 1 < nch) {
-                stage_store((c + 1) & 1);
-                __syncthreads();
+    // The chunk loop, in two copies: waves with receivers (ACT) and waves
+    // past nr, which only help stage X and keep the barriers.  Chunk c reads
+    // LDS buffer c % 3 and R registers rb[c % 3]; at its top it loads X and R
+    // of chunk c + 2 into xs[(c + 2) % 3] and rb[(c + 2) % 3] (both freed by
+    // chunk c - 1); at its end it stores X of chunk c + 1 from xs[(c + 1) % 3]
+    // into buffer (c + 1) % 3, which chunk c - 2 freed.
+    auto run = [&](auto act_tag) {
+        constexpr bool ACT = decltype(act_tag)::value;
+        v4u rb[3][2][4];
+        v4u xs[3][NV];
+        auto chunk = [&](int c, auto q_tag) {
+            constexpr int Q = decltype(q_tag)::value;      // c % 3
+            constexpr int Q1 = (Q + 1) % 3, Q2 = (Q + 2) % 3;
+            const int c2 = min(c + 2, nch - 1);           // past the end: reload the last chunk (unused)
+            stage_load(c2, xs[Q2]);
+            if constexpr (ACT) load_chunk(c2, rb[Q2]);
+            __builtin_amdgcn_sched_barrier(0);            // keep the loads ahead of the K steps
+            if constexpr (ACT) {
+                kstep(Q, lane_off, rb[Q][0]);
+                kstep(Q, lane_off + 16, rb[Q][1]);
             }
-            ++c;
-            j = 0;
+            stage_store(Q1, xs[Q1]);
+            lds_barrier();
+        };
+        stage_load(0, xs[0]);
+        stage_store(0, xs[0]);
+        stage_load(min(1, nch - 1), xs[1]);
+        if constexpr (ACT) {
+            load_chunk(0, rb[0]);
+            load_chunk(min(1, nch - 1), rb[1]);
         }
-    }
-    if (!active) return;
+        lds_barrier();
+        int c = 0;
+        for (; c + 3 <= nch; c += 3) {
+            chunk(c, std::integral_constant<int, 0>{});
+            chunk(c + 1, std::integral_constant<int, 1>{});
+            chunk(c + 2, std::integral_constant<int, 2>{});
+        }
+        if (c < nch) chunk(c, std::integral_constant<int, 0>{});
+        if (c + 1 < nch) chunk(c + 1, std::integral_constant<int, 1>{});
+    };
+    if (r0 < nr) run(std::true_type{});
+    else run(std::false_type{});
+    if (r0 >= nr) return;
 
     // D rows 16a + 4g + v (v = 0..3) are (Re, Im) of focal fbase + 8a + 2g and the next one
     const float rs = C64 ? 1.f : rscale[w];
@@ -384,14 +470,15 @@ __global__ __launch_bounds__(256, 2) void k_contract_lds(
     }
 }
 
-template <int PREC, int RA, bool SPLIT, int PD>
+template <int PREC, int RA, bool SPLIT, bool TILED>
 hipError_t launch_l(const ContractArgs& c, hipStream_t s) {
+    if ((c.ns_pad * (PREC == MK_R_C64 ? 8 : 4)) % kChunkBytes != 0) return hipErrorInvalidValue;
     constexpr int NFB = 8 * RA;
     const int ftiles = (c.ncols + NFB - 1) / NFB;
     const int rtiles = (c.nr + kLdsRcv - 1) / kLdsRcv;
     const int64_t ntiles = (int64_t)ftiles * rtiles * c.B;
     const int64_t per_xcd = (ntiles + 7) / 8;
-    hipLaunchKernelGGL((k_contract_lds<PREC, RA, SPLIT, PD>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_contract_lds<PREC, RA, SPLIT, TILED>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s,
                        c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B, c.ncols,
                        ftiles, rtiles, ntiles, per_xcd);
     return hipGetLastError();
@@ -412,20 +499,31 @@ hipError_t launch_v(const ContractArgs& c, hipStream_t s) {
 
 template <int PREC, bool SPLIT>
 hipError_t launch_p(const ContractArgs& c, int variant, hipStream_t s) {
+    if (c.tiled) {          // tiled R: only the LDS-staged kernels read it
+        switch (variant) {
+            case 5: return launch_l<PREC, 8, SPLIT, true>(c, s);
+            case 6: return launch_l<PREC, 4, SPLIT, true>(c, s);
+            case 7: return launch_l<PREC, 2, SPLIT, true>(c, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (variant) {
         case 0: return launch_v<PREC, 4, 2, SPLIT>(c, s);
         case 1: return launch_v<PREC, 2, 2, SPLIT>(c, s);
         case 2: return launch_v<PREC, 2, 4, SPLIT>(c, s);
         case 3: return launch_v<PREC, 1, 4, SPLIT>(c, s);
         case 4: return launch_v<PREC, 4, 1, SPLIT>(c, s);
-        case 5: return launch_l<PREC, 8, SPLIT, 2>(c, s);
-        case 6: return launch_l<PREC, 4, SPLIT, 4>(c, s);
-        case 7: return launch_l<PREC, 2, SPLIT, 4>(c, s);
+        case 5: return launch_l<PREC, 8, SPLIT, false>(c, s);
+        case 6: return launch_l<PREC, 4, SPLIT, false>(c, s);
+        case 7: return launch_l<PREC, 2, SPLIT, false>(c, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
+
+// contraction variant v (0 = GEMV, 1 + i = matrix-core shape i) reads tiled R
+bool contract_variant_reads_tiled(int variant) { return variant >= 6 && variant <= 8; }
 
 int contract_mfma_variants() { return 8; }
 

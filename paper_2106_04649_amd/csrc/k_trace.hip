@@ -150,31 +150,42 @@ __device__ __forceinline__ float2 unpack_bin(const float2* z, const float2* __re
 
 // TPT threads own one trace: 64 (one wave, four traces per block) when the
 // launch has many traces, 256 (the whole block) when it has few, so that a
-// one-focal pass still spreads over every CU.
+// one-focal pass still spreads over every CU.  The traces of a block are
+// consecutive receivers of one output column, and the block moves their
+// spectra between HBM and LDS together: neighbouring lanes take neighbouring
+// receivers of one bin, so each bin of Y is read and each bin of X written
+// as one contiguous run of TPB elements.  (Those lanes meet in the same LDS
+// banks; padding the regions apart would cost the fifth block per CU at
+// nt = 2048, which is worth more than the two short conflicting phases.)
 template <int NT, int MODE, int TPT>
 __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     constexpr int M = NT / 2;
     constexpr int TPB = 256 / TPT;          // traces per block
+    constexpr int KSTR = 256 / TPB;         // bins per cooperative sweep
+    constexpr int ZS = M;                   // float2 per trace region
     constexpr int PM = (M + TPT - 1) / TPT;
     constexpr bool GMODE = MODE == TM_GFWD || MODE == TM_GOUT;
-    __shared__ float2 lds[TPB * M];
+    __shared__ float2 lds[TPB * ZS];
     __shared__ double red[TPT > 64 ? 4 : 1];
     const int wv = threadIdx.x / TPT;       // trace slot in the block
     const int lane = threadIdx.x % TPT;     // thread within the trace
-    float2* z = lds + wv * M;
+    float2* z = lds + wv * ZS;
 
     // blocks are dealt to the 8 XCDs in contiguous runs, so that neighbouring
     // receivers (which share cache lines of Y and X) meet in one L2
-    const int ntr = a.nfo * a.nr;
-    const int nblk = (ntr + TPB - 1) / TPB;
+    const int nrg = (a.nr + TPB - 1) / TPB; // receiver groups per column
+    const int nblk = a.nfo * nrg;
     const int per_xcd = (nblk + 7) >> 3;
     const int blk = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
     if (blk >= nblk) return;                // uniform over the block
-    int trace = blk * TPB + wv;
-    const bool valid = trace < ntr;
-    if (!valid) trace = ntr - 1;            // keep the wave in the barriers, store nothing
-    const int fo = trace / a.nr;            // output column
-    const int r = trace - fo * a.nr;
+    const int fo = blk / nrg;               // output column
+    const int r0 = (blk - fo * nrg) * TPB;  // first receiver of the block
+    const bool valid = r0 + wv < a.nr;
+    const int r = valid ? r0 + wv : a.nr - 1;   // a slot past nr computes on a copy, stores nothing
+    // cooperative HBM <-> LDS moves: slot cs, bins ck, ck + KSTR, ...
+    const int cs = threadIdx.x % TPB, ck = threadIdx.x / TPB;
+    const bool cvalid = r0 + cs < a.nr;
+    const int rc = cvalid ? r0 + cs : a.nr - 1;
     const int f = GMODE ? (fo >> 1) : fo;   // focal point (G columns interleave f1+ and f1-(-t))
     const int hi = a.lo + a.B - 1;
     int flo = a.lo, fhi = hi;
@@ -187,18 +198,19 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
 
     // ---- spectrum -> time (TM_ITER, TM_GOUT) --------------------------------
     if (MODE == TM_ITER || MODE == TM_GOUT || MODE == TM_RST1 || MODE == TM_RST2) {
-        const float2* Yt = a.Y + (size_t)fo * a.B * a.nr + r;
+        const float2* Yt = a.Y + (size_t)fo * a.B * a.nr + rc;
         auto ybin = [&](int k) {
             return (k >= flo && k <= fhi) ? Yt[(size_t)(k - a.lo) * a.nr] : make_float2(0.f, 0.f);
         };
         // every stored bin is read once: slot k holds bin k, slot 0 the real
         // parts of DC and Nyquist (both real: their imaginary parts are dropped)
-        for (int k = lane; k < M; k += TPT) {
+        float2* zc = lds + cs * ZS;
+        for (int k = ck; k < M; k += KSTR) {
             float2 v = ybin(k);
             if (k == 0) v.y = ybin(M).x;
-            z[k] = v;
+            zc[k] = v;
         }
-        trace_sync<TPT>();
+        __syncthreads();
         // packed spectrum Z[k] = E[k] + i O[k] of the even/odd samples, from
         // bins k and M - k; each thread rewrites its own pair in place
         auto pack = [](float2 xk, float2 xm, float2 t) {
@@ -356,14 +368,16 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     // ---- time -> spectrum (TM_INIT, TM_ITER, TM_GFWD) ---------------------
     trace_sync<TPT>();
     fft_lds<NT, -1, TPT>(z, a.tw, lane);
+    __syncthreads();                          // every trace of the block transformed
+    const float2* zc = lds + cs * ZS;
     const int kend = a.skip_outband ? fhi : hi;
-    const size_t xoff = (size_t)fo * a.B * a.ns_pad + r;
+    const size_t xoff = (size_t)fo * a.B * a.ns_pad + rc;
     if (a.xprec == XP_F32) {
         float2* Xt = reinterpret_cast<float2*>(a.X) + xoff;
-        for (int k = a.lo + lane; k <= kend; k += TPT) {
+        for (int k = a.lo + ck; k <= kend; k += KSTR) {
             float2 v = make_float2(0.f, 0.f);
-            if (k >= flo && k <= fhi) v = unpack_bin<NT>(z, a.tw, k);
-            if (valid) Xt[(size_t)(k - a.lo) * a.ns_pad] = v;
+            if (k >= flo && k <= fhi) v = unpack_bin<NT>(zc, a.tw, k);
+            if (cvalid) Xt[(size_t)(k - a.lo) * a.ns_pad] = v;
         }
     } else {
         // 16-bit X scaled per focal point by the RMS trace norm of the previous field
@@ -375,9 +389,9 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         const bool bf = a.xprec == XP_BF16 || a.xprec == XP_BF16X2;
         const bool split = a.xprec == XP_F16X2 || a.xprec == XP_BF16X2;
         const size_t lo_off = (size_t)a.nfo * a.B * a.ns_pad;       // second plane
-        for (int k = a.lo + lane; k <= kend; k += TPT) {
+        for (int k = a.lo + ck; k <= kend; k += KSTR) {
             float2 v = make_float2(0.f, 0.f);
-            if (k >= flo && k <= fhi) v = unpack_bin<NT>(z, a.tw, k);
+            if (k >= flo && k <= fhi) v = unpack_bin<NT>(zc, a.tw, k);
             v.x *= inv;
             v.y *= inv;
             uint32_t u, ul = 0;
@@ -402,12 +416,12 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
                     ul = (lx >> 16) | (ly & 0xFFFF0000u);
                 }
             }
-            if (valid) {
+            if (cvalid) {
                 Xt[(size_t)(k - a.lo) * a.ns_pad] = u;
                 if (split) Xt[lo_off + (size_t)(k - a.lo) * a.ns_pad] = ul;
             }
         }
-        if (valid && r == 0 && lane == 0) a.xs_out[fo] = xs;
+        if (r0 == 0 && threadIdx.x == 0) a.xs_out[fo] = xs;
     }
     if (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2) {
         nacc = wave_sum_d(nacc);
@@ -465,9 +479,8 @@ __global__ __launch_bounds__(256) void k_norm_reduce(const double* __restrict__ 
 
 template <int NT, int TPT>
 hipError_t launch_trace_tpt(int mode, const TraceArgs& a, hipStream_t s) {
-    const int ntr = a.nfo * a.nr;
     constexpr int TPB = 256 / TPT;
-    const int nblk = (ntr + TPB - 1) / TPB;
+    const int nblk = a.nfo * ((a.nr + TPB - 1) / TPB);
     const dim3 grid(8 * ((nblk + 7) / 8)), block(256);
     switch (mode) {
         case TM_INIT: hipLaunchKernelGGL((k_trace<NT, TM_INIT, TPT>), grid, block, 0, s, a); break;

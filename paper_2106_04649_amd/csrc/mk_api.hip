@@ -137,12 +137,18 @@ int xprec_of(int rprec, int variant, bool fast_x = false) {
     return XP_F32;
 }
 
-int heuristic_variant(int ncols) {
+int heuristic_variant(mk_plan_t p, int ncols) {
+    if (p->r_tiled) {                    // LDS-staged tiles, the only readers of tiled R
+        if (ncols <= 16) return 1 + 7;   // 32 focal-real rows x 256 receivers
+        return 1 + 6;                    // 64 x 256
+    }
     if (ncols <= kGemvMaxCols) return 0;
     if (ncols <= 16) return 1 + 3;       // 32 focal-real rows x 128 receivers
-    if (ncols <= 32) return 1 + 6;       // LDS-staged, 64 focal-real rows x 256 receivers
-    return 1 + 5;                        // LDS-staged, 128 x 256
+    return 1 + 6;                        // LDS-staged, 64 focal-real rows x 256 receivers
 }
+
+// whether contraction variant v can read the plan's layout of R
+bool variant_fits(mk_plan_t p, int v) { return contract_variant_reads_tiled(v) || !p->r_tiled; }
 
 ContractArgs contract_args(mk_plan_t p, const void* X, int ncols, int ncols_mul) {
     ContractArgs c{};
@@ -154,6 +160,7 @@ ContractArgs contract_args(mk_plan_t p, const void* X, int ncols, int ncols_mul)
     c.ncols_w = p->has_fband ? p->ncols : nullptr;
     c.ncols_mul = ncols_mul;
     c.xsplit = 0;
+    c.tiled = p->r_tiled ? 1 : 0;
     c.nr = p->d.nr;
     c.ns = p->d.ns;
     c.ns_pad = p->ns_pad;
@@ -163,7 +170,7 @@ ContractArgs contract_args(mk_plan_t p, const void* X, int ncols, int ncols_mul)
 }
 
 hipError_t launch_choice(ContractArgs c, int variant, hipStream_t s) {
-    if (variant == 0) return launch_contract_gemv(c, s);
+    if (variant == 0) return c.tiled ? hipErrorInvalidValue : launch_contract_gemv(c, s);
     return launch_contract_mfma(c, variant - 1, s);
 }
 
@@ -194,7 +201,7 @@ mk_status autotune(mk_plan_t p, const void* Xbuf, const float* xs, int ncols, in
             const size_t bar = line.rfind('|');
             if (bar != std::string::npos && line.substr(0, bar) == key) {
                 const int v = std::atoi(line.c_str() + bar + 1);
-                if (v >= 0 && v <= contract_mfma_variants() &&
+                if (v >= 0 && v <= contract_mfma_variants() && variant_fits(p, v) &&
                     xprec_of(p->d.rprec, v, (p->d.flags & MK_FLAG_FAST_X) != 0) == xprec) {
                     p->tuned.push_back({ncols, v});
                     *out = v;
@@ -205,9 +212,10 @@ mk_status autotune(mk_plan_t p, const void* Xbuf, const float* xs, int ncols, in
     }
     std::vector<int> cands;
     const bool fast = (p->d.flags & MK_FLAG_FAST_X) != 0;
-    if (xprec_of(p->d.rprec, 0, fast) == xprec && ncols <= 2 * kGemvMaxCols) cands.push_back(0);
+    if (xprec_of(p->d.rprec, 0, fast) == xprec && ncols <= 2 * kGemvMaxCols && variant_fits(p, 0))
+        cands.push_back(0);
     for (int v = 0; v < contract_mfma_variants(); ++v)
-        if (xprec_of(p->d.rprec, 1 + v, fast) == xprec) cands.push_back(1 + v);
+        if (xprec_of(p->d.rprec, 1 + v, fast) == xprec && variant_fits(p, 1 + v)) cands.push_back(1 + v);
     hipEvent_t e0, e1;
     HIP_TRY(p, hipEventCreate(&e0));
     HIP_TRY(p, hipEventCreate(&e1));
@@ -243,7 +251,7 @@ mk_status autotune(mk_plan_t p, const void* Xbuf, const float* xs, int ncols, in
 // The contraction used for ncols columns; the X storage follows from it.
 ContractChoice choose(mk_plan_t p, int ncols) {
     ContractChoice ch;
-    ch.variant = p->tune_mode >= 0 ? p->tune_mode : heuristic_variant(ncols);
+    ch.variant = p->tune_mode >= 0 ? p->tune_mode : heuristic_variant(p, ncols);
     ch.xprec = xprec_of(p->d.rprec, ch.variant, (p->d.flags & MK_FLAG_FAST_X) != 0);
     return ch;
 }
@@ -402,7 +410,7 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
         return fail(nullptr, MK_ERR_ARG, "mk_plan: unknown rprec");
     if (d.rprec == MK_R_C64 && d.ns > 2048)
         return fail(nullptr, MK_ERR_UNSUPPORTED, "mk_plan: complex64 R supports ns <= 2048");
-    if (d.flags & ~(MK_FLAG_GRAPH | MK_FLAG_PROFILE | MK_FLAG_AUTOTUNE | MK_FLAG_FAST_X))
+    if (d.flags & ~(MK_FLAG_GRAPH | MK_FLAG_PROFILE | MK_FLAG_AUTOTUNE | MK_FLAG_FAST_X | MK_FLAG_ROW_R))
         return fail(nullptr, MK_ERR_ARG, "mk_plan: unknown flag bits");
 
     mk_plan_t p = new (std::nothrow) mk_plan_s();
@@ -411,7 +419,8 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     if (!(p->d.div_factor > 0.0)) p->d.div_factor = 1e3;
     p->B = d.iw_hi - d.iw_lo + 1;
     p->M = d.nt / 2;
-    p->ns_pad = (d.ns + 15) & ~15;
+    p->ns_pad = (d.ns + 31) & ~31;      // rows of whole 128-byte chunks in every precision
+    p->r_tiled = d.nf_max > kGemvMaxCols && !(d.flags & MK_FLAG_ROW_R);
     p->stream = reinterpret_cast<hipStream_t>(d.stream);
     p->tune_mode = (d.flags & MK_FLAG_AUTOTUNE) ? -2 : -1;
 
@@ -431,7 +440,8 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     const size_t nfm = (size_t)d.nf_max;
     const size_t trace = (size_t)d.nr * d.nt;
     const size_t relem = d.rprec == MK_R_C64 ? sizeof(float2) : sizeof(uint32_t);
-    const size_t rbytes = (size_t)p->B * d.nr * p->ns_pad * relem;
+    const size_t rbytes = p->r_tiled ? tiled_R_bytes(d.rprec, d.nr, p->B, p->ns_pad)
+                                     : (size_t)p->B * d.nr * p->ns_pad * relem;
     if ((e = hipMalloc(&p->R, rbytes)) != hipSuccess) return bail(e, "R");
     if ((e = dalloc(&p->rscale, (size_t)p->B)) != hipSuccess) return bail(e, "R scales");
     if ((e = dalloc(&p->X, 3 * nfm * p->B * p->ns_pad)) != hipSuccess) return bail(e, "X");
@@ -491,12 +501,18 @@ mk_status mk_load_R(mk_plan_t p, const float* R, int on_device) {
     int h = 0;
     hipError_t e = hipMemsetAsync(p->flag, 0, sizeof(int), p->stream);
     if (e == hipSuccess) {
-        if (d.rprec == MK_R_C64)
+        if (p->r_tiled) {
+            if (d.rprec != MK_R_C64) e = launch_rscale(src, p->rscale, d.nr, p->B, d.ns, p->flag, p->stream);
+            if (e == hipSuccess)
+                e = launch_repack_tiled(d.rprec, src, p->R, p->rscale, d.nr, p->B, d.ns, p->ns_pad, p->flag,
+                                        p->stream);
+        } else if (d.rprec == MK_R_C64) {
             e = launch_repack_c64(src, reinterpret_cast<float2*>(p->R), d.nr, p->B, d.ns, p->ns_pad,
                                   p->flag, p->stream);
-        else
+        } else {
             e = launch_quantize_R(d.rprec, src, p->R, p->rscale, d.nr, p->B, d.ns, p->ns_pad, p->flag,
                                   p->stream);
+        }
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
@@ -759,6 +775,9 @@ mk_status mk_tune(mk_plan_t p, int32_t mode) {
     if (!p) return fail(nullptr, MK_ERR_ARG, "mk_tune: plan is NULL");
     if (mode < -2 || mode > contract_mfma_variants())
         return fail(p, MK_ERR_ARG, "mk_tune: mode outside [-2, number of variants]");
+    if (mode >= 0 && !variant_fits(p, mode))
+        return fail(p, MK_ERR_ARG, "mk_tune: this variant reads row-major R; the plan keeps R tiled "
+                                   "(nf_max > 4 without MK_FLAG_ROW_R)");
     p->tune_mode = mode;
     p->tuned.clear();
     drop_graphs(p);

@@ -78,12 +78,13 @@ struct mk_plan_s {
     mk_plan_desc d{};
     int B = 0;          // stored bins
     int M = 0;          // nt / 2
-    int ns_pad = 0;     // padded row length of R and X (complex elements, multiple of 16)
+    int ns_pad = 0;     // padded row length of R and X (complex elements, multiple of 32)
+    bool r_tiled = false;   // R in the LDS-staged contraction's tiles (nf_max > 4, no MK_FLAG_ROW_R)
     int device = 0;
     hipStream_t stream = nullptr;
 
     // device memory (plan-owned)
-    void* R = nullptr;         // [B][nr][ns_pad] complex64 or 16-bit pairs
+    void* R = nullptr;         // [B][nr][ns_pad] complex64 or 16-bit pairs, or tiled (r_tiled)
     float* rscale = nullptr;   // [B] per-frequency scale of 16-bit R
     float2* X = nullptr;       // [3 nf_max][B][ns_pad]: series slabs, then G-assembly slabs
     float2* Y = nullptr;       // [2 nf_max][B][nr]
@@ -173,6 +174,7 @@ struct ContractArgs {
     const int* ncols_w;
     int ncols_mul;
     int xsplit;            // 16-bit X held as hi and lo planes (two products)
+    int tiled;             // R in the LDS-staged contraction's tiles
     int nr, ns, ns_pad, B, ncols;
 };
 
@@ -190,6 +192,20 @@ hipError_t launch_repack_c64(const float* Rin, float2* Rout, int nr, int B, int 
                              int* flag, hipStream_t s);
 hipError_t launch_quantize_R(int prec, const float* Rin, void* Rout, float* rscale, int nr, int B,
                              int ns, int ns_pad, int* flag, hipStream_t s);
+// per-frequency scales of 16-bit R (k_rmax); the tiled repack below uses them
+hipError_t launch_rscale(const float* Rin, float* rscale, int nr, int B, int ns, int* flag, hipStream_t s);
+// Tiled R for the LDS-staged contraction: for bin w, 16-receiver group rg and
+// 128-byte chunk c of the rows, a 2 KB tile [h][lane] of 16-byte pieces where
+// lane = 16 g + i holds receiver 16 rg + i, row bytes c*128 + 32 g + 16 h; the
+// tiles follow in (w, rg, c) order, so one wave load of 64 x 16 bytes is 1 KB
+// of contiguous memory.  Receivers past nr and shots past ns are zero.
+constexpr int kTileRows = 16;
+constexpr int kTileChunkBytes = 128;
+// R into the tiles of the LDS-staged contraction (any precision)
+hipError_t launch_repack_tiled(int prec, const float* Rin, void* Rout, const float* rscale, int nr, int B,
+                               int ns, int ns_pad, int* flag, hipStream_t s);
+size_t tiled_R_bytes(int prec, int nr, int B, int ns_pad);
+bool contract_variant_reads_tiled(int variant);
 hipError_t launch_check_finite(const float* x, int64_t n, int* flag, hipStream_t s);
 hipError_t launch_tail_prep(const float* hist, int ntr, int k, int T, float* x, float* scale, hipStream_t s);
 hipError_t launch_tail_apply(const float* hist, const float* y, const float* scale, const int32_t* itd, int shift,

@@ -19,22 +19,38 @@ pytestmark = pytest.mark.gpu
 TOL = {0: TOL_FP32, 1: 1e-3, 2: 1e-2}
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+def _flags(variant, tiled):
+    """Row-major R for the variants that read only that layout (plans with nf > 4 tile R by default)."""
+    mk = require_gpu()
+    return 0 if tiled else mk.MK_FLAG_ROW_R
+
+
+@pytest.mark.parametrize("variant,tiled", [(v, False) for v in range(9)] + [(v, True) for v in (6, 7, 8)])
 @pytest.mark.parametrize("n,nt,nf", [(70, 64, 6), (37, 128, 40), (300, 32, 20)])
-def test_every_contraction_variant_fp32(variant, n, nt, nf):
-    say(f"variant {variant} n={n} nt={nt} nf={nf}")
+def test_every_contraction_variant_fp32(variant, tiled, n, nt, nf):
+    say(f"variant {variant} tiled {tiled} n={n} nt={nt} nf={nf}")
     p = small_problem(seed=20 + nf, n=n, nt=nt, nf=nf, niter=6)
-    g = run_gpu(p, tune=variant)
+    g = run_gpu(p, tune=variant, flags=_flags(variant, tiled))
     assert g["variant"] == variant
-    assert_parity(g, run_oracle(p), label=f"v{variant}")
+    assert_parity(g, run_oracle(p), label=f"v{variant}{'t' if tiled else ''}")
+
+
+def test_row_major_variant_refused_on_tiled_plan():
+    mk = require_gpu()
+    plan = mk.mk_plan(16, 16, 64, 0.004, 10.0, nf_max=8)
+    with pytest.raises(mk.MKError):
+        mk.mk_tune(plan, 1)
+    mk.mk_tune(plan, 7)
+    mk.mk_destroy(plan)
 
 
 @pytest.mark.parametrize("rprec", [1, 2])
-@pytest.mark.parametrize("variant", [0, 1, 4, 6, 7, 8])
-def test_reduced_precision_R(rprec, variant):
-    say(f"rprec {rprec} variant {variant}")
+@pytest.mark.parametrize("variant,tiled", [(0, False), (1, False), (4, False), (7, False), (6, True), (7, True),
+                                           (8, True)])
+def test_reduced_precision_R(rprec, variant, tiled):
+    say(f"rprec {rprec} variant {variant} tiled {tiled}")
     p = small_problem(seed=31, n=48, nt=128, nf=20, niter=8)
-    g = run_gpu(p, rprec=rprec, tune=variant)
+    g = run_gpu(p, rprec=rprec, tune=variant, flags=_flags(variant, tiled))
     assert_parity(g, run_oracle(p), tol=TOL[rprec], label=f"prec{rprec}-v{variant}")
 
 
@@ -45,7 +61,7 @@ def test_single_plane_16bit_X(rprec, variant):
     mk = require_gpu()
     say(f"fast X rprec {rprec} variant {variant}")
     p = small_problem(seed=31, n=48, nt=128, nf=20, niter=8)
-    g = run_gpu(p, rprec=rprec, tune=variant, flags=mk.MK_FLAG_FAST_X)
+    g = run_gpu(p, rprec=rprec, tune=variant, flags=mk.MK_FLAG_FAST_X | _flags(variant, variant >= 6))
     assert_parity(g, run_oracle(p), tol=2 * TOL[rprec], label=f"fastx{rprec}-v{variant}")
 
 
@@ -57,7 +73,7 @@ def test_per_focal_bands_batched(rprec, variant):
     hi = rng.integers(10, 65, size=p.nf)
     lo = np.where(rng.random(p.nf) < 0.3, rng.integers(0, 8, size=p.nf), 0)
     fb = np.stack([lo, hi], axis=1).astype(np.int32)
-    g = run_gpu(p, fbands=fb, rprec=rprec, tune=variant)
+    g = run_gpu(p, fbands=fb, rprec=rprec, tune=variant, flags=_flags(variant, variant >= 6))
     assert_parity(g, run_oracle(p, fbands=fb), tol=TOL[rprec], label=f"bands{rprec}-{variant}")
 
 
@@ -87,9 +103,9 @@ def test_medium_focal_line_batched():
     assert_parity(g, r, label="medium64-fp32")
     g16 = run_gpu(p, niter=2, rprec=1)
     assert_parity(g16, r, tol=1e-3, label="medium64-fp16")
-    for v in (6, 1):                                  # both matrix-core kernel families at full size
-        gv = run_gpu(p, niter=2, rprec=1, tune=v)
+    for v, tiled in ((6, True), (7, True), (7, False), (1, False)):   # both kernel families, both layouts
+        gv = run_gpu(p, niter=2, rprec=1, tune=v, flags=_flags(v, tiled))
         assert gv["variant"] == v
-        assert_parity(gv, r, tol=1e-3, label=f"medium64-fp16-v{v}")
-    g32 = run_gpu(p, niter=2, tune=6)
-    assert_parity(g32, r, label="medium64-fp32-v6")
+        assert_parity(gv, r, tol=1e-3, label=f"medium64-fp16-v{v}{'t' if tiled else ''}")
+    g32 = run_gpu(p, niter=2, tune=8)
+    assert_parity(g32, r, label="medium64-fp32-v8t")
