@@ -3,8 +3,9 @@
 //
 // One wavefront owns one trace (f, r); a 256-thread block holds four traces.
 // The real transforms of length nt use one complex transform of length
-// M = nt/2 on packed even/odd samples (Stockham autosort, radix 4 with one
-// radix-2 stage when log2 M is odd), with exact twiddles from a table of
+// M = nt/2 on packed even/odd samples (Stockham autosort: radix-16 passes
+// when a wave owns the trace, radix 4 (with one radix-2 pass when log2 M is
+// odd) when the whole block does), with exact twiddles from a table of
 // exp(-2 pi i k / nt) computed in double on the host.
 //
 // TM_ITER implements one pass of Algorithm 1 after the space integral of
@@ -22,13 +23,27 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// twiddle exp(DIR * 2 pi i idx / nt) from the forward table exp(-2 pi i idx / nt)
-template <int DIR>
-__device__ __forceinline__ float2 twid(const float2* __restrict__ tw, int idx) {
-    float2 t = tw[idx];
+// Twiddle exp(DIR 2 pi i idx / nt), idx in [0, nt), from a quarter table
+// tq[r] = exp(-2 pi i r / nt), r < nt/4, held in LDS: with idx = qd nt/4 + r,
+// exp(-2 pi i idx / nt) = (-i)^qd tq[r] (an exact swap and sign change).
+template <int DIR, int NT>
+__device__ __forceinline__ float2 twid(const float2* tq, int idx) {
+    constexpr int Q = NT / 4;
+    const int qd = (idx / Q) & 3, r = idx & (Q - 1);
+    const float2 w = tq[r];
+    const bool sw = (qd & 1) != 0;                         // odd quadrant: swap
+    const float x = sw ? w.y : w.x, y = sw ? w.x : w.y;
+    const float sx = (qd == 2 || qd == 3) ? -1.f : 1.f;    // (-i)^qd = (1,0) (0,-1) (-1,0) (0,1) on (x, y)
+    const float sy = (qd == 1 || qd == 2) ? -1.f : 1.f;
+    float2 t = make_float2(sx * x, sy * y);
     if (DIR > 0) t.y = -t.y;
     return t;
 }
+
+// LDS slot of element k of a trace's packed spectrum: one float2 of padding
+// after every 16, so that the stride-16 accesses of the radix-16 passes (and
+// the neighbouring traces of the cooperative phases) spread over all banks.
+__device__ __forceinline__ int zi(int k) { return k + (k >> 4); }
 
 // Barrier among the threads that own one trace: the whole block, or one
 // wave, whose lanes run in lockstep and whose LDS accesses complete in
@@ -48,7 +63,7 @@ __device__ __forceinline__ void trace_sync() {
 // threads that own one trace (one wave, or the whole block).
 // DIR = -1: forward (exp(-i...)), DIR = +1: inverse, both unnormalised.
 template <int NT, int DIR, int TPT>
-__device__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
+__device__ __forceinline__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
     constexpr int M = NT / 2;
     constexpr int LOG2M = ilog2c(M);
     constexpr int N4 = LOG2M / 2;
@@ -64,7 +79,7 @@ __device__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
             const int j = lane + TPT * p;
             if (j < Q) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v[p][q] = z[j + q * Q];
+                for (int q = 0; q < 4; ++q) v[p][q] = z[zi(j + q * Q)];
             }
         }
         trace_sync<TPT>();
@@ -75,9 +90,9 @@ __device__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
                 const int k = j & (Ns - 1);
                 const int base = k * (NT >> (lns + 2));     // k * NT / (4 Ns)
                 const float2 a0 = v[p][0];
-                const float2 a1 = st == 0 ? v[p][1] : cmul(v[p][1], twid<DIR>(tw, base));
-                const float2 a2 = st == 0 ? v[p][2] : cmul(v[p][2], twid<DIR>(tw, 2 * base));
-                const float2 a3 = st == 0 ? v[p][3] : cmul(v[p][3], twid<DIR>(tw, 3 * base));
+                const float2 a1 = st == 0 ? v[p][1] : cmul(v[p][1], twid<DIR, NT>(tw, base));
+                const float2 a2 = st == 0 ? v[p][2] : cmul(v[p][2], twid<DIR, NT>(tw, 2 * base));
+                const float2 a3 = st == 0 ? v[p][3] : cmul(v[p][3], twid<DIR, NT>(tw, 3 * base));
                 const float2 s02 = make_float2(a0.x + a2.x, a0.y + a2.y);
                 const float2 d02 = make_float2(a0.x - a2.x, a0.y - a2.y);
                 const float2 s13 = make_float2(a1.x + a3.x, a1.y + a3.y);
@@ -91,10 +106,10 @@ __device__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
                     y3 = make_float2(d02.x + d13.y, d02.y - d13.x);
                 }
                 const int idxD = ((j - k) << 2) + k;
-                z[idxD] = make_float2(s02.x + s13.x, s02.y + s13.y);
-                z[idxD + Ns] = y1;
-                z[idxD + 2 * Ns] = make_float2(s02.x - s13.x, s02.y - s13.y);
-                z[idxD + 3 * Ns] = y3;
+                z[zi(idxD)] = make_float2(s02.x + s13.x, s02.y + s13.y);
+                z[zi(idxD + Ns)] = y1;
+                z[zi(idxD + 2 * Ns)] = make_float2(s02.x - s13.x, s02.y - s13.y);
+                z[zi(idxD + 3 * Ns)] = y3;
             }
         }
         trace_sync<TPT>();
@@ -109,8 +124,8 @@ __device__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
         for (int p = 0; p < PER2; ++p) {
             const int j = lane + TPT * p;
             if (j < H) {
-                v[p][0] = z[j];
-                v[p][1] = z[j + H];
+                v[p][0] = z[zi(j)];
+                v[p][1] = z[zi(j + H)];
             }
         }
         trace_sync<TPT>();
@@ -120,14 +135,143 @@ __device__ void fft_lds(float2* z, const float2* __restrict__ tw, int lane) {
             if (j < H) {
                 const int k = j & (Ns - 1);
                 const float2 a0 = v[p][0];
-                const float2 a1 = lns == 0 ? v[p][1] : cmul(v[p][1], twid<DIR>(tw, k * (NT >> (lns + 1))));
+                const float2 a1 = lns == 0 ? v[p][1] : cmul(v[p][1], twid<DIR, NT>(tw, k * (NT >> (lns + 1))));
                 const int idxD = ((j - k) << 1) + k;
-                z[idxD] = make_float2(a0.x + a1.x, a0.y + a1.y);
-                z[idxD + Ns] = make_float2(a0.x - a1.x, a0.y - a1.y);
+                z[zi(idxD)] = make_float2(a0.x + a1.x, a0.y + a1.y);
+                z[zi(idxD + Ns)] = make_float2(a0.x - a1.x, a0.y - a1.y);
             }
         }
         trace_sync<TPT>();
     }
+}
+
+// ---- radix-16 Stockham transform (one wave per trace) --------------------
+// Passes of radix 16 and one final pass of radix 2, 4 or 8 (1024 points:
+// 16 x 16 x 4), each lane holding whole butterflies in registers, so a
+// transform makes three LDS round trips instead of five.  Pass with span Ns
+// and radix R: butterfly j (k = j mod Ns) takes z[j + q M/R], q < R,
+// multiplies input q by W_{Ns R}^{q k}, transforms, and writes output m to
+// z[(j - k) R + k + m Ns].
+
+// exp(2 pi i n / 16) for n = 0..15, and its sine
+__device__ __forceinline__ float c16(int n) {
+    constexpr float c[16] = {1.f, 0.92387953251128676f, 0.70710678118654752f, 0.38268343236508977f,
+                             0.f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128676f,
+                             -1.f, -0.92387953251128676f, -0.70710678118654752f, -0.38268343236508977f,
+                             0.f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128676f};
+    return c[n & 15];
+}
+__device__ __forceinline__ float s16(int n) { return c16(n + 12); }     // sin(x) = cos(x - pi/2)
+
+// v * exp(DIR 2 pi i n / 16)
+template <int DIR>
+__device__ __forceinline__ float2 rot16(float2 v, int n) {
+    const float c = c16(n), sn = DIR * s16(n);
+    return make_float2(v.x * c - v.y * sn, v.x * sn + v.y * c);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft2(float2& a0, float2& a1) {
+    const float2 t = a0;
+    a0 = make_float2(t.x + a1.x, t.y + a1.y);
+    a1 = make_float2(t.x - a1.x, t.y - a1.y);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+    const float2 s02 = make_float2(a0.x + a2.x, a0.y + a2.y), d02 = make_float2(a0.x - a2.x, a0.y - a2.y);
+    const float2 s13 = make_float2(a1.x + a3.x, a1.y + a3.y), d13 = make_float2(a1.x - a3.x, a1.y - a3.y);
+    a0 = make_float2(s02.x + s13.x, s02.y + s13.y);
+    a2 = make_float2(s02.x - s13.x, s02.y - s13.y);
+    if (DIR < 0) {       // y1 = d02 - i d13, y3 = d02 + i d13
+        a1 = make_float2(d02.x + d13.y, d02.y - d13.x);
+        a3 = make_float2(d02.x - d13.y, d02.y + d13.x);
+    } else {             // y1 = d02 + i d13, y3 = d02 - i d13
+        a1 = make_float2(d02.x - d13.y, d02.y + d13.x);
+        a3 = make_float2(d02.x + d13.y, d02.y - d13.x);
+    }
+}
+
+// In-register DFT of R points (R = 2, 4, 8, 16).  R = R1 R2 with input
+// q = R2 a + b: DFT_R1 over a, twiddle W_R^{b k1}, DFT_R2 over b; output
+// X[k1 + R1 k2] ends in register R2 k1 + k2 (see out_reg).
+template <int R, int DIR>
+__device__ __forceinline__ void dft_reg(float2 (&v)[R]) {
+    if constexpr (R == 2) {
+        dft2<DIR>(v[0], v[1]);
+    } else if constexpr (R == 4) {
+        dft4<DIR>(v[0], v[1], v[2], v[3]);
+    } else {
+        constexpr int R1 = R == 16 ? 4 : 2, R2 = 4;
+#pragma unroll
+        for (int b = 0; b < R2; ++b) {
+            if constexpr (R1 == 4) dft4<DIR>(v[b], v[4 + b], v[8 + b], v[12 + b]);
+            else dft2<DIR>(v[b], v[4 + b]);
+#pragma unroll
+            for (int k1 = 1; k1 < R1; ++k1) v[R2 * k1 + b] = rot16<DIR>(v[R2 * k1 + b], (16 / R) * b * k1);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) dft4<DIR>(v[R2 * k1], v[R2 * k1 + 1], v[R2 * k1 + 2], v[R2 * k1 + 3]);
+    }
+}
+
+// register holding output m of dft_reg
+template <int R>
+__device__ __forceinline__ constexpr int out_reg(int m) {
+    return R == 16 ? 4 * (m & 3) + (m >> 2) : R == 8 ? 4 * (m & 1) + (m >> 1) : m;
+}
+
+template <int NT, int DIR, int NS, int R>
+__device__ __forceinline__ void fft16_pass(float2* z, const float2* __restrict__ tw, int lane) {
+    constexpr int M = NT / 2;
+    constexpr int NB = M / R;                // butterflies
+    constexpr int PB = (NB + 63) / 64;       // per lane
+    constexpr int TWS = NT / (NS * R);       // twiddle index step: W_{NS R}^{q k} = twid(q k TWS)
+    float2 v[PB][R];
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+        const int j = lane + 64 * p;
+        if (j < NB) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[p][q] = z[zi(j + q * NB)];
+        }
+    }
+    trace_sync<64>();
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+        const int j = lane + 64 * p;
+        if (j < NB) {
+            const int k = j & (NS - 1);
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int q = 1; q < R; ++q) v[p][q] = cmul(v[p][q], twid<DIR, NT>(tw, q * k * TWS));
+            }
+            dft_reg<R, DIR>(v[p]);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int m = 0; m < R; ++m) z[zi(base + m * NS)] = v[p][out_reg<R>(m)];
+        }
+    }
+    trace_sync<64>();
+}
+
+template <int NT, int DIR, int NS, int BITS>
+__device__ __forceinline__ void fft16_passes(float2* z, const float2* __restrict__ tw, int lane) {
+    if constexpr (BITS >= 4) {
+        fft16_pass<NT, DIR, NS, 16>(z, tw, lane);
+        fft16_passes<NT, DIR, NS * 16, BITS - 4>(z, tw, lane);
+    } else if constexpr (BITS > 0) {
+        fft16_pass<NT, DIR, NS, (1 << BITS)>(z, tw, lane);
+    }
+}
+
+// the transform of M = NT/2 points for TPT threads per trace: radix 16 when
+// a wave owns the trace, radix 4 when the whole block does (more butterflies
+// to spread over 256 threads)
+template <int NT, int DIR, int TPT>
+__device__ __forceinline__ void fft_trace(float2* z, const float2* __restrict__ tw, int lane) {
+    if constexpr (TPT == 64 && NT >= 16) fft16_passes<NT, DIR, 1, ilog2c(NT / 2)>(z, tw, lane);
+    else fft_lds<NT, DIR, TPT>(z, tw, lane);
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -140,11 +284,11 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 template <int NT>
 __device__ __forceinline__ float2 unpack_bin(const float2* z, const float2* __restrict__ tw, int k) {
     constexpr int M = NT / 2;
-    const float2 zk = z[k & (M - 1)];
-    const float2 zm = z[(M - k) & (M - 1)];
+    const float2 zk = z[zi(k & (M - 1))];
+    const float2 zm = z[zi((M - k) & (M - 1))];
     const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
     const float2 d = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
-    const float2 wd = cmul(tw[k], d);
+    const float2 wd = cmul(twid<-1, NT>(tw, k), d);
     return make_float2(e.x + wd.y, e.y - wd.x);          // E - i W^k D
 }
 
@@ -154,18 +298,17 @@ __device__ __forceinline__ float2 unpack_bin(const float2* z, const float2* __re
 // consecutive receivers of one output column, and the block moves their
 // spectra between HBM and LDS together: neighbouring lanes take neighbouring
 // receivers of one bin, so each bin of Y is read and each bin of X written
-// as one contiguous run of TPB elements.  (Those lanes meet in the same LDS
-// banks; padding the regions apart would cost the fifth block per CU at
-// nt = 2048, which is worth more than the two short conflicting phases.)
+// as one contiguous run of TPB elements.
 template <int NT, int MODE, int TPT>
 __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     constexpr int M = NT / 2;
     constexpr int TPB = 256 / TPT;          // traces per block
     constexpr int KSTR = 256 / TPB;         // bins per cooperative sweep
-    constexpr int ZS = M;                   // float2 per trace region
+    constexpr int ZS = M + M / 16;          // float2 per trace region (padded, see zi)
     constexpr int PM = (M + TPT - 1) / TPT;
     constexpr bool GMODE = MODE == TM_GFWD || MODE == TM_GOUT;
     __shared__ float2 lds[TPB * ZS];
+    __shared__ float2 tq[NT / 4];            // quarter twiddle table (see twid)
     __shared__ double red[TPT > 64 ? 4 : 1];
     const int wv = threadIdx.x / TPT;       // trace slot in the block
     const int lane = threadIdx.x % TPT;     // thread within the trace
@@ -178,6 +321,8 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     const int per_xcd = (nblk + 7) >> 3;
     const int blk = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
     if (blk >= nblk) return;                // uniform over the block
+    for (int i = threadIdx.x; i < NT / 4; i += 256) tq[i] = a.tw[i];
+    __syncthreads();
     const int fo = blk / nrg;               // output column
     const int r0 = (blk - fo * nrg) * TPB;  // first receiver of the block
     const bool valid = r0 + wv < a.nr;
@@ -208,7 +353,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         for (int k = ck; k < M; k += KSTR) {
             float2 v = ybin(k);
             if (k == 0) v.y = ybin(M).x;
-            zc[k] = v;
+            zc[zi(k)] = v;
         }
         __syncthreads();
         // packed spectrum Z[k] = E[k] + i O[k] of the even/odd samples, from
@@ -220,16 +365,16 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
             return make_float2(e.x - o.y, e.y + o.x);
         };
         for (int k = lane; k <= M / 2; k += TPT) {
-            const float2 zk = z[k], zm = z[(M - k) & (M - 1)];
+            const float2 zk = z[zi(k)], zm = z[zi((M - k) & (M - 1))];
             if (k == 0) {
-                z[0] = pack(make_float2(zk.x, 0.f), make_float2(zk.y, 0.f), a.tw[0]);
+                z[zi(0)] = pack(make_float2(zk.x, 0.f), make_float2(zk.y, 0.f), make_float2(1.f, 0.f));
             } else {
-                z[k] = pack(zk, zm, a.tw[k]);
-                if (k != M - k) z[M - k] = pack(zm, zk, a.tw[M - k]);
+                z[zi(k)] = pack(zk, zm, twid<-1, NT>(tq, k));
+                if (k != M - k) z[zi(M - k)] = pack(zm, zk, twid<-1, NT>(tq, M - k));
             }
         }
         trace_sync<TPT>();
-        fft_lds<NT, +1, TPT>(z, a.tw, lane);
+        fft_trace<NT, +1, TPT>(z, tq, lane);
         // z[m] = (RN[2m], RN[2m+1]) / s
     }
 
@@ -253,15 +398,15 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
                 const bool k0 = (s0 < L) && (-s0 < L) && (t0 != M);
                 const bool k1 = (s1 < L) && (-s1 < L);
                 // N[t] = -RN[(nt - t) mod nt] inside the window
-                const float n0 = k0 ? -s * z[(M - m) & (M - 1)].x : 0.f;
-                const float n1 = k1 ? -s * z[M - 1 - m].y : 0.f;
+                const float n0 = k0 ? -s * z[zi((M - m) & (M - 1))].x : 0.f;
+                const float n1 = k1 ? -s * z[zi(M - 1 - m)].y : 0.f;
                 if (MODE == TM_ITER) {
                     nacc += (double)n0 * n0 + (double)n1 * n1;
                     if (valid && (k0 || k1)) {
                         float2* pa = reinterpret_cast<float2*>(acc + tbase) + m;
                         float2 o = *pa;
                         if (a.parity == 0) {             // f1- -= N(-t)  ==  f1- += theta RN
-                            const float2 zm = z[m];
+                            const float2 zm = z[zi(m)];
                             if (k0) o.x += s * zm.x;
                             if (k1) o.y += s * zm.y;
                         } else {                          // f1+ += N
@@ -279,7 +424,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
                     // f1- := theta S f1+ (overwrite); the field fed on is N' = -(theta RN)(-t)
                     nacc += (double)n0 * n0 + (double)n1 * n1;
                     if (valid) {
-                        const float2 zm = z[m];
+                        const float2 zm = z[zi(m)];
                         reinterpret_cast<float2*>(a.f1m + tbase)[m] =
                             make_float2(k0 ? s * zm.x : 0.f, k1 ? s * zm.y : 0.f);
                     }
@@ -300,7 +445,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
 #pragma unroll
         for (int p = 0; p < PM; ++p) {
             const int m = lane + TPT * p;
-            if (m < M) z[m] = out[p];
+            if (m < M) z[zi(m)] = out[p];
         }
     } else if (MODE == TM_INIT) {
         const float* g = a.src + tbase;
@@ -317,14 +462,14 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
                     reinterpret_cast<float2*>(a.f1m + tbase)[m] = make_float2(0.f, 0.f);
                     if (a.n0) reinterpret_cast<float2*>(a.n0 + tbase)[m] = make_float2(n0, n1);
                 }
-                z[m] = make_float2(n0, n1);
+                z[zi(m)] = make_float2(n0, n1);
             }
         }
     } else if (MODE == TM_FWDF) {
 #pragma unroll
         for (int p = 0; p < PM; ++p) {
             const int m = lane + TPT * p;
-            if (m < M) z[m] = reinterpret_cast<const float2*>(a.f1p + tbase)[m];
+            if (m < M) z[zi(m)] = reinterpret_cast<const float2*>(a.f1p + tbase)[m];
         }
     } else if (MODE == TM_GFWD) {
         const bool minus = (fo & 1) != 0;
@@ -339,7 +484,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
                     const float* q = a.f1m + tbase;
                     v = make_float2(q[(NT - 2 * m) & (NT - 1)], q[NT - 2 * m - 1]);
                 }
-                z[m] = v;
+                z[zi(m)] = v;
             }
         }
     } else if (MODE == TM_GOUT) {
@@ -348,7 +493,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         for (int p = 0; p < PM; ++p) {
             const int m = lane + TPT * p;
             if (m < M && valid) {
-                const float2 zm = z[m];
+                const float2 zm = z[zi(m)];
                 const double rn0 = (double)(s * zm.x), rn1 = (double)(s * zm.y);
                 if (!plus) {                          // G- = S[f1+] - f1-
                     const float2 q = reinterpret_cast<const float2*>(a.f1m + tbase)[m];
@@ -367,7 +512,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
 
     // ---- time -> spectrum (TM_INIT, TM_ITER, TM_GFWD) ---------------------
     trace_sync<TPT>();
-    fft_lds<NT, -1, TPT>(z, a.tw, lane);
+    fft_trace<NT, -1, TPT>(z, tq, lane);
     __syncthreads();                          // every trace of the block transformed
     const float2* zc = lds + cs * ZS;
     const int kend = a.skip_outband ? fhi : hi;
@@ -376,7 +521,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         float2* Xt = reinterpret_cast<float2*>(a.X) + xoff;
         for (int k = a.lo + ck; k <= kend; k += KSTR) {
             float2 v = make_float2(0.f, 0.f);
-            if (k >= flo && k <= fhi) v = unpack_bin<NT>(zc, a.tw, k);
+            if (k >= flo && k <= fhi) v = unpack_bin<NT>(zc, tq, k);
             if (cvalid) Xt[(size_t)(k - a.lo) * a.ns_pad] = v;
         }
     } else {
@@ -391,7 +536,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         const size_t lo_off = (size_t)a.nfo * a.B * a.ns_pad;       // second plane
         for (int k = a.lo + ck; k <= kend; k += KSTR) {
             float2 v = make_float2(0.f, 0.f);
-            if (k >= flo && k <= fhi) v = unpack_bin<NT>(zc, a.tw, k);
+            if (k >= flo && k <= fhi) v = unpack_bin<NT>(zc, tq, k);
             v.x *= inv;
             v.y *= inv;
             uint32_t u, ul = 0;

@@ -67,7 +67,7 @@ void free_plan_memory(mk_plan_t p) {
     drop_graphs(p);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     void* bufs[] = {p->R, p->rscale, p->X, p->Y, p->f1p, p->f1m, p->gp, p->gm, p->stage, p->itd,
-                    p->fband, p->perm, p->iperm, p->ncols, p->npart, p->norm0, p->nlast, p->xscale,
+                    p->fband, p->perm, p->iperm, p->ncols, p->npart, p->norm0, p->gdnorm, p->nlast, p->xscale,
                     p->norms, p->tw, p->flag, p->n0, p->hist, p->tail_w, p->tail_x, p->tail_work,
                     p->tail_y, p->tail_scale};
     for (void* b : bufs)
@@ -364,7 +364,7 @@ mk_status assemble_G(mk_plan_t p) {
     float2* Xg = p->X + (size_t)nf * p->B * p->ns_pad;
     a.X = Xg;
     a.xprec = p->g_choice.xprec;
-    a.xs_in = p->norm0;
+    a.xs_in = p->gdnorm;      // f1+ and f1- stay on the scale of G_d (norm0 may hold a restart residual)
     a.xs_out = p->xscale + nf;
     a.skip_outband = (p->g_choice.variant != 0 && p->has_fband) ? 1 : 0;
     MK_TRY(run_trace(p, TM_GFWD, a, 4));
@@ -458,6 +458,7 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     if ((e = dalloc(&p->ncols, (size_t)p->B)) != hipSuccess) return bail(e, "ncols");
     if ((e = dalloc(&p->npart, 2 * nfm * d.nr)) != hipSuccess) return bail(e, "norm partials");
     if ((e = dalloc(&p->norm0, nfm)) != hipSuccess) return bail(e, "norm0");
+    if ((e = dalloc(&p->gdnorm, nfm)) != hipSuccess) return bail(e, "gdnorm");
     if ((e = dalloc(&p->nlast, nfm)) != hipSuccess) return bail(e, "nlast");
     if ((e = dalloc(&p->xscale, 3 * nfm)) != hipSuccess) return bail(e, "X scales");
     if ((e = dalloc(&p->tw, (size_t)d.nt)) != hipSuccess) return bail(e, "twiddles");
@@ -613,6 +614,7 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
     // ||N_-1|| = ||G_d|| per focal point (also the scale of the first 16-bit X)
     HIP_TRY(p, launch_sumsq(p->gp, (int)ntr, d.nt, p->npart, p->stream));
     HIP_TRY(p, launch_norm_reduce(p->npart, d.nr, nf, p->norm0, p->nlast, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(p->gdnorm, p->norm0, nf * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
     TraceArgs a = trace_args(p, nf);
     a.src = p->gp;
     a.xprec = p->series_choice.xprec;

@@ -99,7 +99,8 @@ struct mk_plan_s {
     int32_t* iperm = nullptr;  // [nf_max] caller's focal index -> sorted position
     int32_t* ncols = nullptr;  // [B] active focal count per bin (sorted order)
     double* npart = nullptr;   // [2 nf_max][nr]
-    double* norm0 = nullptr;   // [nf_max]
+    double* norm0 = nullptr;   // [nf_max] norm the 16-bit X of the series is scaled by (||G_d||, then ||rho||)
+    double* gdnorm = nullptr;  // [nf_max] ||G_d||: scale of the 16-bit X of the G assembly (f1 fields)
     double* nlast = nullptr;   // [nf_max] norm of the last N (scales 16-bit X)
     float* xscale = nullptr;   // [3 nf_max] scale stored with 16-bit X
     double* norms = nullptr;   // [norm_cap][nf_max]

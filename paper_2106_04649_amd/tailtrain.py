@@ -140,7 +140,7 @@ def build_dataset(seeds, k, T, gen, rprec=0):
         xs.append(x)
         ys.append(y)
         ms.append(m)
-        if (i + 1) % 16 == 0:
+        if (i + 1) % (16 if len(seeds) > 64 else 1) == 0:
             log(f"dataset {i + 1}/{len(seeds)} models ({time.perf_counter() - t0:.1f} s)")
     solver.destroy()
     return torch.cat(xs), torch.cat(ys), torch.cat(ms)
@@ -249,6 +249,7 @@ def evaluate(params, seeds, k, T, gen, rprec=0):
             if res is not None:
                 row[name]["judge_residual"] = res
         rows.append(row)
+        log(f"evaluated model {len(rows)}/{len(seeds)}")
     solver.destroy()
     return rows
 

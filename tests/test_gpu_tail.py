@@ -133,3 +133,21 @@ def test_tail_state_errors():
         mk.mk_tail_apply(plan, 2)                      # once per series
     assert ei.value.status == mk.MK_ERR_STATE
     mk.mk_destroy(plan)
+
+
+@pytest.mark.parametrize("rprec", [1, 2])
+def test_restart_then_G_with_16bit_R(rprec):
+    """16-bit R: after the restart the series' X scale is the (small) residual
+    norm; the G assembly must keep f1+ and f1- on the scale of G_d, or its
+    16-bit spectra overflow.  Three focal points put G (six columns) on the
+    matrix cores with 16-bit X."""
+    say(f"restart + G, rprec {rprec}")
+    p = small_problem(seed=75, n=24, nt=128, nf=3, niter=8)
+    g = _gpu(p, 1, 2, rprec=rprec)
+    r = _ref(p, 1, 2)
+    tol = {1: 2e-3, 2: 2e-2}[rprec]
+    for key in FIELD_NAMES:
+        assert np.all(np.isfinite(g[key])), key
+        e = max(rel_l2(g[key][f], r[key][f]) for f in range(p.nf))
+        say(f"  {key}: {e:.2e}")
+        assert e <= tol, (key, e)
