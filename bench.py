@@ -47,7 +47,7 @@ PEAK_TFLOPS = {0: 157.3, 1: 2500.0, 2: 2500.0}     # dense MFMA: fp32, fp16, bf1
 # for the kernel source it was measured on (sha256 prefix of the file).
 TRAFFIC = {
     "k_contract_c64": {"source": "paper_2106_04649_amd/csrc/k_contract.hip",
-                       "sha": "3c2cd1184d5dae5c", "bytes": 3070776158,
+                       "sha": "576a68ac9b5a34b2", "bytes": 3006353126,
                        "profile": "profiles/k_contract_c64_601x601_nt2048_nf1.md"},
 }
 
@@ -284,6 +284,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-combined", action="store_true", help="skip the FP16 + learned-tail schedule search")
     ap.add_argument("--graph", action="store_true", help="replay the passes as HIP graphs")
     args = ap.parse_args()
 
@@ -372,7 +373,7 @@ def main() -> int:
                 avg_s, times, variant = profile_contract(pb, rprec)
                 flops = 8.0 * nr * nr * B * pb.nf
                 rb = 8 if rprec == 0 else 4
-                xb = 8 if variant == 0 or rprec == 0 else 4
+                xb = 8      # complex64 X, or 16-bit X as hi + lo planes (the default)
                 nbytes = contract_bytes(nr, nr, B, pb.nf, r_bytes=rb, x_bytes=xb)
                 tf = flops / avg_s / 1e12
                 gbs = nbytes / avg_s / 1e9
@@ -391,7 +392,7 @@ def main() -> int:
         f32 = batched["paths"]["fp32"]["iters_per_s"]
         f16 = batched["paths"]["fp16"]["iters_per_s"]
         batched["fp16_over_fp32"] = round(f16 / f32, 3)
-        combined = combined_path(pb, args, sample, ref, batched)
+        combined = None if args.no_combined else combined_path(pb, args, sample, ref, batched)
         if combined is not None:
             batched["combined"] = combined
 

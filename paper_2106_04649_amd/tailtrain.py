@@ -281,6 +281,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "tailnet_k4.npz"))
     ap.add_argument("--report", default=None)
+    ap.add_argument("--eval-only", default=None, metavar="NPZ",
+                    help="skip training: evaluate the network saved in NPZ on the held-out models")
     args = ap.parse_args(argv)
 
     import torch
@@ -296,6 +298,18 @@ def main(argv=None):
         gen = lambda s: medium_problem_gpu(int(s), nf=args.nf)     # noqa: E731
         train_seeds = list(range(5000, 5000 + args.train))
         hold_seeds = list(range(15000, 15000 + args.holdout))
+    if args.eval_only:
+        saved = np.load(args.eval_only)
+        params = saved["params"].astype(np.float32)
+        rows = evaluate(params, hold_seeds, int(saved["k"]), int(saved["T"]), gen, args.rprec)
+        report = {"workload": args.workload, "rprec": args.rprec, "network": os.path.basename(args.eval_only),
+                  "holdout_models": len(hold_seeds), "k": int(saved["k"]), "T": int(saved["T"]),
+                  "summary": summarise(rows)}
+        if args.report:
+            with open(args.report, "w") as fh:
+                json.dump({"report": report, "rows": rows}, fh)
+        print(json.dumps(report), flush=True)
+        return 0
     log(f"building the training set ({args.train} models)")
     X, Y, M = build_dataset(train_seeds, args.k, args.T, gen, args.rprec)
     log(f"training set: {X.shape[0]} traces")
