@@ -204,12 +204,13 @@ def _errs(got, ref, n):
 
 
 def combined_path(pb, args, sample, ref, batched, tol=1e-3):
-    """FP16 R + batched + learned series tail, against plain FP32 batched.
+    """FP16 R + batched + series tail, against plain FP32 batched.
 
-    The schedule (extra passes after the tail) is the shortest that keeps
+    Each path's schedule (passes after the tail) is the shortest that keeps
     every output within `tol` of the FP64 oracle on the sampled focal points;
-    plain FP32 is timed at the workload's 32 passes and, for the stricter
-    comparison, at its own shortest pass count reaching the same accuracy.
+    the plain paths are timed at their own shortest pass counts reaching the
+    same accuracy.  Paths: the learned tail (network), the geometric tail, the
+    restart alone (no tail), plain FP16 R and plain FP32 R.
     """
     if not os.path.exists(TAIL_WEIGHTS):
         log(f"no trained tail network at {TAIL_WEIGHTS}: combined path skipped")
@@ -219,15 +220,15 @@ def combined_path(pb, args, sample, ref, batched, tol=1e-3):
     out = {"tol": tol, "k": k, "T": T, "weights": os.path.relpath(TAIL_WEIGHTS, ROOT)}
     n = len(sample)
     r16 = Runner(pb, rprec=1, niter=0, tail=(params, k, T, 0, 0))
+    p16 = Runner(pb, rprec=1, niter=32)
     r32 = Runner(pb, rprec=0, niter=32)
 
     def errors(r):
         r.step()
         return _errs(r.fields(sample), ref, n)
 
-    # shortest schedules reaching tol
-    sched = {}
-    for mode, name in ((0, "learned"), (2, "no_tail")):
+    sched, timing = {}, {}
+    for mode, name in ((0, "learned"), (1, "geometric"), (2, "no_tail")):
         sched[name] = None
         for extra in (0, 1, 2, 3, 4, 6, 8, 12):
             r16.tail = (params, k, T, mode, extra)
@@ -235,38 +236,30 @@ def combined_path(pb, args, sample, ref, batched, tol=1e-3):
             if max(e.values()) <= tol:
                 sched[name] = {"extra": extra, "syntheses": k + 2 + extra, "err": e}
                 break
-    sched["plain_fp32"] = None
-    for P in range(2, 33):
-        r32.niter = P
-        e = errors(r32)
-        if max(e.values()) <= tol:
-            sched["plain_fp32"] = {"passes": P, "err": e}
-            break
+        if sched[name] is not None:
+            timing[name] = r16.time(args.steps, args.warmup) / args.steps
+    for name, r in (("plain_fp16", p16), ("plain_fp32", r32)):
+        sched[name] = None
+        for P in range(2, 33):
+            r.niter = P
+            e = errors(r)
+            if max(e.values()) <= tol:
+                sched[name] = {"passes": P, "err": e}
+                timing[name] = r.time(args.steps, args.warmup) / args.steps
+                break
+    for r in (r16, p16, r32):
+        r.destroy()
     out["schedules"] = sched
-    log("schedules: " + json.dumps({k_: (v or {}).get("syntheses", (v or {}).get("passes")) for k_, v in sched.items()}))
-    if sched.get("learned") is None:
-        r16.destroy()
-        r32.destroy()
-        return out
-    r16.tail = (params, k, T, 0, sched["learned"]["extra"])
-    wl = r16.time(args.steps, args.warmup)
-    wp = None
-    if sched.get("plain_fp32"):
-        r32.niter = sched["plain_fp32"]["passes"]
-        wp = r32.time(args.steps, args.warmup)
-    r16.destroy()
-    r32.destroy()
+    out["ms_per_step"] = {k_: round(v * 1e3, 3) for k_, v in timing.items()}
     t32 = batched["paths"]["fp32"]["ms_per_step"] / 1e3
-    tl = wl / args.steps
-    out["ms_per_step"] = round(tl * 1e3, 3)
-    out["solves_per_s"] = round(pb.nf / tl, 2)
-    out["plain_fp32_32pass_solves_per_s"] = round(pb.nf / t32, 2)
-    out["speedup_vs_plain_fp32_32pass"] = round(t32 / tl, 3)
-    if wp:
-        out["plain_fp32_same_tol_ms_per_step"] = round(wp * 1e3 / args.steps, 3)
-        out["speedup_vs_plain_fp32_same_tol"] = round((wp / args.steps) / tl, 3)
-    log(f"combined: {out.get('speedup_vs_plain_fp32_32pass')}x vs plain FP32 (32 passes), "
-        f"{out.get('speedup_vs_plain_fp32_same_tol')}x vs plain FP32 at the same accuracy")
+    out["plain_fp32_32pass_ms_per_step"] = round(t32 * 1e3, 3)
+    if "plain_fp32" in timing:
+        base = timing["plain_fp32"]
+        out["speedup_vs_plain_fp32_same_tol"] = {k_: round(base / v, 3) for k_, v in timing.items()}
+    out["speedup_vs_plain_fp32_32pass"] = {k_: round(t32 / v, 3) for k_, v in timing.items()}
+    log("combined: schedules " + json.dumps({k_: (v or {}).get("syntheses", (v or {}).get("passes"))
+                                             for k_, v in sched.items()}) +
+        " speedup vs plain FP32 at the same accuracy " + json.dumps(out.get("speedup_vs_plain_fp32_same_tol")))
     return out
 
 

@@ -27,7 +27,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ x, c
     extern __shared__ float xs[];                  // [C][64 + 2 halo]
     const int n = blockIdx.x;
     const int t0 = blockIdx.y * 64;
-    const int og = blockIdx.z * 4 + (threadIdx.x >> 6);
+    // the output group is uniform over a wave: say so, so that the weights
+    // come through the scalar cache and the bounds checks do not diverge
+    const int og = __builtin_amdgcn_readfirstlane(blockIdx.z * 4 + (threadIdx.x >> 6));
     const int tl = threadIdx.x & 63;
     const int halo = d * kHalf;
     const int W64 = 64 + 2 * halo;
@@ -43,14 +45,31 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ x, c
     float acc[OPT];
 #pragma unroll
     for (int i = 0; i < OPT; ++i) acc[i] = (o0 + i < O && b) ? b[o0 + i] : 0.f;
+    // channel by channel: the five taps of one (output, channel) pair are
+    // contiguous, so they come in one scalar load of five words; the sum over
+    // taps and channels keeps the order c, then j
+    const int nout = min(OPT, O - o0);            // uniform
     for (int c = 0; c < C; ++c) {
         const float* xr = xs + c * W64 + tl;
+        float xv[kTaps];
 #pragma unroll
-        for (int j = 0; j < kTaps; ++j) {
-            const float xv = xr[j * d];
+        for (int j = 0; j < kTaps; ++j) xv[j] = xr[j * d];
+        if (nout == OPT) {
 #pragma unroll
-            for (int i = 0; i < OPT; ++i)
-                if (o0 + i < O) acc[i] = fmaf(W[((size_t)(o0 + i) * C + c) * kTaps + j], xv, acc[i]);
+            for (int i = 0; i < OPT; ++i) {
+                const float* w5 = W + ((size_t)(o0 + i) * C + c) * kTaps;
+#pragma unroll
+                for (int j = 0; j < kTaps; ++j) acc[i] = fmaf(w5[j], xv[j], acc[i]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < OPT; ++i) {
+                if (i < nout) {
+                    const float* w5 = W + ((size_t)(o0 + i) * C + c) * kTaps;
+#pragma unroll
+                    for (int j = 0; j < kTaps; ++j) acc[i] = fmaf(w5[j], xv[j], acc[i]);
+                }
+            }
         }
     }
     const int t = t0 + tl;
