@@ -220,29 +220,31 @@ mk_status mk_profile(mk_plan_t plan, int32_t kind, double* total_ms, int64_t* la
  * N_0 .. N_{k-1} of one trace (k channels over a window of T samples centred
  * on t = 0, normalised per trace) to two channels: the even-pass and the
  * odd-pass sums of the remaining terms of the series.
- *   conv(k -> 64, 5 taps, dilation 1), ReLU, conv(64 -> 64, 5, dilation 4),
- *   ReLU, conv(64 -> 2, 5, dilation 16); zero padding outside the window.
- * Parameters: one FP32 vector, W1 [64][k][5], b1 [64], W2 [64][64][5],
- * b2 [64], W3 [2][64][5], b3 [2].  The forward pass is meant to run on
+ *   conv(k -> H, 5 taps, dilation 1), ReLU, conv(H -> H, 5, dilation 4),
+ *   ReLU, conv(H -> 2, 5, dilation 16); zero padding outside the window;
+ *   H ("hidden", 1..128) hidden channels.
+ * Parameters: one FP32 vector, W1 [H][k][5], b1 [H], W2 [H][H][5],
+ * b2 [H], W3 [2][H][5], b3 [2].  The forward pass is meant to run on
  * BF16-rounded parameters (mk_net_round / the wq output of mk_net_adam).
  * Every pointer below is device memory owned by the caller; work is
  * enqueued on `stream` (hipStream_t, NULL = null stream) and not
  * synchronised.  Errors: MK_ERR_ARG (NULL, bad sizes), MK_ERR_HIP; the
  * message is in mk_net_last_error().
  */
-int32_t mk_net_param_count(int32_t k);   /* -1 when k is outside [1, 16] */
+int32_t mk_net_param_count(int32_t k, int32_t hidden);   /* -1 when k or hidden is out of range */
 const char* mk_net_last_error(void);
 
-/* Forward pass: x [N][k][T] -> y [N][2][T]; work [2][N][64][T] keeps the
+/* Forward pass: x [N][k][T] -> y [N][2][T]; work [2][N][hidden][T] keeps the
  * hidden activations for mk_net_backward. */
-mk_status mk_net_forward(const float* params, const float* x, int32_t N, int32_t k, int32_t T,
+mk_status mk_net_forward(const float* params, const float* x, int32_t N, int32_t k, int32_t hidden, int32_t T,
                          float* work, float* y, void* stream);
 
 /* Gradient of sum(gy * y) with respect to every parameter -> grads (same
  * layout as params); work as left by mk_net_forward; work2 holds
- * 2 N 64 T + 64 * 64 * 5 floats of scratch. */
+ * 2 N hidden T + hidden * hidden * 5 floats of scratch. */
 mk_status mk_net_backward(const float* params, const float* x, const float* work, const float* gy,
-                          int32_t N, int32_t k, int32_t T, float* grads, float* work2, void* stream);
+                          int32_t N, int32_t k, int32_t hidden, int32_t T, float* grads, float* work2,
+                          void* stream);
 
 /* Masked mean squared error over both output channels: loss (one double)
  * = sum(((y - target) mask)^2) / count, gy = 2 (y - target) mask / count;
@@ -269,9 +271,11 @@ mk_status mk_tail_record(mk_plan_t plan, int32_t k, int32_t T);
 
 /*
  * mk_tail_load -- load the tail network's parameters (host FP32, layout of
- * mk_net_param_count(k) for the recorded k); they are rounded to BF16.
- * Errors: MK_ERR_ARG (NULL, wrong count, non-finite), MK_ERR_STATE (no
- * mk_tail_record), MK_ERR_OOM, MK_ERR_HIP.
+ * mk_net_param_count(k, hidden) for the recorded k; the hidden width follows
+ * from count); they are rounded to BF16.  Recording again with another k or
+ * T drops the loaded network.
+ * Errors: MK_ERR_ARG (NULL, a count that fits no hidden width, non-finite),
+ * MK_ERR_STATE (no mk_tail_record), MK_ERR_OOM, MK_ERR_HIP.
  */
 mk_status mk_tail_load(mk_plan_t plan, const float* params, int32_t count);
 

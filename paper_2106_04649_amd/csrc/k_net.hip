@@ -1,9 +1,11 @@
 // Kernels of the series-tail network: a 3-layer dilated 1D convolution over
 // the first k Neumann iterates of a trace, trained and run on the GPU.
 //
-//   conv(k -> 64, 5 taps, dilation 1), ReLU,
-//   conv(64 -> 64, 5 taps, dilation 4), ReLU,
-//   conv(64 -> 2, 5 taps, dilation 16)
+//   conv(k -> H, 5 taps, dilation 1), ReLU,
+//   conv(H -> H, 5 taps, dilation 4), ReLU,
+//   conv(H -> 2, 5 taps, dilation 16)
+//
+// with H hidden channels (64 for the reference architecture).
 //
 // y[n][o][t] = b[o] + sum_c sum_j W[o][c][j] x[n][c][t + d (j - 2)], zero
 // outside [0, T).  Activations are [N][C][T] float32.  The forward pass uses
@@ -206,9 +208,12 @@ hipError_t conv_fwd(const float* x, const float* W, const float* b, float* y, in
     const int halo = d * kHalf;
     const size_t lds = (size_t)C * (64 + 2 * halo) * sizeof(float);
     if (lds > 65536) return hipErrorInvalidValue;
-    if (O >= 16) {
+    if (O >= 64) {
         const dim3 grid(N, (T + 63) / 64, (O + 63) / 64);
         hipLaunchKernelGGL(k_conv_fwd<16>, grid, dim3(256), lds, s, x, W, b, y, C, O, T, d, relu);
+    } else if (O >= 16) {
+        const dim3 grid(N, (T + 63) / 64, (O + 15) / 16);
+        hipLaunchKernelGGL(k_conv_fwd<4>, grid, dim3(256), lds, s, x, W, b, y, C, O, T, d, relu);
     } else {
         const dim3 grid(N, (T + 63) / 64, (O + 3) / 4);
         hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), lds, s, x, W, b, y, C, O, T, d, relu);
@@ -220,13 +225,11 @@ hipError_t conv_fwd(const float* x, const float* W, const float* b, float* y, in
 
 // Parameter layout (one FP32 vector): W1 [H][k][5], b1 [H], W2 [H][H][5],
 // b2 [H], W3 [2][H][5], b3 [2].
-int net_param_count(int k) {
-    const int H = kNetHidden;
+int net_param_count(int k, int H) {
     return H * k * kTaps + H + H * H * kTaps + H + 2 * H * kTaps + 2;
 }
 
-static void offsets(int k, int* o) {
-    const int H = kNetHidden;
+static void offsets(int k, int H, int* o) {
     o[0] = 0;                          // W1
     o[1] = o[0] + H * k * kTaps;       // b1
     o[2] = o[1] + H;                   // W2
@@ -235,11 +238,10 @@ static void offsets(int k, int* o) {
     o[5] = o[4] + 2 * H * kTaps;       // b3
 }
 
-hipError_t net_forward(const float* P, const float* x, int N, int k, int T, float* a1, float* a2,
+hipError_t net_forward(const float* P, const float* x, int N, int k, int H, int T, float* a1, float* a2,
                        float* y, hipStream_t s) {
-    const int H = kNetHidden;
     int o[6];
-    offsets(k, o);
+    offsets(k, H, o);
     // a1, a2 hold post-ReLU activations; the ReLU masks come from them (h > 0 <=> a > 0)
     hipError_t e = conv_fwd(x, P + o[0], P + o[1], a1, N, k, H, T, kNetDil[0], 1, s);
     if (e == hipSuccess) e = conv_fwd(a1, P + o[2], P + o[3], a2, N, H, H, T, kNetDil[1], 1, s);
@@ -248,10 +250,9 @@ hipError_t net_forward(const float* P, const float* x, int N, int k, int T, floa
 }
 
 hipError_t net_backward(const float* P, const float* x, const float* a1, const float* a2, const float* gy,
-                        int N, int k, int T, float* G, float* g1, float* g2, float* wt, hipStream_t s) {
-    const int H = kNetHidden;
+                        int N, int k, int H, int T, float* G, float* g1, float* g2, float* wt, hipStream_t s) {
     int o[6];
-    offsets(k, o);
+    offsets(k, H, o);
     const int64_t nact = (int64_t)N * H * T;
     const unsigned gblk = (unsigned)std::min<int64_t>((nact + 255) / 256, 16384);
     // layer 3

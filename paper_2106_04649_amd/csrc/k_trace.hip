@@ -45,6 +45,14 @@ __device__ __forceinline__ float2 twid(const float2* tq, int idx) {
 // the neighbouring traces of the cooperative phases) spread over all banks.
 __device__ __forceinline__ int zi(int k) { return k + (k >> 4); }
 
+// zi(base + q S): for S a multiple of 16 this is zi(base) + q (S + S/16), a
+// constant offset from one address (the form the LDS instructions take).
+template <int S>
+__device__ __forceinline__ int zstep(int base, int q) {
+    if constexpr (S % 16 == 0) return zi(base) + q * (S + S / 16);
+    else return zi(base + q * S);
+}
+
 // Barrier among the threads that own one trace: the whole block, or one
 // wave, whose lanes run in lockstep and whose LDS accesses complete in
 // issue order, so that only the compiler has to be kept from reordering.
@@ -233,7 +241,7 @@ __device__ __forceinline__ void fft16_pass(float2* z, const float2* __restrict__
         const int j = lane + 64 * p;
         if (j < NB) {
 #pragma unroll
-            for (int q = 0; q < R; ++q) v[p][q] = z[zi(j + q * NB)];
+            for (int q = 0; q < R; ++q) v[p][q] = z[zstep<NB>(j, q)];
         }
     }
     trace_sync<64>();
@@ -248,8 +256,14 @@ __device__ __forceinline__ void fft16_pass(float2* z, const float2* __restrict__
             }
             dft_reg<R, DIR>(v[p]);
             const int base = (j - k) * R + k;
+            if constexpr (NS == 1 && R == 16) {      // base = 16 j: zi(base + m) = zi(base) + m
+                float2* zb = z + zi(base);
 #pragma unroll
-            for (int m = 0; m < R; ++m) z[zi(base + m * NS)] = v[p][out_reg<R>(m)];
+                for (int m = 0; m < R; ++m) zb[m] = v[p][out_reg<R>(m)];
+            } else {
+#pragma unroll
+                for (int m = 0; m < R; ++m) z[zstep<NS>(base, m)] = v[p][out_reg<R>(m)];
+            }
         }
     }
     trace_sync<64>();
@@ -292,25 +306,127 @@ __device__ __forceinline__ float2 unpack_bin(const float2* z, const float2* __re
     return make_float2(e.x + wd.y, e.y - wd.x);          // E - i W^k D
 }
 
+// Packed spectrum Z[k] = E[k] + i O[k] of the even/odd samples, from bins
+// xk = X[k] and xm = X[M - k] of the real trace's spectrum; t = W^k.
+__device__ __forceinline__ float2 pack_bins(float2 xk, float2 xm, float2 t) {
+    const float2 e = make_float2(0.5f * (xk.x + xm.x), 0.5f * (xk.y - xm.y));
+    const float2 d = make_float2(0.5f * (xk.x - xm.x), 0.5f * (xk.y + xm.y));
+    const float2 o = make_float2(d.x * t.x + d.y * t.y, d.y * t.x - d.x * t.y);   // d * conj(t)
+    return make_float2(e.x - o.y, e.y + o.x);
+}
+
+// Barrier for LDS traffic only: outstanding global loads stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// ---- the fused pass (one wave per trace, M = 1024 or 2048) ----------------
+// The inverse transform's first pass packs its inputs on load, its last pass
+// leaves the time samples in registers, and the forward transform's first
+// pass starts from those registers: lane l holds element l + 64 e of the
+// trace after the inverse transform, which is exactly the set of inputs its
+// first forward butterflies take.
+
+// First inverse pass (span 1, radix 16) fed from the half spectrum in LDS:
+// input i is packed from bins i and M - i (slot 0 holds the real DC and
+// Nyquist values).
+template <int NT>
+__device__ __forceinline__ void inv_first_pass(float2* z, const float2* tq, int lane) {
+    constexpr int M = NT / 2, NB = M / 16, PB = NB / 64;
+    static_assert(NB % 64 == 0, "whole butterflies per lane");
+    float2 v[PB][16];
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = lane + 64 * p, i = j + q * NB;
+            // bin M - i sits at zi(M - q NB) - (j + ceil(j / 16)); for i = 0 this
+            // reads padding, replaced below
+            const int jr = j + ((j + 15) >> 4);
+            float2 xk = z[zstep<NB>(j, q)], xm = (z - jr)[(M - q * NB) + (M - q * NB) / 16];
+            if (i == 0) {
+                xm = make_float2(xk.y, 0.f);
+                xk.y = 0.f;
+            }
+            v[p][q] = pack_bins(xk, xm, twid<-1, NT>(tq, i));
+        }
+    }
+    trace_sync<64>();
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+        dft_reg<16, +1>(v[p]);
+        float2* zb = z + zi(16 * (lane + 64 * p));
+#pragma unroll
+        for (int m = 0; m < 16; ++m) zb[m] = v[p][out_reg<16>(m)];
+    }
+    trace_sync<64>();
+}
+
+// Last inverse pass (radix R, span M / R) kept in registers: output m of
+// butterfly p is element lane + 64 (p + PB m).
+template <int NT, int R>
+__device__ __forceinline__ void inv_last_pass(const float2* z, const float2* tq, int lane,
+                                              float2 (&v)[NT / 2 / (64 * R)][R]) {
+    constexpr int M = NT / 2, NB = M / R, PB = NB / 64;
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[p][q] = z[zstep<NB>(lane + 64 * p, q)];
+    }
+    trace_sync<64>();
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+        const int k = lane + 64 * p;                 // < span: k = j
+#pragma unroll
+        for (int q = 1; q < R; ++q) v[p][q] = cmul(v[p][q], twid<+1, NT>(tq, q * k * 2));
+        dft_reg<R, +1>(v[p]);
+    }
+}
+
+// First forward pass (span 1, radix 16) on registers: x[e] is element lane + 64 e.
+template <int NT>
+__device__ __forceinline__ void fwd_first_pass(float2* z, const float2 (&x)[NT / 128], int lane) {
+    constexpr int M = NT / 2, NB = M / 16, PB = NB / 64;
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+        float2 v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = x[p + PB * q];    // input lane + 64 p + q NB
+        dft_reg<16, -1>(v);
+        float2* zb = z + zi(16 * (lane + 64 * p));
+#pragma unroll
+        for (int m = 0; m < 16; ++m) zb[m] = v[out_reg<16>(m)];
+    }
+}
+
 // TPT threads own one trace: 64 (one wave, four traces per block) when the
 // launch has many traces, 256 (the whole block) when it has few, so that a
 // one-focal pass still spreads over every CU.  The traces of a block are
 // consecutive receivers of one output column, and the block moves their
 // spectra between HBM and LDS together: neighbouring lanes take neighbouring
 // receivers of one bin, so each bin of Y is read and each bin of X written
-// as one contiguous run of TPB elements.
+// as one contiguous run of TPB elements.  Every global load a phase needs is
+// issued before the first of them is used.
 template <int NT, int MODE, int TPT>
-__global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
+__global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trace(TraceArgs a) {
     constexpr int M = NT / 2;
     constexpr int TPB = 256 / TPT;          // traces per block
     constexpr int KSTR = 256 / TPB;         // bins per cooperative sweep
-    constexpr int ZS = M + M / 16;          // float2 per trace region (padded, see zi)
+    constexpr int NY = (M + KSTR - 1) / KSTR;
+    // float2 per trace region: padded (see zi), plus 8 so that the traces of
+    // a block start 16 banks apart
+    constexpr int ZS = M + M / 16 + 8;
     constexpr int PM = (M + TPT - 1) / TPT;
+    constexpr int TQN = NT / 4, TQP = (TQN + 255) / 256;
     constexpr bool GMODE = MODE == TM_GFWD || MODE == TM_GOUT;
+    constexpr bool YIN = MODE == TM_ITER || MODE == TM_GOUT || MODE == TM_RST1 || MODE == TM_RST2;
+    constexpr bool FUSED = (MODE == TM_ITER || MODE == TM_RST1) && TPT == 64 && (M == 1024 || M == 2048);
     __shared__ float2 lds[TPB * ZS];
-    __shared__ float2 tq[NT / 4];            // quarter twiddle table (see twid)
+    __shared__ float2 tq[TQN];               // quarter twiddle table (see twid)
     __shared__ double red[TPT > 64 ? 4 : 1];
-    const int wv = threadIdx.x / TPT;       // trace slot in the block
+    const int wv = TPT == 64 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64) : 0;   // trace slot
     const int lane = threadIdx.x % TPT;     // thread within the trace
     float2* z = lds + wv * ZS;
 
@@ -321,8 +437,6 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     const int per_xcd = (nblk + 7) >> 3;
     const int blk = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
     if (blk >= nblk) return;                // uniform over the block
-    for (int i = threadIdx.x; i < NT / 4; i += 256) tq[i] = a.tw[i];
-    __syncthreads();
     const int fo = blk / nrg;               // output column
     const int r0 = (blk - fo * nrg) * TPB;  // first receiver of the block
     const bool valid = r0 + wv < a.nr;
@@ -340,188 +454,331 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
     }
     const size_t tbase = ((size_t)f * a.nr + r) * NT;
     const float s = a.scale;
+    // window of the mute, |t| < L (loaded first: the f1 addresses depend on it)
+    [[maybe_unused]] int L = 0;
+    if constexpr (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2) L = a.itd[f * a.nr + r] - a.shift;
+    float2 tqv[TQP];
+#pragma unroll
+    for (int i = 0; i < TQP; ++i) tqv[i] = a.tw[min((int)threadIdx.x + 256 * i, TQN - 1)];
 
-    // ---- spectrum -> time (TM_ITER, TM_GOUT) --------------------------------
-    if (MODE == TM_ITER || MODE == TM_GOUT || MODE == TM_RST1 || MODE == TM_RST2) {
+    // Y bins in [flo, fhi]; the others are zero (clamped, always valid, address)
+    float2 yv[NY];
+    float ynyq = 0.f;
+    if constexpr (YIN) {
         const float2* Yt = a.Y + (size_t)fo * a.B * a.nr + rc;
-        auto ybin = [&](int k) {
-            return (k >= flo && k <= fhi) ? Yt[(size_t)(k - a.lo) * a.nr] : make_float2(0.f, 0.f);
+        auto yload = [&](int k) {
+            // the load is unconditional and its bits are masked: a selected
+            // load would be sunk into a branch and waited for on its own
+            const float2 v = Yt[(size_t)(min(max(k, a.lo), hi) - a.lo) * a.nr];
+            const uint32_t msk = ((k >= flo) & (k <= fhi)) ? 0xFFFFFFFFu : 0u;
+            return make_float2(__uint_as_float(__float_as_uint(v.x) & msk),
+                               __uint_as_float(__float_as_uint(v.y) & msk));
         };
+#pragma unroll
+        for (int i = 0; i < NY; ++i) yv[i] = yload(ck + KSTR * i);
+        ynyq = yload(M).x;
+    }
+
+    auto win = [&](int u) -> bool {         // sample u of the trace is inside the mute window
+        const int sg = u < M ? u : u - NT;
+        return (sg < L) & (-sg < L) & (u != M);   // no short circuit: no branches
+    };
+    float* acc = (a.parity == 0) ? a.f1m : a.f1p;
+
+#pragma unroll
+    for (int i = 0; i < TQP; ++i) {
+        if constexpr (TQN % 256 == 0) tq[threadIdx.x + 256 * i] = tqv[i];      // unconditional: the load stays early
+        else if ((int)threadIdx.x + 256 * i < TQN) tq[threadIdx.x + 256 * i] = tqv[i];
+    }
+    if constexpr (YIN) {
         // every stored bin is read once: slot k holds bin k, slot 0 the real
         // parts of DC and Nyquist (both real: their imaginary parts are dropped)
         float2* zc = lds + cs * ZS;
-        for (int k = ck; k < M; k += KSTR) {
-            float2 v = ybin(k);
-            if (k == 0) v.y = ybin(M).x;
-            zc[zi(k)] = v;
-        }
-        __syncthreads();
-        // packed spectrum Z[k] = E[k] + i O[k] of the even/odd samples, from
-        // bins k and M - k; each thread rewrites its own pair in place
-        auto pack = [](float2 xk, float2 xm, float2 t) {
-            const float2 e = make_float2(0.5f * (xk.x + xm.x), 0.5f * (xk.y - xm.y));
-            const float2 d = make_float2(0.5f * (xk.x - xm.x), 0.5f * (xk.y + xm.y));
-            const float2 o = make_float2(d.x * t.x + d.y * t.y, d.y * t.x - d.x * t.y);   // d * conj(W^k)
-            return make_float2(e.x - o.y, e.y + o.x);
-        };
-        for (int k = lane; k <= M / 2; k += TPT) {
-            const float2 zk = z[zi(k)], zm = z[zi((M - k) & (M - 1))];
-            if (k == 0) {
-                z[zi(0)] = pack(make_float2(zk.x, 0.f), make_float2(zk.y, 0.f), make_float2(1.f, 0.f));
-            } else {
-                z[zi(k)] = pack(zk, zm, twid<-1, NT>(tq, k));
-                if (k != M - k) z[zi(M - k)] = pack(zm, zk, twid<-1, NT>(tq, M - k));
+#pragma unroll
+        for (int i = 0; i < NY; ++i) {
+            const int k = ck + KSTR * i;
+            if (k < M) {
+                float2 v = yv[i];
+                if (k == 0) v.y = ynyq;
+                zc[zi(k)] = v;
             }
         }
-        trace_sync<TPT>();
-        fft_trace<NT, +1, TPT>(z, tq, lane);
-        // z[m] = (RN[2m], RN[2m+1]) / s
     }
+    lds_barrier();
 
     double nacc = 0.0;
-    float2 out[PM];
-
-    if (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2) {
-        const int L = a.itd[f * a.nr + r] - a.shift;        // keep |t| < L
-        float* acc = (a.parity == 0) ? a.f1m : a.f1p;
-        const int hT = a.hist_T >> 1;
-        float* hrow = (MODE == TM_ITER && a.hist && a.rec_slot >= 0)
-                          ? a.hist + (((size_t)f * a.nr + r) * a.hist_k + a.rec_slot) * a.hist_T
-                          : nullptr;
+    if constexpr (FUSED) {
+        // ---- spectrum -> time -> mute -> spectrum, one LDS trip saved ----
+        constexpr int LOG2M = ilog2c(M);
+        constexpr int LOG2RL = (LOG2M % 4) == 0 ? 4 : LOG2M % 4;
+        constexpr int RL = 1 << LOG2RL, PBL = M / (64 * RL), QN = M / 64;
+        inv_first_pass<NT>(z, tq, lane);
+        fft16_passes<NT, +1, 16, LOG2M - 4 - LOG2RL>(z, tq, lane);
+        float2 x[QN];                           // element lane + 64 e: (RN[2 idx], RN[2 idx + 1]) / s
+        {
+            float2 v[PBL][RL];
+            inv_last_pass<NT, RL>(z, tq, lane, v);
 #pragma unroll
-        for (int p = 0; p < PM; ++p) {
-            const int m = lane + TPT * p;
-            if (m < M) {
-                const int t0 = 2 * m, t1 = 2 * m + 1;
-                const int s0 = t0 < M ? t0 : t0 - NT;
-                const int s1 = t1 < M ? t1 : t1 - NT;
-                const bool k0 = (s0 < L) && (-s0 < L) && (t0 != M);
-                const bool k1 = (s1 < L) && (-s1 < L);
-                // N[t] = -RN[(nt - t) mod nt] inside the window
-                const float n0 = k0 ? -s * z[zi((M - m) & (M - 1))].x : 0.f;
-                const float n1 = k1 ? -s * z[zi(M - 1 - m)].y : 0.f;
-                if (MODE == TM_ITER) {
-                    nacc += (double)n0 * n0 + (double)n1 * n1;
-                    if (valid && (k0 || k1)) {
-                        float2* pa = reinterpret_cast<float2*>(acc + tbase) + m;
-                        float2 o = *pa;
-                        if (a.parity == 0) {             // f1- -= N(-t)  ==  f1- += theta RN
-                            const float2 zm = z[zi(m)];
-                            if (k0) o.x += s * zm.x;
-                            if (k1) o.y += s * zm.y;
-                        } else {                          // f1+ += N
-                            o.x += n0;
-                            o.y += n1;
+            for (int p = 0; p < PBL; ++p) {
+#pragma unroll
+                for (int m = 0; m < RL; ++m) x[p + PBL * m] = v[p][out_reg<RL>(m)];
+            }
+        }
+        // The window is symmetric (theta(-t) = theta(t)), so the next field
+        // N = -theta RN(-t) is the time reverse of -Q with Q = theta RN: Q is
+        // transformed, and the reversal becomes X = -conj(FFT Q) at the end.
+#pragma unroll
+        for (int e = 0; e < QN; ++e) {
+            const int idx = lane + 64 * e;
+            const float q0 = win(2 * idx) ? s * x[e].x : 0.f;
+            const float q1 = win(2 * idx + 1) ? s * x[e].y : 0.f;
+            x[e] = make_float2(q0, q1);
+            nacc += (double)q0 * q0 + (double)q1 * q1;
+        }
+        if constexpr (MODE == TM_ITER) {
+            // Even passes add Q to f1- element by element.  Odd passes
+            // subtract Q(-t) from f1+: the pair at (M - idx) mod M holds
+            // samples -2 idx (element idx, x) and -(2 idx - 1) (element
+            // idx - 1, y).  The pairs outside the window are neither read
+            // nor written; all reads are issued before the first update.
+            float2* ap = reinterpret_cast<float2*>(acc + tbase);
+            const bool odd = a.parity != 0;
+            auto gidx = [&](int idx) { return odd ? (M - idx) & (M - 1) : idx; };
+            auto inw = [&](int idx) -> bool {
+                return valid & (win(2 * idx) | win(odd ? (2 * idx - 1) & (NT - 1) : 2 * idx + 1));
+            };
+            const float ylast = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[QN - 1].y), 63));
+            constexpr int FCH = 8;              // elements whose reads are in flight together
+#pragma unroll
+            for (int e0 = 0; e0 < QN; e0 += FCH) {
+                float2 o[FCH];
+#pragma unroll
+                for (int c = 0; c < FCH; ++c) {
+                    const int idx = lane + 64 * (e0 + c);
+                    o[c] = ap[inw(idx) ? gidx(idx) : 0];
+                }
+#pragma unroll
+                for (int c = 0; c < FCH; ++c) {
+                    const int e = e0 + c, idx = lane + 64 * e;
+                    // y of element idx - 1: lane - 1, or lane 63 of the previous e
+                    const float ya = __shfl(x[e].y, (lane + 63) & 63, 64);
+                    const float yb = e == 0 ? ylast
+                                            : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[e - 1].y), 63));
+                    const float2 dd = odd ? make_float2(-x[e].x, -(lane == 0 ? yb : ya)) : x[e];
+                    if (inw(idx)) ap[gidx(idx)] = make_float2(o[c].x + dd.x, o[c].y + dd.y);
+                }
+            }
+            const int hT = a.hist_T >> 1;
+            float* hrow = (a.hist && a.rec_slot >= 0)
+                              ? a.hist + (((size_t)f * a.nr + r) * a.hist_k + a.rec_slot) * a.hist_T
+                              : nullptr;
+            if (hrow && valid) {                // record N_i on the window |t| < T/2
+#pragma unroll
+                for (int e = 0; e < QN; ++e) {
+                    const int idx = lane + 64 * e;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int u = 2 * idx + c;
+                        const int sr = u == M ? -M : (u < M ? -u : NT - u);   // signed time of -u
+                        if (sr < hT && -sr <= hT) hrow[sr + hT] = -(c ? x[e].y : x[e].x);
+                    }
+                }
+            }
+        } else {                                // TM_RST1: f1- := theta S f1+ = Q
+            if (valid) {
+#pragma unroll
+                for (int e = 0; e < QN; ++e)
+                    reinterpret_cast<float2*>(a.f1m + tbase)[lane + 64 * e] = x[e];
+            }
+        }
+        fwd_first_pass<NT>(z, x, lane);
+        trace_sync<64>();
+        fft16_passes<NT, -1, 16, LOG2M - 4>(z, tq, lane);
+    } else {
+        // ---- spectrum -> time (TM_ITER, TM_GOUT, TM_RST1, TM_RST2) ------------
+        if constexpr (YIN) {
+            // packed spectrum from bins k and M - k; each thread rewrites its own pair in place
+            for (int k = lane; k <= M / 2; k += TPT) {
+                const float2 zk = z[zi(k)], zm = z[zi((M - k) & (M - 1))];
+                if (k == 0) {
+                    z[zi(0)] = pack_bins(make_float2(zk.x, 0.f), make_float2(zk.y, 0.f), make_float2(1.f, 0.f));
+                } else {
+                    z[zi(k)] = pack_bins(zk, zm, twid<-1, NT>(tq, k));
+                    if (k != M - k) z[zi(M - k)] = pack_bins(zm, zk, twid<-1, NT>(tq, M - k));
+                }
+            }
+            trace_sync<TPT>();
+            fft_trace<NT, +1, TPT>(z, tq, lane);
+            // z[m] = (RN[2m], RN[2m+1]) / s
+        }
+
+        float2 out[PM];
+        if constexpr (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2) {
+            const int hT = a.hist_T >> 1;
+            float* hrow = (MODE == TM_ITER && a.hist && a.rec_slot >= 0)
+                              ? a.hist + (((size_t)f * a.nr + r) * a.hist_k + a.rec_slot) * a.hist_T
+                              : nullptr;
+            // global operands first (clamped to the trace's first pair when unused)
+            float2 g0[PM], g1[PM];
+#pragma unroll
+            for (int p = 0; p < PM; ++p) {
+                const int m = min(lane + TPT * p, M - 1);
+                if constexpr (MODE == TM_ITER) {
+                    const bool w = valid && (win(2 * m) || win(2 * m + 1));
+                    g0[p] = reinterpret_cast<const float2*>(acc + tbase)[w ? m : 0];
+                } else if constexpr (MODE == TM_RST2) {
+                    g0[p] = reinterpret_cast<const float2*>(a.n0 + tbase)[m];
+                    g1[p] = reinterpret_cast<const float2*>(a.f1p + tbase)[m];
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < PM; ++p) {
+                const int m = lane + TPT * p;
+                if (m < M) {
+                    const int t0 = 2 * m, t1 = 2 * m + 1;
+                    const int s0 = t0 < M ? t0 : t0 - NT;
+                    const int s1 = t1 < M ? t1 : t1 - NT;
+                    const bool k0 = win(t0), k1 = win(t1);
+                    // N[t] = -RN[(nt - t) mod nt] inside the window
+                    const float n0 = k0 ? -s * z[zi((M - m) & (M - 1))].x : 0.f;
+                    const float n1 = k1 ? -s * z[zi(M - 1 - m)].y : 0.f;
+                    if constexpr (MODE == TM_ITER) {
+                        nacc += (double)n0 * n0 + (double)n1 * n1;
+                        if (valid && (k0 || k1)) {
+                            float2 o = g0[p];
+                            if (a.parity == 0) {             // f1- -= N(-t)  ==  f1- += theta RN
+                                const float2 zm = z[zi(m)];
+                                if (k0) o.x += s * zm.x;
+                                if (k1) o.y += s * zm.y;
+                            } else {                          // f1+ += N
+                                o.x += n0;
+                                o.y += n1;
+                            }
+                            reinterpret_cast<float2*>(acc + tbase)[m] = o;
                         }
-                        *pa = o;
+                        if (hrow && valid) {                  // record N_i on the window |t| < T/2
+                            if (s0 < hT && -s0 <= hT) hrow[s0 + hT] = n0;
+                            if (s1 < hT && -s1 <= hT) hrow[s1 + hT] = n1;
+                        }
+                        out[p] = make_float2(n0, n1);
+                    } else if constexpr (MODE == TM_RST1) {
+                        // f1- := theta S f1+ (overwrite); the field fed on is N' = -(theta RN)(-t)
+                        nacc += (double)n0 * n0 + (double)n1 * n1;
+                        if (valid) {
+                            const float2 zm = z[zi(m)];
+                            reinterpret_cast<float2*>(a.f1m + tbase)[m] =
+                                make_float2(k0 ? s * zm.x : 0.f, k1 ? s * zm.y : 0.f);
+                        }
+                        out[p] = make_float2(n0, n1);
+                    } else {
+                        // N'' = A^2 f1+; rho = N_-1 + N'' - f1+; f1+ := N_-1 + N''
+                        const float2 b0 = g0[p], fp = g1[p];
+                        const float2 nf2 = make_float2(b0.x + n0, b0.y + n1);
+                        const float2 rho = make_float2(nf2.x - fp.x, nf2.y - fp.y);
+                        nacc += (double)rho.x * rho.x + (double)rho.y * rho.y;
+                        if (valid) reinterpret_cast<float2*>(a.f1p + tbase)[m] = nf2;
+                        out[p] = rho;
                     }
-                    if (hrow && valid) {                  // record N_i on the window |t| < T/2
-                        if (s0 < hT && -s0 <= hT) hrow[s0 + hT] = n0;
-                        if (s1 < hT && -s1 <= hT) hrow[s1 + hT] = n1;
-                    }
-                    out[p] = make_float2(n0, n1);
-                } else if (MODE == TM_RST1) {
-                    // f1- := theta S f1+ (overwrite); the field fed on is N' = -(theta RN)(-t)
+                }
+            }
+            trace_sync<TPT>();
+#pragma unroll
+            for (int p = 0; p < PM; ++p) {
+                const int m = lane + TPT * p;
+                if (m < M) z[zi(m)] = out[p];
+            }
+        } else if constexpr (MODE == TM_INIT) {
+            const float* g = a.src + tbase;
+#pragma unroll
+            for (int p = 0; p < PM; ++p) {
+                const int m = min(lane + TPT * p, M - 1);
+                out[p] = make_float2(g[(NT - 2 * m) & (NT - 1)], g[NT - 2 * m - 1]);   // N_-1[t] = Gd[(nt - t) mod nt]
+            }
+#pragma unroll
+            for (int p = 0; p < PM; ++p) {
+                const int m = lane + TPT * p;
+                if (m < M) {
+                    const float n0 = out[p].x, n1 = out[p].y;
                     nacc += (double)n0 * n0 + (double)n1 * n1;
                     if (valid) {
-                        const float2 zm = z[zi(m)];
-                        reinterpret_cast<float2*>(a.f1m + tbase)[m] =
-                            make_float2(k0 ? s * zm.x : 0.f, k1 ? s * zm.y : 0.f);
+                        reinterpret_cast<float2*>(a.f1p + tbase)[m] = make_float2(n0, n1);
+                        reinterpret_cast<float2*>(a.f1m + tbase)[m] = make_float2(0.f, 0.f);
+                        if (a.n0) reinterpret_cast<float2*>(a.n0 + tbase)[m] = make_float2(n0, n1);
                     }
-                    out[p] = make_float2(n0, n1);
-                } else {
-                    // N'' = A^2 f1+; rho = N_-1 + N'' - f1+; f1+ := N_-1 + N''
-                    const float2 b0 = reinterpret_cast<const float2*>(a.n0 + tbase)[m];
-                    const float2 fp = reinterpret_cast<const float2*>(a.f1p + tbase)[m];
-                    const float2 nf2 = make_float2(b0.x + n0, b0.y + n1);
-                    const float2 rho = make_float2(nf2.x - fp.x, nf2.y - fp.y);
-                    nacc += (double)rho.x * rho.x + (double)rho.y * rho.y;
-                    if (valid) reinterpret_cast<float2*>(a.f1p + tbase)[m] = nf2;
-                    out[p] = rho;
+                    z[zi(m)] = make_float2(n0, n1);
                 }
             }
-        }
-        trace_sync<TPT>();
+        } else if constexpr (MODE == TM_FWDF) {
 #pragma unroll
-        for (int p = 0; p < PM; ++p) {
-            const int m = lane + TPT * p;
-            if (m < M) z[zi(m)] = out[p];
-        }
-    } else if (MODE == TM_INIT) {
-        const float* g = a.src + tbase;
+            for (int p = 0; p < PM; ++p)
+                out[p] = reinterpret_cast<const float2*>(a.f1p + tbase)[min(lane + TPT * p, M - 1)];
 #pragma unroll
-        for (int p = 0; p < PM; ++p) {
-            const int m = lane + TPT * p;
-            if (m < M) {
-                // N_-1[t] = Gd[(nt - t) mod nt]
-                const float n0 = g[(NT - 2 * m) & (NT - 1)];
-                const float n1 = g[NT - 2 * m - 1];
-                nacc += (double)n0 * n0 + (double)n1 * n1;
-                if (valid) {
-                    reinterpret_cast<float2*>(a.f1p + tbase)[m] = make_float2(n0, n1);
-                    reinterpret_cast<float2*>(a.f1m + tbase)[m] = make_float2(0.f, 0.f);
-                    if (a.n0) reinterpret_cast<float2*>(a.n0 + tbase)[m] = make_float2(n0, n1);
-                }
-                z[zi(m)] = make_float2(n0, n1);
+            for (int p = 0; p < PM; ++p) {
+                const int m = lane + TPT * p;
+                if (m < M) z[zi(m)] = out[p];
             }
-        }
-    } else if (MODE == TM_FWDF) {
+        } else if constexpr (MODE == TM_GFWD) {
+            const bool minus = (fo & 1) != 0;
 #pragma unroll
-        for (int p = 0; p < PM; ++p) {
-            const int m = lane + TPT * p;
-            if (m < M) z[zi(m)] = reinterpret_cast<const float2*>(a.f1p + tbase)[m];
-        }
-    } else if (MODE == TM_GFWD) {
-        const bool minus = (fo & 1) != 0;
-#pragma unroll
-        for (int p = 0; p < PM; ++p) {
-            const int m = lane + TPT * p;
-            if (m < M) {
-                float2 v;
+            for (int p = 0; p < PM; ++p) {
+                const int m = min(lane + TPT * p, M - 1);
                 if (!minus) {
-                    v = reinterpret_cast<const float2*>(a.f1p + tbase)[m];
+                    out[p] = reinterpret_cast<const float2*>(a.f1p + tbase)[m];
                 } else {                             // f1-(-t)
                     const float* q = a.f1m + tbase;
-                    v = make_float2(q[(NT - 2 * m) & (NT - 1)], q[NT - 2 * m - 1]);
+                    out[p] = make_float2(q[(NT - 2 * m) & (NT - 1)], q[NT - 2 * m - 1]);
                 }
-                z[zi(m)] = v;
             }
-        }
-    } else if (MODE == TM_GOUT) {
-        const bool plus = (fo & 1) != 0;
 #pragma unroll
-        for (int p = 0; p < PM; ++p) {
-            const int m = lane + TPT * p;
-            if (m < M && valid) {
-                const float2 zm = z[zi(m)];
-                const double rn0 = (double)(s * zm.x), rn1 = (double)(s * zm.y);
-                if (!plus) {                          // G- = S[f1+] - f1-
-                    const float2 q = reinterpret_cast<const float2*>(a.f1m + tbase)[m];
-                    reinterpret_cast<float2*>(a.gm + tbase)[m] =
-                        make_float2((float)(rn0 - (double)q.x), (float)(rn1 - (double)q.y));
-                } else {                              // G+ = f1+(-t) - S[f1-(-t)]
+            for (int p = 0; p < PM; ++p) {
+                const int m = lane + TPT * p;
+                if (m < M) z[zi(m)] = out[p];
+            }
+        } else if constexpr (MODE == TM_GOUT) {
+            const bool plus = (fo & 1) != 0;
+#pragma unroll
+            for (int p = 0; p < PM; ++p) {
+                const int m = min(lane + TPT * p, M - 1);
+                if (!plus) {
+                    out[p] = reinterpret_cast<const float2*>(a.f1m + tbase)[m];
+                } else {
                     const float* q = a.f1p + tbase;
-                    const double r0 = q[(NT - 2 * m) & (NT - 1)], r1 = q[NT - 2 * m - 1];
-                    reinterpret_cast<float2*>(a.gp + tbase)[m] =
-                        make_float2((float)(r0 - rn0), (float)(r1 - rn1));
+                    out[p] = make_float2(q[(NT - 2 * m) & (NT - 1)], q[NT - 2 * m - 1]);
                 }
             }
+#pragma unroll
+            for (int p = 0; p < PM; ++p) {
+                const int m = lane + TPT * p;
+                if (m < M && valid) {
+                    const float2 zm = z[zi(m)];
+                    const double rn0 = (double)(s * zm.x), rn1 = (double)(s * zm.y);
+                    if (!plus) {                          // G- = S[f1+] - f1-
+                        reinterpret_cast<float2*>(a.gm + tbase)[m] =
+                            make_float2((float)(rn0 - (double)out[p].x), (float)(rn1 - (double)out[p].y));
+                    } else {                              // G+ = f1+(-t) - S[f1-(-t)]
+                        reinterpret_cast<float2*>(a.gp + tbase)[m] =
+                            make_float2((float)((double)out[p].x - rn0), (float)((double)out[p].y - rn1));
+                    }
+                }
+            }
+            return;
         }
-        return;
-    }
 
-    // ---- time -> spectrum (TM_INIT, TM_ITER, TM_GFWD) ---------------------
-    trace_sync<TPT>();
-    fft_trace<NT, -1, TPT>(z, tq, lane);
-    __syncthreads();                          // every trace of the block transformed
+        // ---- time -> spectrum (TM_INIT, TM_ITER, TM_GFWD, TM_FWDF, restart) ----
+        trace_sync<TPT>();
+        fft_trace<NT, -1, TPT>(z, tq, lane);
+    }
+    lds_barrier();                            // every trace of the block transformed
     const float2* zc = lds + cs * ZS;
     const int kend = a.skip_outband ? fhi : hi;
     const size_t xoff = (size_t)fo * a.B * a.ns_pad + rc;
+    const float cj = FUSED ? -1.f : 1.f;      // fused pass: X = -conj(FFT Q)
     if (a.xprec == XP_F32) {
         float2* Xt = reinterpret_cast<float2*>(a.X) + xoff;
         for (int k = a.lo + ck; k <= kend; k += KSTR) {
             float2 v = make_float2(0.f, 0.f);
             if (k >= flo && k <= fhi) v = unpack_bin<NT>(zc, tq, k);
+            v.x *= cj;
             if (cvalid) Xt[(size_t)(k - a.lo) * a.ns_pad] = v;
         }
     } else {
@@ -537,7 +794,7 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         for (int k = a.lo + ck; k <= kend; k += KSTR) {
             float2 v = make_float2(0.f, 0.f);
             if (k >= flo && k <= fhi) v = unpack_bin<NT>(zc, tq, k);
-            v.x *= inv;
+            v.x *= cj * inv;
             v.y *= inv;
             uint32_t u, ul = 0;
             if (!bf) {
@@ -568,9 +825,9 @@ __global__ __launch_bounds__(256) void k_trace(TraceArgs a) {
         }
         if (r0 == 0 && threadIdx.x == 0) a.xs_out[fo] = xs;
     }
-    if (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2) {
+    if constexpr (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2) {
         nacc = wave_sum_d(nacc);
-        if (TPT > 64) {                      // combine the block's waves in a fixed order
+        if constexpr (TPT > 64) {            // combine the block's waves in a fixed order
             if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nacc;
             __syncthreads();
             nacc = red[0] + red[1] + red[2] + red[3];

@@ -808,10 +808,15 @@ mk_status mk_tail_record(mk_plan_t p, int32_t k, int32_t T) {
     HIP_TRY(p, hipStreamSynchronize(p->stream));
     if (p->hist) HIP_TRY(p, hipFree(p->hist));
     p->hist = nullptr;
-    if (p->tail_w && k != p->hist_k) {
-        HIP_TRY(p, hipFree(p->tail_w));
-        p->tail_w = nullptr;
+    if (k != p->hist_k || T != p->hist_T) {      // network and its buffers were sized for the old (k, T)
+        float** bufs[] = {&p->tail_w, &p->tail_x, &p->tail_work, &p->tail_y};
+        for (float** b : bufs) {
+            if (*b) HIP_TRY(p, hipFree(*b));
+            *b = nullptr;
+        }
         p->tail_nw = 0;
+        p->tail_hidden = 0;
+        p->tail_net_hidden = 0;
     }
     const size_t n = (size_t)p->d.nf_max * p->d.nr * k * T;
     HIP_TRY(p, dalloc(&p->hist, n));
@@ -826,21 +831,37 @@ mk_status mk_tail_load(mk_plan_t p, const float* params, int32_t count) {
     if (!p) return fail(nullptr, MK_ERR_ARG, "mk_tail_load: plan is NULL");
     if (!params) return fail(p, MK_ERR_ARG, "mk_tail_load: params is NULL");
     if (!p->hist) return fail(p, MK_ERR_STATE, "mk_tail_load: call mk_tail_record first");
-    if (count != net_param_count(p->hist_k))
-        return fail(p, MK_ERR_ARG, "mk_tail_load: parameter count does not match k");
+    int H = 0;                                   // the hidden width follows from the count
+    for (int h = 1; h <= kNetHiddenMax && !H; ++h)
+        if (net_param_count(p->hist_k, h) == count) H = h;
+    if (!H) return fail(p, MK_ERR_ARG, "mk_tail_load: parameter count fits no hidden width for this k");
     for (int i = 0; i < count; ++i)
         if (!std::isfinite(params[i])) return fail(p, MK_ERR_ARG, "mk_tail_load: non-finite parameter");
     HIP_TRY(p, hipStreamSynchronize(p->stream));
+    if (p->tail_w && p->tail_nw != count) {
+        HIP_TRY(p, hipFree(p->tail_w));
+        p->tail_w = nullptr;
+    }
     if (!p->tail_w) HIP_TRY(p, dalloc(&p->tail_w, (size_t)count));
     HIP_TRY(p, hipMemcpyAsync(p->tail_w, params, count * sizeof(float), hipMemcpyHostToDevice, p->stream));
     HIP_TRY(p, net_round_bf16(p->tail_w, p->tail_w, count, p->stream));
     p->tail_nw = count;
+    if (p->tail_work && p->tail_hidden < H) {       // activations sized for a narrower network
+        HIP_TRY(p, hipFree(p->tail_work));
+        p->tail_work = nullptr;
+    }
+    if (!p->tail_work) {
+        const int ntr = p->d.nf_max * p->d.nr;
+        p->tail_chunk = std::min(ntr, 4096);
+        HIP_TRY(p, dalloc(&p->tail_work, 2 * (size_t)p->tail_chunk * H * p->hist_T));
+        p->tail_hidden = H;
+    }
+    p->tail_net_hidden = H;
     if (!p->tail_x) {
         const int ntr = p->d.nf_max * p->d.nr;
         p->tail_chunk = std::min(ntr, 4096);
         const size_t c = (size_t)p->tail_chunk, T = (size_t)p->hist_T, k = (size_t)p->hist_k;
         HIP_TRY(p, dalloc(&p->tail_x, c * 16 * T));                 // room for k <= 16
-        HIP_TRY(p, dalloc(&p->tail_work, 2 * c * kNetHidden * T));
         HIP_TRY(p, dalloc(&p->tail_y, c * 2 * T));
         HIP_TRY(p, dalloc(&p->tail_scale, (size_t)ntr));
         (void)k;
@@ -880,12 +901,13 @@ mk_status mk_tail_apply(mk_plan_t p, int32_t mode, double* rel_resid) {
     const int nr = p->d.nr, nt = p->d.nt, k = p->hist_k, T = p->hist_T;
     const int ntr = p->nf * nr;
     if (mode == 0) {
-        const size_t act = (size_t)p->tail_chunk * kNetHidden * T;
+        const int H = p->tail_net_hidden;
+        const size_t act = (size_t)p->tail_chunk * H * T;
         for (int c0 = 0; c0 < ntr; c0 += p->tail_chunk) {
             const int n = std::min(p->tail_chunk, ntr - c0);
             const float* h = p->hist + (size_t)c0 * k * T;
             HIP_TRY(p, launch_tail_prep(h, n, k, T, p->tail_x, p->tail_scale + c0, p->stream));
-            HIP_TRY(p, net_forward(p->tail_w, p->tail_x, n, k, T, p->tail_work, p->tail_work + act, p->tail_y,
+            HIP_TRY(p, net_forward(p->tail_w, p->tail_x, n, k, H, T, p->tail_work, p->tail_work + act, p->tail_y,
                                    p->stream));
             HIP_TRY(p, launch_tail_apply(h, p->tail_y, p->tail_scale + c0, p->itd + c0, p->shift, n, k, T, nt, 0,
                                          p->f1p + (size_t)c0 * nt, p->f1m + (size_t)c0 * nt, p->stream));

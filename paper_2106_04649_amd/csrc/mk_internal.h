@@ -115,12 +115,14 @@ struct mk_plan_s {
     float* tail_w = nullptr;   // BF16-rounded parameters
     int tail_nw = 0;
     float* tail_x = nullptr;   // [chunk][k][T] normalised input
-    float* tail_work = nullptr;   // [2][chunk][64][T]
+    float* tail_work = nullptr;   // [2][chunk][hidden][T]
     float* tail_y = nullptr;   // [chunk][2][T]
     float* tail_scale = nullptr;  // [nf_max][nr]
     int tail_chunk = 0;
     int pass_base = 0;         // passes before the current series (a restart starts a new one)
     bool tail_applied = false;
+    int tail_hidden = 0;       // hidden width tail_work is sized for
+    int tail_net_hidden = 0;   // hidden width of the loaded network
     std::vector<double> gd_norm_host;   // ||G_d|| per focal point (caller order)
 
     // series state
@@ -213,13 +215,13 @@ hipError_t launch_tail_apply(const float* hist, const float* y, const float* sca
                              int ntr, int k, int T, int nt, int mode, float* f1p, float* f1m, hipStream_t s);
 
 // series-tail network (fixed architecture: k -> 64 -> 64 -> 2 channels, 5 taps)
-constexpr int kNetHidden = 64;
+constexpr int kNetHiddenMax = 128;      // widest hidden layer the ABI accepts
 constexpr int kNetDil[3] = {1, 4, 16};
-int net_param_count(int k);
-hipError_t net_forward(const float* P, const float* x, int N, int k, int T, float* a1, float* a2,
+int net_param_count(int k, int H);
+hipError_t net_forward(const float* P, const float* x, int N, int k, int H, int T, float* a1, float* a2,
                        float* y, hipStream_t s);
 hipError_t net_backward(const float* P, const float* x, const float* a1, const float* a2, const float* gy,
-                        int N, int k, int T, float* G, float* g1, float* g2, float* wt, hipStream_t s);
+                        int N, int k, int H, int T, float* G, float* g1, float* g2, float* wt, hipStream_t s);
 hipError_t net_mse(const float* y, const float* tgt, const float* mask, int N, int T, float* gy,
                    double* part, int nparts, double* loss, float count, hipStream_t s);
 hipError_t net_adam(float* w, float* wq, const float* g, float* m, float* v, int n, int step, float lr,

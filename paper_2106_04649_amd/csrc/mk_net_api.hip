@@ -16,29 +16,35 @@ mk_status net_hip(hipError_t e, const char* where) {
 }
 
 bool net_dims_ok(int N, int k, int T) { return N >= 1 && k >= 1 && k <= 16 && T >= 1 && T <= 4096; }
+bool hidden_ok(int H) { return H >= 1 && H <= kNetHiddenMax; }
 }  // namespace
 
 extern "C" {
 
-int32_t mk_net_param_count(int32_t k) { return k >= 1 && k <= 16 ? net_param_count(k) : -1; }
+int32_t mk_net_param_count(int32_t k, int32_t hidden) {
+    return k >= 1 && k <= 16 && hidden_ok(hidden) ? net_param_count(k, hidden) : -1;
+}
 
 const char* mk_net_last_error(void) { return g_net_error.c_str(); }
 
-mk_status mk_net_forward(const float* params, const float* x, int32_t N, int32_t k, int32_t T, float* work,
-                         float* y, void* stream) {
+mk_status mk_net_forward(const float* params, const float* x, int32_t N, int32_t k, int32_t hidden, int32_t T,
+                         float* work, float* y, void* stream) {
     if (!params || !x || !work || !y) return net_fail(MK_ERR_ARG, "mk_net_forward: NULL pointer");
-    if (!net_dims_ok(N, k, T)) return net_fail(MK_ERR_ARG, "mk_net_forward: bad N, k or T");
-    const size_t act = (size_t)N * kNetHidden * T;
-    return net_hip(net_forward(params, x, N, k, T, work, work + act, y, (hipStream_t)stream), "mk_net_forward");
+    if (!net_dims_ok(N, k, T) || !hidden_ok(hidden))
+        return net_fail(MK_ERR_ARG, "mk_net_forward: bad N, k, hidden or T");
+    const size_t act = (size_t)N * hidden * T;
+    return net_hip(net_forward(params, x, N, k, hidden, T, work, work + act, y, (hipStream_t)stream),
+                   "mk_net_forward");
 }
 
 mk_status mk_net_backward(const float* params, const float* x, const float* work, const float* gy, int32_t N,
-                          int32_t k, int32_t T, float* grads, float* work2, void* stream) {
+                          int32_t k, int32_t hidden, int32_t T, float* grads, float* work2, void* stream) {
     if (!params || !x || !work || !gy || !grads || !work2)
         return net_fail(MK_ERR_ARG, "mk_net_backward: NULL pointer");
-    if (!net_dims_ok(N, k, T)) return net_fail(MK_ERR_ARG, "mk_net_backward: bad N, k or T");
-    const size_t act = (size_t)N * kNetHidden * T;
-    return net_hip(net_backward(params, x, work, work + act, gy, N, k, T, grads, work2, work2 + act,
+    if (!net_dims_ok(N, k, T) || !hidden_ok(hidden))
+        return net_fail(MK_ERR_ARG, "mk_net_backward: bad N, k, hidden or T");
+    const size_t act = (size_t)N * hidden * T;
+    return net_hip(net_backward(params, x, work, work + act, gy, N, k, hidden, T, grads, work2, work2 + act,
                                 work2 + 2 * act, (hipStream_t)stream),
                    "mk_net_backward");
 }

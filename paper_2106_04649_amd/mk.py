@@ -80,10 +80,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mk_tail_load": (i32, [P, P, i32]),
         "mk_tail_history": (i32, [P, P, ctypes.c_int]),
         "mk_tail_apply": (i32, [P, i32, P]),
-        "mk_net_param_count": (i32, [i32]),
+        "mk_net_param_count": (i32, [i32, i32]),
         "mk_net_last_error": (ctypes.c_char_p, []),
-        "mk_net_forward": (i32, [P, P, i32, i32, i32, P, P, P]),
-        "mk_net_backward": (i32, [P, P, P, P, i32, i32, i32, P, P, P]),
+        "mk_net_forward": (i32, [P, P, i32, i32, i32, i32, P, P, P]),
+        "mk_net_backward": (i32, [P, P, P, P, i32, i32, i32, i32, P, P, P]),
         "mk_net_loss": (i32, [P, P, P, i32, i32, ctypes.c_float, P, P, P, i32, P]),
         "mk_net_adam": (i32, [P, P, P, P, P, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, P]),
@@ -306,20 +306,30 @@ def _net_check(status: int) -> None:
         raise MKError(status, load_library().mk_net_last_error().decode())
 
 
-def mk_net_param_count(k: int) -> int:
-    return int(load_library().mk_net_param_count(int(k)))
+def mk_net_param_count(k: int, hidden: int = 64) -> int:
+    return int(load_library().mk_net_param_count(int(k), int(hidden)))
 
 
-def mk_net_forward(params, x, work, y, stream=None) -> None:
+def net_hidden(nparams: int, k: int) -> int:
+    """Hidden width of a parameter vector of nparams floats for k inputs."""
+    for h in range(1, 129):
+        if mk_net_param_count(k, h) == nparams:
+            return h
+    raise ValueError(f"{nparams} parameters fit no hidden width for k={k}")
+
+
+def mk_net_forward(params, x, work, y, stream=None, hidden=None) -> None:
     N, k, T = x.shape
+    h = net_hidden(params.numel(), k) if hidden is None else int(hidden)
     s = _current_stream() if stream is None else stream
-    _net_check(load_library().mk_net_forward(_dev(params), _dev(x), N, k, T, _dev(work), _dev(y), s))
+    _net_check(load_library().mk_net_forward(_dev(params), _dev(x), N, k, h, T, _dev(work), _dev(y), s))
 
 
-def mk_net_backward(params, x, work, gy, grads, work2, stream=None) -> None:
+def mk_net_backward(params, x, work, gy, grads, work2, stream=None, hidden=None) -> None:
     N, k, T = x.shape
+    h = net_hidden(params.numel(), k) if hidden is None else int(hidden)
     s = _current_stream() if stream is None else stream
-    _net_check(load_library().mk_net_backward(_dev(params), _dev(x), _dev(work), _dev(gy), N, k, T,
+    _net_check(load_library().mk_net_backward(_dev(params), _dev(x), _dev(work), _dev(gy), N, k, h, T,
                                               _dev(grads), _dev(work2), s))
 
 

@@ -146,10 +146,10 @@ def build_dataset(seeds, k, T, gen, rprec=0):
     return torch.cat(xs), torch.cat(ys), torch.cat(ms)
 
 
-def init_params_flat(k, seed=0):
+def init_params_flat(k, seed=0, H=64):
     """He initialisation (last layer scaled down), flattened in the library's layout."""
     rng = np.random.default_rng(seed)
-    H, Kt = 64, 5
+    Kt = 5
 
     def w(o, c, scale):
         return rng.standard_normal((o, c, Kt)) * scale
@@ -159,19 +159,19 @@ def init_params_flat(k, seed=0):
     return np.concatenate([q.ravel() for q in parts]).astype(np.float32)
 
 
-def fit(X, Y, Mk, k, T, steps, batch, lr, seed=0, val=None):
+def fit(X, Y, Mk, k, T, steps, batch, lr, seed=0, val=None, H=64):
     import torch
 
-    n = mk.mk_net_param_count(k)
-    w = torch.from_numpy(init_params_flat(k, seed)).cuda()
+    n = mk.mk_net_param_count(k, H)
+    w = torch.from_numpy(init_params_flat(k, seed, H)).cuda()
     wq = torch.empty_like(w)
     mk.mk_net_round(w, wq)
     m = torch.zeros_like(w)
     v = torch.zeros_like(w)
     g = torch.zeros_like(w)
     N = X.shape[0]
-    work = torch.empty(2 * batch * 64 * T, device="cuda")
-    work2 = torch.empty(2 * batch * 64 * T + 64 * 64 * 5, device="cuda")
+    work = torch.empty(2 * batch * H * T, device="cuda")
+    work2 = torch.empty(2 * batch * H * T + H * H * 5, device="cuda")
     yb = torch.empty((batch, 2, T), device="cuda")
     gy = torch.empty_like(yb)
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -185,30 +185,30 @@ def fit(X, Y, Mk, k, T, steps, batch, lr, seed=0, val=None):
         cnt = float(mb.sum().item()) * 2.0
         if cnt <= 0:
             continue
-        mk.mk_net_forward(wq, xb, work, yb)
+        mk.mk_net_forward(wq, xb, work, yb, hidden=H)
         mk.mk_net_loss(yb, tb, mb, cnt, gy, loss, part)
-        mk.mk_net_backward(wq, xb, work, gy, g, work2)
+        mk.mk_net_backward(wq, xb, work, gy, g, work2, hidden=H)
         lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * step / steps))      # cosine decay
         mk.mk_net_adam(w, wq, g, m, v, step, lr=lr_t)
         if step % 200 == 0 or step == steps:
             rec = {"step": step, "loss": float(loss.item())}
             if val is not None:
-                rec["val_loss"] = evaluate_loss(wq, *val, T, batch)
+                rec["val_loss"] = evaluate_loss(wq, *val, T, batch, H)
             curve.append(rec)
             log(f"step {step}: {rec} ({time.perf_counter() - t0:.1f} s)")
     assert n == w.numel()
     return w.cpu().numpy(), curve
 
 
-def evaluate_loss(wq, X, Y, Mk, T, batch):
+def evaluate_loss(wq, X, Y, Mk, T, batch, H):
     import torch
 
     tot, cnt = 0.0, 0.0
-    work = torch.empty(2 * batch * 64 * T, device="cuda")
+    work = torch.empty(2 * batch * H * T, device="cuda")
     yb = torch.empty((batch, 2, T), device="cuda")
     for i in range(0, X.shape[0] - batch + 1, batch):
         xb = X[i:i + batch].contiguous()
-        mk.mk_net_forward(wq, xb, work, yb)
+        mk.mk_net_forward(wq, xb, work, yb, hidden=H)
         r = (yb - Y[i:i + batch]) * Mk[i:i + batch][:, None, :]
         tot += float((r * r).sum().item())
         cnt += float(Mk[i:i + batch].sum().item()) * 2
@@ -279,6 +279,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--hidden", type=int, default=64, help="hidden channels of the tail network")
     ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "tailnet_k4.npz"))
     ap.add_argument("--report", default=None)
     ap.add_argument("--eval-only", default=None, metavar="NPZ",
@@ -304,6 +305,7 @@ def main(argv=None):
         rows = evaluate(params, hold_seeds, int(saved["k"]), int(saved["T"]), gen, args.rprec)
         report = {"workload": args.workload, "rprec": args.rprec, "network": os.path.basename(args.eval_only),
                   "holdout_models": len(hold_seeds), "k": int(saved["k"]), "T": int(saved["T"]),
+                  "hidden": mk.net_hidden(params.size, int(saved["k"])),
                   "summary": summarise(rows)}
         if args.report:
             with open(args.report, "w") as fh:
@@ -316,9 +318,9 @@ def main(argv=None):
     nval = min(len(hold_seeds), 16 if args.workload == "tail" else 2)
     Xv, Yv, Mv = build_dataset(hold_seeds[:nval], args.k, args.T, gen, args.rprec)
     params, curve = fit(X, Y, M, args.k, args.T, args.steps, args.batch, args.lr,
-                        val=(Xv, Yv, Mv))
-    np.savez(args.out, params=params, k=args.k, T=args.T, train_models=args.train, steps=args.steps,
-             workload=args.workload, curve=json.dumps(curve))
+                        val=(Xv, Yv, Mv), H=args.hidden)
+    np.savez(args.out, params=params, k=args.k, T=args.T, hidden=args.hidden, train_models=args.train,
+             steps=args.steps, workload=args.workload, curve=json.dumps(curve))
     log(f"saved {args.out}")
     del X, Y, M
     torch.cuda.empty_cache()
@@ -326,6 +328,7 @@ def main(argv=None):
     summary = summarise(rows)
     report = {"workload": args.workload, "rprec": args.rprec,
               "train_models": args.train, "holdout_models": len(hold_seeds), "k": args.k, "T": args.T,
+              "hidden": args.hidden,
               "steps": args.steps, "curve": curve, "summary": summary}
     if args.report:
         with open(args.report, "w") as fh:

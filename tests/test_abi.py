@@ -90,5 +90,8 @@ def test_null_arguments(lib):
 
 
 def test_net_param_count(lib):
-    assert lib.mk_net_param_count(4) == 64 * 4 * 5 + 64 + 64 * 64 * 5 + 64 + 2 * 64 * 5 + 2
-    assert lib.mk_net_param_count(0) == -1
+    for H in (64, 16, 1):
+        assert lib.mk_net_param_count(4, H) == H * 4 * 5 + H + H * H * 5 + H + 2 * H * 5 + 2
+    assert lib.mk_net_param_count(0, 64) == -1
+    assert lib.mk_net_param_count(4, 0) == -1
+    assert lib.mk_net_param_count(4, 129) == -1

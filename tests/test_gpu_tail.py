@@ -87,11 +87,11 @@ def test_no_tail_restart_equals_plain_passes():
     np.testing.assert_allclose(g["norms"], plain["norms"][K + 2:], rtol=1e-3)
 
 
-@pytest.mark.parametrize("tune", [None, 1])
-def test_network_tail_matches_reference(tune):
-    say(f"network tail, contraction {tune}")
+@pytest.mark.parametrize("tune,hidden", [(None, 64), (1, 64), (None, 12)])
+def test_network_tail_matches_reference(tune, hidden):
+    say(f"network tail, contraction {tune}, hidden {hidden}")
     rng = np.random.default_rng(5)
-    P = tn.init_params(rng, k=K)
+    P = tn.init_params(rng, k=K, hidden=hidden)
     P["W3"] *= 5.0
     P["b3"] = 0.01 * rng.standard_normal(2)
     flat = np.concatenate([P["W1"].ravel(), P["b1"], P["W2"].ravel(), P["b2"], P["W3"].ravel(), P["b3"]])
@@ -114,7 +114,7 @@ def test_tail_state_errors():
     plan = mk.mk_plan(8, 8, 64, p.geom.dt, p.geom.dx)
     mk.mk_load_R(plan, p.Rhat)
     with pytest.raises(mk.MKError) as ei:
-        mk.mk_tail_load(plan, np.zeros(mk.mk_net_param_count(4), np.float32))
+        mk.mk_tail_load(plan, np.zeros(mk.mk_net_param_count(4, 64), np.float32))
     assert ei.value.status == mk.MK_ERR_STATE
     mk.mk_tail_record(plan, 4, 32)
     with pytest.raises(mk.MKError):

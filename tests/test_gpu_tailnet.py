@@ -14,8 +14,7 @@ def _flat(P, k):
     return np.concatenate([P["W1"].ravel(), P["b1"], P["W2"].ravel(), P["b2"], P["W3"].ravel(), P["b3"]])
 
 
-def _unflat(v, k):
-    H = 64
+def _unflat(v, k, H):
     out, o = {}, 0
     for name, shape in (("W1", (H, k, 5)), ("b1", (H,)), ("W2", (H, H, 5)), ("b2", (H,)),
                         ("W3", (2, H, 5)), ("b3", (2,))):
@@ -25,14 +24,15 @@ def _unflat(v, k):
     return out
 
 
-@pytest.mark.parametrize("N,k,T", [(3, 4, 70), (5, 2, 200), (1, 4, 64)])
-def test_forward_loss_backward_match_reference(N, k, T):
+@pytest.mark.parametrize("N,k,T,H", [(3, 4, 70, 64), (5, 2, 200, 64), (1, 4, 64, 64), (4, 4, 130, 16),
+                                     (2, 3, 90, 8), (3, 4, 70, 5)])
+def test_forward_loss_backward_match_reference(N, k, T, H):
     mk = require_gpu()
     import torch
 
-    say(f"tailnet N={N} k={k} T={T}")
+    say(f"tailnet N={N} k={k} T={T} H={H}")
     rng = np.random.default_rng(N * 100 + T)
-    P = tn.init_params(rng, k=k)
+    P = tn.init_params(rng, k=k, hidden=H)
     for key in P:
         P[key] = (P[key] + 0.05 * rng.standard_normal(P[key].shape)).astype(np.float32).astype(np.float64)
     x = rng.standard_normal((N, k, T)).astype(np.float32)
@@ -42,12 +42,13 @@ def test_forward_loss_backward_match_reference(N, k, T):
     loss_ref, g_ref = tn.loss_and_grad(P, x.astype(np.float64), tgt.astype(np.float64),
                                        mask.astype(np.float64))
     y_ref, _ = tn.forward(P, x.astype(np.float64))
-    assert mk.mk_net_param_count(k) == _flat(P, k).size
+    assert mk.mk_net_param_count(k, H) == _flat(P, k).size
+    assert mk.net_hidden(_flat(P, k).size, k) == H
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     params = d(_flat(P, k).astype(np.float32))
     xd, td, md = d(x), d(tgt), d(mask)
-    work = torch.zeros(2 * N * 64 * T, device="cuda")
-    work2 = torch.zeros(2 * N * 64 * T + 64 * 64 * 5, device="cuda")
+    work = torch.zeros(2 * N * H * T, device="cuda")
+    work2 = torch.zeros(2 * N * H * T + H * H * 5, device="cuda")
     y = torch.zeros((N, 2, T), device="cuda")
     gy = torch.zeros_like(y)
     grads = torch.zeros_like(params)
@@ -59,7 +60,7 @@ def test_forward_loss_backward_match_reference(N, k, T):
     torch.cuda.synchronize()
     np.testing.assert_allclose(y.cpu().numpy(), y_ref, rtol=1e-4, atol=1e-5 * np.abs(y_ref).max())
     assert abs(loss.item() - loss_ref) <= 1e-4 * loss_ref
-    G = _unflat(grads.cpu().numpy().astype(np.float64), k)
+    G = _unflat(grads.cpu().numpy().astype(np.float64), k, H)
     for key in g_ref:
         scale = np.abs(g_ref[key]).max() + 1e-30
         err = np.abs(G[key] - g_ref[key]).max() / scale
