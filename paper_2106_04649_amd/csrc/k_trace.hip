@@ -229,8 +229,18 @@ __device__ __forceinline__ constexpr int out_reg(int m) {
     return R == 16 ? 4 * (m & 3) + (m >> 2) : R == 8 ? 4 * (m & 1) + (m >> 1) : m;
 }
 
-template <int NT, int DIR, int NS, int R>
-__device__ __forceinline__ void fft16_pass(float2* z, const float2* __restrict__ tw, int lane) {
+// Twiddles of a pass.  Span 16 (W_{16 R}^{q k}, k < 16): read from a 16 x 16
+// table of W_256^{q k} that sits in the padding slots of the block's four
+// trace regions (ZS > 0: t16 is this lane's row).  Last pass of radix 4 or 8
+// (W_M^{q k}): powers of W_M^k, which is entry 2 k of the first quadrant.
+// Otherwise decoded from the quarter table.
+template <int ZS>
+__device__ __forceinline__ float2 t16_at(const float2* t16, int qq) {
+    return t16[(qq >> 2) * ZS + 17 * 16 * (qq & 3)];
+}
+
+template <int NT, int DIR, int NS, int R, int ZS>
+__device__ __forceinline__ void fft16_pass(float2* z, const float2* __restrict__ tw, const float2* t16, int lane) {
     constexpr int M = NT / 2;
     constexpr int NB = M / R;                // butterflies
     constexpr int PB = (NB + 63) / 64;       // per lane
@@ -250,7 +260,28 @@ __device__ __forceinline__ void fft16_pass(float2* z, const float2* __restrict__
         const int j = lane + 64 * p;
         if (j < NB) {
             const int k = j & (NS - 1);
-            if constexpr (NS > 1) {
+            if constexpr (NS == 16 && ZS > 0) {
+#pragma unroll
+                for (int q = 1; q < R; ++q) {
+                    float2 t = t16_at<ZS>(t16, (16 / R) * q);
+                    if (DIR > 0) t.y = -t.y;
+                    v[p][q] = cmul(v[p][q], t);
+                }
+            } else if constexpr (NS * R == M && (R == 4 || R == 8) && NS > 16) {
+                float2 w[R];
+                w[1] = tw[2 * k];
+                if (DIR > 0) w[1].y = -w[1].y;
+                w[2] = cmul(w[1], w[1]);
+                w[3] = cmul(w[2], w[1]);
+                if constexpr (R == 8) {
+                    w[4] = cmul(w[2], w[2]);
+                    w[5] = cmul(w[4], w[1]);
+                    w[6] = cmul(w[4], w[2]);
+                    w[7] = cmul(w[4], w[3]);
+                }
+#pragma unroll
+                for (int q = 1; q < R; ++q) v[p][q] = cmul(v[p][q], w[q]);
+            } else if constexpr (NS > 1) {
 #pragma unroll
                 for (int q = 1; q < R; ++q) v[p][q] = cmul(v[p][q], twid<DIR, NT>(tw, q * k * TWS));
             }
@@ -269,22 +300,22 @@ __device__ __forceinline__ void fft16_pass(float2* z, const float2* __restrict__
     trace_sync<64>();
 }
 
-template <int NT, int DIR, int NS, int BITS>
-__device__ __forceinline__ void fft16_passes(float2* z, const float2* __restrict__ tw, int lane) {
+template <int NT, int DIR, int NS, int BITS, int ZS>
+__device__ __forceinline__ void fft16_passes(float2* z, const float2* __restrict__ tw, const float2* t16, int lane) {
     if constexpr (BITS >= 4) {
-        fft16_pass<NT, DIR, NS, 16>(z, tw, lane);
-        fft16_passes<NT, DIR, NS * 16, BITS - 4>(z, tw, lane);
+        fft16_pass<NT, DIR, NS, 16, ZS>(z, tw, t16, lane);
+        fft16_passes<NT, DIR, NS * 16, BITS - 4, ZS>(z, tw, t16, lane);
     } else if constexpr (BITS > 0) {
-        fft16_pass<NT, DIR, NS, (1 << BITS)>(z, tw, lane);
+        fft16_pass<NT, DIR, NS, (1 << BITS), ZS>(z, tw, t16, lane);
     }
 }
 
 // the transform of M = NT/2 points for TPT threads per trace: radix 16 when
 // a wave owns the trace, radix 4 when the whole block does (more butterflies
 // to spread over 256 threads)
-template <int NT, int DIR, int TPT>
-__device__ __forceinline__ void fft_trace(float2* z, const float2* __restrict__ tw, int lane) {
-    if constexpr (TPT == 64 && NT >= 16) fft16_passes<NT, DIR, 1, ilog2c(NT / 2)>(z, tw, lane);
+template <int NT, int DIR, int TPT, int ZS>
+__device__ __forceinline__ void fft_trace(float2* z, const float2* __restrict__ tw, const float2* t16, int lane) {
+    if constexpr (TPT == 64 && NT >= 16) fft16_passes<NT, DIR, 1, ilog2c(NT / 2), ZS>(z, tw, t16, lane);
     else fft_lds<NT, DIR, TPT>(z, tw, lane);
 }
 
@@ -292,18 +323,6 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
-}
-
-// rfft bin k of the real trace whose packed transform Z is in z (k in [0, M]).
-template <int NT>
-__device__ __forceinline__ float2 unpack_bin(const float2* z, const float2* __restrict__ tw, int k) {
-    constexpr int M = NT / 2;
-    const float2 zk = z[zi(k & (M - 1))];
-    const float2 zm = z[zi((M - k) & (M - 1))];
-    const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-    const float2 d = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
-    const float2 wd = cmul(twid<-1, NT>(tw, k), d);
-    return make_float2(e.x + wd.y, e.y - wd.x);          // E - i W^k D
 }
 
 // Packed spectrum Z[k] = E[k] + i O[k] of the even/odd samples, from bins
@@ -370,6 +389,7 @@ template <int NT, int R>
 __device__ __forceinline__ void inv_last_pass(const float2* z, const float2* tq, int lane,
                                               float2 (&v)[NT / 2 / (64 * R)][R]) {
     constexpr int M = NT / 2, NB = M / R, PB = NB / 64;
+    static_assert(R == 4 || R == 8, "last pass of 1024 or 2048 points");
 #pragma unroll
     for (int p = 0; p < PB; ++p) {
 #pragma unroll
@@ -379,8 +399,20 @@ __device__ __forceinline__ void inv_last_pass(const float2* z, const float2* tq,
 #pragma unroll
     for (int p = 0; p < PB; ++p) {
         const int k = lane + 64 * p;                 // < span: k = j
+        // W_M^{-q k} as powers of conj(W_M^k) = conj(W_NT^{2k}), first quadrant
+        float2 w[R];
+        w[1] = tq[2 * k];
+        w[1].y = -w[1].y;
+        w[2] = cmul(w[1], w[1]);
+        w[3] = cmul(w[2], w[1]);
+        if constexpr (R == 8) {
+            w[4] = cmul(w[2], w[2]);
+            w[5] = cmul(w[4], w[1]);
+            w[6] = cmul(w[4], w[2]);
+            w[7] = cmul(w[4], w[3]);
+        }
 #pragma unroll
-        for (int q = 1; q < R; ++q) v[p][q] = cmul(v[p][q], twid<+1, NT>(tq, q * k * 2));
+        for (int q = 1; q < R; ++q) v[p][q] = cmul(v[p][q], w[q]);
         dft_reg<R, +1>(v[p]);
     }
 }
@@ -423,12 +455,17 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
     constexpr bool GMODE = MODE == TM_GFWD || MODE == TM_GOUT;
     constexpr bool YIN = MODE == TM_ITER || MODE == TM_GOUT || MODE == TM_RST1 || MODE == TM_RST2;
     constexpr bool FUSED = (MODE == TM_ITER || MODE == TM_RST1) && TPT == 64 && (M == 1024 || M == 2048);
+    // the span-16 twiddle table lives in the padding of the four trace regions
+    constexpr int ZT = (TPT == 64 && M >= 1024) ? ZS : 0;
     __shared__ float2 lds[TPB * ZS];
     __shared__ float2 tq[TQN];               // quarter twiddle table (see twid)
     __shared__ double red[TPT > 64 ? 4 : 1];
     const int wv = TPT == 64 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64) : 0;   // trace slot
     const int lane = threadIdx.x % TPT;     // thread within the trace
     float2* z = lds + wv * ZS;
+    // entry (q, k) of the span-16 table, n = 16 q + k, is padding slot n mod 64
+    // (index 17 slot + 16) of region n / 64; a lane reads row k = lane mod 16
+    const float2* t16 = lds + 17 * (lane & 15) + 16;
 
     // blocks are dealt to the 8 XCDs in contiguous runs, so that neighbouring
     // receivers (which share cache lines of Y and X) meet in one L2
@@ -456,10 +493,13 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
     const float s = a.scale;
     // window of the mute, |t| < L (loaded first: the f1 addresses depend on it)
     [[maybe_unused]] int L = 0;
-    if constexpr (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2) L = a.itd[f * a.nr + r] - a.shift;
+    if constexpr (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2)
+        L = min(a.itd[f * a.nr + r] - a.shift, M);     // |t| < L; t = -M is never kept
     float2 tqv[TQP];
 #pragma unroll
     for (int i = 0; i < TQP; ++i) tqv[i] = a.tw[min((int)threadIdx.x + 256 * i, TQN - 1)];
+    [[maybe_unused]] float2 t16v;
+    if constexpr (ZT > 0) t16v = a.tw[NT + threadIdx.x];
 
     // Y bins in [flo, fhi]; the others are zero (clamped, always valid, address)
     float2 yv[NY];
@@ -479,9 +519,8 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
         ynyq = yload(M).x;
     }
 
-    auto win = [&](int u) -> bool {         // sample u of the trace is inside the mute window
-        const int sg = u < M ? u : u - NT;
-        return (sg < L) & (-sg < L) & (u != M);   // no short circuit: no branches
+    auto win = [&](int u) -> bool {         // sample u (signed time u or u - nt) inside the window
+        return (u < L) | (u > NT - L);      // with L <= M; no short circuit: no branches
     };
     float* acc = (a.parity == 0) ? a.f1m : a.f1p;
 
@@ -489,6 +528,10 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
     for (int i = 0; i < TQP; ++i) {
         if constexpr (TQN % 256 == 0) tq[threadIdx.x + 256 * i] = tqv[i];      // unconditional: the load stays early
         else if ((int)threadIdx.x + 256 * i < TQN) tq[threadIdx.x + 256 * i] = tqv[i];
+    }
+    if constexpr (ZT > 0) {
+        const int n = threadIdx.x, q = n >> 4;
+        lds[(q >> 2) * ZS + 17 * (16 * (q & 3) + (n & 15)) + 16] = t16v;
     }
     if constexpr (YIN) {
         // every stored bin is read once: slot k holds bin k, slot 0 the real
@@ -513,7 +556,7 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
         constexpr int LOG2RL = (LOG2M % 4) == 0 ? 4 : LOG2M % 4;
         constexpr int RL = 1 << LOG2RL, PBL = M / (64 * RL), QN = M / 64;
         inv_first_pass<NT>(z, tq, lane);
-        fft16_passes<NT, +1, 16, LOG2M - 4 - LOG2RL>(z, tq, lane);
+        fft16_passes<NT, +1, 16, LOG2M - 4 - LOG2RL, ZT>(z, tq, t16, lane);
         float2 x[QN];                           // element lane + 64 e: (RN[2 idx], RN[2 idx + 1]) / s
         {
             float2 v[PBL][RL];
@@ -593,7 +636,7 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
         }
         fwd_first_pass<NT>(z, x, lane);
         trace_sync<64>();
-        fft16_passes<NT, -1, 16, LOG2M - 4>(z, tq, lane);
+        fft16_passes<NT, -1, 16, LOG2M - 4, ZT>(z, tq, t16, lane);
     } else {
         // ---- spectrum -> time (TM_ITER, TM_GOUT, TM_RST1, TM_RST2) ------------
         if constexpr (YIN) {
@@ -608,7 +651,7 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
                 }
             }
             trace_sync<TPT>();
-            fft_trace<NT, +1, TPT>(z, tq, lane);
+            fft_trace<NT, +1, TPT, ZT>(z, tq, t16, lane);
             // z[m] = (RN[2m], RN[2m+1]) / s
         }
 
@@ -766,34 +809,56 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
 
         // ---- time -> spectrum (TM_INIT, TM_ITER, TM_GFWD, TM_FWDF, restart) ----
         trace_sync<TPT>();
-        fft_trace<NT, -1, TPT>(z, tq, lane);
+        fft_trace<NT, -1, TPT, ZT>(z, tq, t16, lane);
     }
     lds_barrier();                            // every trace of the block transformed
+    // rfft bins kb + KSTR i of slot cs, unrolled: the LDS slots of bins k and
+    // M - k step by a constant, W^k = W^kb W^{KSTR i} (the second factor at a
+    // constant index), and the halves of E and D are folded into the scale
+    constexpr int NXI = M / KSTR + 1;         // bins up to M
+    constexpr int ZK = KSTR + KSTR / 16;      // slot step of KSTR bins
     const float2* zc = lds + cs * ZS;
     const int kend = a.skip_outband ? fhi : hi;
-    const size_t xoff = (size_t)fo * a.B * a.ns_pad + rc;
+    const int kb = a.lo + ck;
+    const int zkb = zi(kb), zmb = zi(M - kb);
+    const float2 wb = twid<-1, NT>(tq, kb & (NT - 1));
+    const size_t xoff = (size_t)fo * a.B * a.ns_pad + rc + (size_t)ck * a.ns_pad;
+    const size_t xstep = (size_t)KSTR * a.ns_pad;
+    auto bin2 = [&](int i) -> float2 {        // 2 X[k] (0 outside the focal band)
+        const int k = kb + KSTR * i;
+        const bool past = k >= M;             // k = M reads slot 0; beyond M nothing is stored
+        const float2 zk = zc[past ? 0 : zkb + ZK * i];
+        const float2 zm = zc[(past || (i == 0 && k == 0)) ? 0 : zmb - ZK * i];
+        const float2 w = cmul(wb, twid<-1, NT>(tq, (KSTR * i) & (NT - 1)));
+        const float2 e2 = make_float2(zk.x + zm.x, zk.y - zm.y);
+        const float2 d2 = make_float2(zk.x - zm.x, zk.y + zm.y);
+        const float2 wd = cmul(w, d2);
+        const bool in = (k >= flo) & (k <= fhi);
+        return make_float2(in ? e2.x + wd.y : 0.f, in ? e2.y - wd.x : 0.f);
+    };
     const float cj = FUSED ? -1.f : 1.f;      // fused pass: X = -conj(FFT Q)
     if (a.xprec == XP_F32) {
         float2* Xt = reinterpret_cast<float2*>(a.X) + xoff;
-        for (int k = a.lo + ck; k <= kend; k += KSTR) {
-            float2 v = make_float2(0.f, 0.f);
-            if (k >= flo && k <= fhi) v = unpack_bin<NT>(zc, tq, k);
-            v.x *= cj;
-            if (cvalid) Xt[(size_t)(k - a.lo) * a.ns_pad] = v;
+#pragma unroll
+        for (int i = 0; i < NXI; ++i) {
+            float2 v = bin2(i);
+            v.x *= 0.5f * cj;
+            v.y *= 0.5f;
+            if (cvalid & (kb + KSTR * i <= kend)) Xt[i * xstep] = v;
         }
     } else {
         // 16-bit X scaled per focal point by the RMS trace norm of the previous field
         const double nrm = a.xs_in ? a.xs_in[f] : 0.0;
         float xs = (float)(nrm / sqrt((double)a.nr));
         if (!(xs >= 0x1p-100f) || !isfinite(xs)) xs = 1.f;
-        const float inv = 1.f / xs;
+        const float inv = 0.5f / xs;
         uint32_t* Xt = reinterpret_cast<uint32_t*>(a.X) + xoff;
         const bool bf = a.xprec == XP_BF16 || a.xprec == XP_BF16X2;
         const bool split = a.xprec == XP_F16X2 || a.xprec == XP_BF16X2;
         const size_t lo_off = (size_t)a.nfo * a.B * a.ns_pad;       // second plane
-        for (int k = a.lo + ck; k <= kend; k += KSTR) {
-            float2 v = make_float2(0.f, 0.f);
-            if (k >= flo && k <= fhi) v = unpack_bin<NT>(zc, tq, k);
+#pragma unroll
+        for (int i = 0; i < NXI; ++i) {
+            float2 v = bin2(i);
             v.x *= cj * inv;
             v.y *= inv;
             uint32_t u, ul = 0;
@@ -818,9 +883,9 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
                     ul = (lx >> 16) | (ly & 0xFFFF0000u);
                 }
             }
-            if (cvalid) {
-                Xt[(size_t)(k - a.lo) * a.ns_pad] = u;
-                if (split) Xt[lo_off + (size_t)(k - a.lo) * a.ns_pad] = ul;
+            if (cvalid & (kb + KSTR * i <= kend)) {
+                Xt[i * xstep] = u;
+                if (split) Xt[lo_off + i * xstep] = ul;
             }
         }
         if (r0 == 0 && threadIdx.x == 0) a.xs_out[fo] = xs;

@@ -461,7 +461,7 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     if ((e = dalloc(&p->gdnorm, nfm)) != hipSuccess) return bail(e, "gdnorm");
     if ((e = dalloc(&p->nlast, nfm)) != hipSuccess) return bail(e, "nlast");
     if ((e = dalloc(&p->xscale, 3 * nfm)) != hipSuccess) return bail(e, "X scales");
-    if ((e = dalloc(&p->tw, (size_t)d.nt)) != hipSuccess) return bail(e, "twiddles");
+    if ((e = dalloc(&p->tw, (size_t)d.nt + 256)) != hipSuccess) return bail(e, "twiddles");
     if ((e = dalloc(&p->flag, 1)) != hipSuccess) return bail(e, "flag");
     if ((e = dalloc(&p->n0, nfm * trace)) != hipSuccess) return bail(e, "N_-1");
     // the padding columns of X (s >= ns) must read as zero
@@ -470,10 +470,14 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
         return bail(e, "clear X");
     if ((e = hipMemsetAsync(p->xscale, 0, 3 * nfm * sizeof(float), p->stream)) != hipSuccess)
         return bail(e, "clear X scales");
-    std::vector<float2> tw(d.nt);
+    std::vector<float2> tw(d.nt + 256);
     for (int k = 0; k < d.nt; ++k) {
         const double ang = -2.0 * M_PI * (double)k / (double)d.nt;
         tw[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    for (int n = 0; n < 256; ++n) {          // W_256^{q k}, n = 16 q + k
+        const double ang = -2.0 * M_PI * (double)((n >> 4) * (n & 15)) / 256.0;
+        tw[d.nt + n] = make_float2((float)std::cos(ang), (float)std::sin(ang));
     }
     if ((e = hipMemcpyAsync(p->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice,
                             p->stream)) != hipSuccess)

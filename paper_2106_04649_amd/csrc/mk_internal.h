@@ -31,7 +31,7 @@ enum XPrec : int { XP_F32 = 0, XP_F16 = 1, XP_BF16 = 2, XP_F16X2 = 3, XP_BF16X2 
 //   src [nf][nr][nt]        float, G_d for TM_INIT
 //   f1p, f1m, gp, gm [nf][nr][nt] float
 //   itd [nf][nr], fband [nf][2] (or null), npart [nfo][nr] double
-//   tw  [nt] complex: exp(-2 pi i k / nt)
+//   tw  [nt + 256] complex: exp(-2 pi i k / nt), then exp(-2 pi i q k / 256) at 16 q + k
 struct TraceArgs {
     const float2* Y;
     void* X;           // float2 (XP_F32) or 16-bit pairs (XP_F16 / XP_BF16)
@@ -105,7 +105,7 @@ struct mk_plan_s {
     float* xscale = nullptr;   // [3 nf_max] scale stored with 16-bit X
     double* norms = nullptr;   // [norm_cap][nf_max]
     int norm_cap = 0;
-    float2* tw = nullptr;      // [nt]
+    float2* tw = nullptr;      // [nt + 256]
     int* flag = nullptr;       // device scratch flag (non-finite input detection)
     float* n0 = nullptr;       // [nf_max][nr][nt] N_-1 = G_d(-t)
 
@@ -214,7 +214,7 @@ hipError_t launch_tail_prep(const float* hist, int ntr, int k, int T, float* x, 
 hipError_t launch_tail_apply(const float* hist, const float* y, const float* scale, const int32_t* itd, int shift,
                              int ntr, int k, int T, int nt, int mode, float* f1p, float* f1m, hipStream_t s);
 
-// series-tail network (fixed architecture: k -> 64 -> 64 -> 2 channels, 5 taps)
+// series-tail network (k -> H -> H -> 2 channels, 5 taps, H hidden channels)
 constexpr int kNetHiddenMax = 128;      // widest hidden layer the ABI accepts
 constexpr int kNetDil[3] = {1, 4, 16};
 int net_param_count(int k, int H);
