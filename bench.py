@@ -210,7 +210,8 @@ def combined_path(pb, args, sample, ref, batched, tol=1e-3):
     every output within `tol` of the FP64 oracle on the sampled focal points;
     the plain paths are timed at their own shortest pass counts reaching the
     same accuracy.  Paths: the learned tail (network), the geometric tail, the
-    restart alone (no tail), plain FP16 R and plain FP32 R.
+    restart alone (no tail), each with two-plane and one-plane 16-bit X, then
+    plain FP16 R and plain FP32 R.
     """
     if not os.path.exists(TAIL_WEIGHTS):
         log(f"no trained tail network at {TAIL_WEIGHTS}: combined path skipped")
@@ -219,7 +220,10 @@ def combined_path(pb, args, sample, ref, batched, tol=1e-3):
     params, k, T = w["params"], int(w["k"]), int(w["T"])
     out = {"tol": tol, "k": k, "T": T, "weights": os.path.relpath(TAIL_WEIGHTS, ROOT)}
     n = len(sample)
+    from paper_2106_04649_amd import mk
+
     r16 = Runner(pb, rprec=1, niter=0, tail=(params, k, T, 0, 0))
+    r16x = Runner(pb, rprec=1, niter=0, tail=(params, k, T, 0, 0), flags=mk.MK_FLAG_FAST_X)
     p16 = Runner(pb, rprec=1, niter=32)
     r32 = Runner(pb, rprec=0, niter=32)
 
@@ -228,16 +232,19 @@ def combined_path(pb, args, sample, ref, batched, tol=1e-3):
         return _errs(r.fields(sample), ref, n)
 
     sched, timing = {}, {}
-    for mode, name in ((0, "learned"), (1, "geometric"), (2, "no_tail")):
-        sched[name] = None
-        for extra in (0, 1, 2, 3, 4, 6, 8, 12):
-            r16.tail = (params, k, T, mode, extra)
-            e = errors(r16)
-            if max(e.values()) <= tol:
-                sched[name] = {"extra": extra, "syntheses": k + 2 + extra, "err": e}
-                break
-        if sched[name] is not None:
-            timing[name] = r16.time(args.steps, args.warmup) / args.steps
+    # "_1x": one 16-bit plane of X (MK_FLAG_FAST_X), half the matrix-core products
+    for run, sfx in ((r16, ""), (r16x, "_1x")):
+        for mode, base in ((0, "learned"), (1, "geometric"), (2, "no_tail")):
+            name = base + sfx
+            sched[name] = None
+            for extra in (0, 1, 2, 3, 4, 6, 8, 12):
+                run.tail = (params, k, T, mode, extra)
+                e = errors(run)
+                if max(e.values()) <= tol:
+                    sched[name] = {"extra": extra, "syntheses": k + 2 + extra, "err": e}
+                    break
+            if sched[name] is not None:
+                timing[name] = run.time(args.steps, args.warmup) / args.steps
     for name, r in (("plain_fp16", p16), ("plain_fp32", r32)):
         sched[name] = None
         for P in range(2, 33):
@@ -247,7 +254,7 @@ def combined_path(pb, args, sample, ref, batched, tol=1e-3):
                 sched[name] = {"passes": P, "err": e}
                 timing[name] = r.time(args.steps, args.warmup) / args.steps
                 break
-    for r in (r16, p16, r32):
+    for r in (r16, r16x, p16, r32):
         r.destroy()
     out["schedules"] = sched
     out["ms_per_step"] = {k_: round(v * 1e3, 3) for k_, v in timing.items()}

@@ -137,7 +137,9 @@ mk_status mk_load_R(mk_plan_t plan, const float* R, int on_device);
  * every output and norm comes back in the caller's order.
  * Errors: MK_ERR_ARG (nf outside [1, nf_max], null Gd or itd, negative
  * shift, band outside the plan band, non-finite Gd), MK_ERR_STATE (R not
- * loaded), MK_ERR_HIP.
+ * loaded), MK_ERR_HIP.  The argument checks leave the plan as it was; a
+ * non-finite device Gd (found from its norm, after the arrays were taken in)
+ * and MK_ERR_HIP leave no focal points set.
  */
 mk_status mk_set_focal(mk_plan_t plan, int32_t nf, const float* Gd, const int32_t* itd,
                        int32_t shift, const int32_t* band, int on_device);

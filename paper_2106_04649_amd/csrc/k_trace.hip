@@ -433,6 +433,25 @@ __device__ __forceinline__ void fwd_first_pass(float2* z, const float2 (&x)[NT /
     }
 }
 
+// The time reverse of a trace, (x[(nt - 2m) mod nt], x[nt - 2m - 1]) for
+// m = lane + 64 p, read as aligned pairs (one wave per trace): pair M - 1 - m
+// holds x[nt - 2m - 1] and the even sample of element m + 1, which moves one
+// lane up (lane 63 of p feeds lane 0 of p + 1, and of p = 0 from the last p).
+template <int NT>
+__device__ __forceinline__ void load_reversed(const float* __restrict__ x, int lane, float2 (&out)[NT / 128]) {
+    constexpr int M = NT / 2, PM = M / 64;
+    const float2* x2 = reinterpret_cast<const float2*>(x);
+    float2 v[PM];
+#pragma unroll
+    for (int p = 0; p < PM; ++p) v[p] = x2[M - 1 - (lane + 64 * p)];
+#pragma unroll
+    for (int p = 0; p < PM; ++p) {
+        const float xa = __shfl(v[p].x, (lane + 63) & 63, 64);
+        const float xb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[(p + PM - 1) % PM].x), 63));
+        out[p] = make_float2(lane == 0 ? xb : xa, v[p].y);
+    }
+}
+
 // TPT threads own one trace: 64 (one wave, four traces per block) when the
 // launch has many traces, 256 (the whole block) when it has few, so that a
 // one-focal pass still spreads over every CU.  The traces of a block are
@@ -639,7 +658,11 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
         fft16_passes<NT, -1, 16, LOG2M - 4, ZT>(z, tq, t16, lane);
     } else {
         // ---- spectrum -> time (TM_ITER, TM_GOUT, TM_RST1, TM_RST2) ------------
-        if constexpr (YIN) {
+        if constexpr (YIN && TPT == 64 && M >= 1024) {
+            constexpr int LOG2M = ilog2c(M);
+            inv_first_pass<NT>(z, tq, lane);
+            fft16_passes<NT, +1, 16, LOG2M - 4, ZT>(z, tq, t16, lane);
+        } else if constexpr (YIN) {
             // packed spectrum from bins k and M - k; each thread rewrites its own pair in place
             for (int k = lane; k <= M / 2; k += TPT) {
                 const float2 zk = z[zi(k)], zm = z[zi((M - k) & (M - 1))];
@@ -731,11 +754,15 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
                 if (m < M) z[zi(m)] = out[p];
             }
         } else if constexpr (MODE == TM_INIT) {
-            const float* g = a.src + tbase;
+            const float* g = a.src + tbase;                // N_-1[t] = Gd[(nt - t) mod nt]
+            if constexpr (TPT == 64 && M >= 64) {
+                load_reversed<NT>(g, lane, out);
+            } else {
 #pragma unroll
-            for (int p = 0; p < PM; ++p) {
-                const int m = min(lane + TPT * p, M - 1);
-                out[p] = make_float2(g[(NT - 2 * m) & (NT - 1)], g[NT - 2 * m - 1]);   // N_-1[t] = Gd[(nt - t) mod nt]
+                for (int p = 0; p < PM; ++p) {
+                    const int m = min(lane + TPT * p, M - 1);
+                    out[p] = make_float2(g[(NT - 2 * m) & (NT - 1)], g[NT - 2 * m - 1]);
+                }
             }
 #pragma unroll
             for (int p = 0; p < PM; ++p) {
@@ -762,14 +789,23 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
             }
         } else if constexpr (MODE == TM_GFWD) {
             const bool minus = (fo & 1) != 0;
-#pragma unroll
-            for (int p = 0; p < PM; ++p) {
-                const int m = min(lane + TPT * p, M - 1);
+            if constexpr (TPT == 64 && M >= 64) {
                 if (!minus) {
-                    out[p] = reinterpret_cast<const float2*>(a.f1p + tbase)[m];
-                } else {                             // f1-(-t)
-                    const float* q = a.f1m + tbase;
-                    out[p] = make_float2(q[(NT - 2 * m) & (NT - 1)], q[NT - 2 * m - 1]);
+#pragma unroll
+                    for (int p = 0; p < PM; ++p) out[p] = reinterpret_cast<const float2*>(a.f1p + tbase)[lane + 64 * p];
+                } else {
+                    load_reversed<NT>(a.f1m + tbase, lane, out);     // f1-(-t)
+                }
+            } else {
+#pragma unroll
+                for (int p = 0; p < PM; ++p) {
+                    const int m = min(lane + TPT * p, M - 1);
+                    if (!minus) {
+                        out[p] = reinterpret_cast<const float2*>(a.f1p + tbase)[m];
+                    } else {                             // f1-(-t)
+                        const float* q = a.f1m + tbase;
+                        out[p] = make_float2(q[(NT - 2 * m) & (NT - 1)], q[NT - 2 * m - 1]);
+                    }
                 }
             }
 #pragma unroll
@@ -779,14 +815,23 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
             }
         } else if constexpr (MODE == TM_GOUT) {
             const bool plus = (fo & 1) != 0;
-#pragma unroll
-            for (int p = 0; p < PM; ++p) {
-                const int m = min(lane + TPT * p, M - 1);
+            if constexpr (TPT == 64 && M >= 64) {
                 if (!plus) {
-                    out[p] = reinterpret_cast<const float2*>(a.f1m + tbase)[m];
+#pragma unroll
+                    for (int p = 0; p < PM; ++p) out[p] = reinterpret_cast<const float2*>(a.f1m + tbase)[lane + 64 * p];
                 } else {
-                    const float* q = a.f1p + tbase;
-                    out[p] = make_float2(q[(NT - 2 * m) & (NT - 1)], q[NT - 2 * m - 1]);
+                    load_reversed<NT>(a.f1p + tbase, lane, out);     // f1+(-t)
+                }
+            } else {
+#pragma unroll
+                for (int p = 0; p < PM; ++p) {
+                    const int m = min(lane + TPT * p, M - 1);
+                    if (!plus) {
+                        out[p] = reinterpret_cast<const float2*>(a.f1m + tbase)[m];
+                    } else {
+                        const float* q = a.f1p + tbase;
+                        out[p] = make_float2(q[(NT - 2 * m) & (NT - 1)], q[NT - 2 * m - 1]);
+                    }
                 }
             }
 #pragma unroll
@@ -914,15 +959,15 @@ __global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ x, int 
     if (lane == 0) npart[trace] = acc;
 }
 
-// dst[j] = src[perm[j]] for blocks of `per` floats.
-__global__ void k_gather(const float* __restrict__ src, float* __restrict__ dst,
-                         const int* __restrict__ perm, int nf, int64_t per) {
-    const int64_t total = (int64_t)nf * per;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int j = (int)(i / per);
-        dst[i] = src[(int64_t)perm[j] * per + (i - (int64_t)j * per)];
-    }
+// dst[j] = src[perm[j]] for blocks of `per` elements of type T; block row
+// blockIdx.y is block j.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ src, T* __restrict__ dst,
+                                                const int* __restrict__ perm, int64_t per) {
+    const int j = blockIdx.y;
+    const T* s = src + (int64_t)perm[j] * per;
+    T* d = dst + (int64_t)j * per;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < per; i += (int64_t)gridDim.x * 256) d[i] = s[i];
 }
 
 __global__ __launch_bounds__(256) void k_norm_reduce(const double* __restrict__ npart, int nr,
@@ -1004,10 +1049,16 @@ hipError_t launch_sumsq(const float* x, int ntr, int nt, double* npart, hipStrea
 
 hipError_t launch_gather(const float* src, float* dst, const int* perm, int nf, int64_t per,
                          hipStream_t s) {
-    const int64_t total = (int64_t)nf * per;
-    if (total <= 0) return hipSuccess;
-    const int64_t blocks = (total + 255) / 256;
-    const unsigned g = (unsigned)(blocks < 16384 ? blocks : 16384);
-    hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, s, src, dst, perm, nf, per);
+    if (nf <= 0 || per <= 0) return hipSuccess;
+    const bool v4 = per % 4 == 0 && reinterpret_cast<uintptr_t>(src) % 16 == 0 &&
+                    reinterpret_cast<uintptr_t>(dst) % 16 == 0;
+    const int64_t n = v4 ? per / 4 : per;
+    const int64_t blocks = (n + 255) / 256;
+    const dim3 grid((unsigned)(blocks < 512 ? blocks : 512), (unsigned)nf);
+    if (v4)
+        hipLaunchKernelGGL(k_gather<float4>, grid, dim3(256), 0, s, reinterpret_cast<const float4*>(src),
+                           reinterpret_cast<float4*>(dst), perm, n);
+    else
+        hipLaunchKernelGGL(k_gather<float>, grid, dim3(256), 0, s, src, dst, perm, n);
     return hipGetLastError();
 }

@@ -344,16 +344,6 @@ mk_status copy_in(mk_plan_t p, T* dst, const T* src, size_t n, int on_device, co
     return MK_OK;
 }
 
-mk_status device_all_finite(mk_plan_t p, const float* x, int64_t n, bool* ok) {
-    int h = 0;
-    HIP_TRY(p, hipMemsetAsync(p->flag, 0, sizeof(int), p->stream));
-    HIP_TRY(p, launch_check_finite(x, n, p->flag, p->stream));
-    HIP_TRY(p, hipMemcpyAsync(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(p, hipStreamSynchronize(p->stream));
-    *ok = (h == 0);
-    return MK_OK;
-}
-
 // G+ and G- from one batched synthesis of the interleaved columns
 // [f1+[0], f1-(-t)[0], f1+[1], ...].  Their spectra go to X slabs
 // [nf, 3 nf): slabs [0, nf) hold the spectrum of the last N_i, which the
@@ -571,17 +561,24 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
     for (int j = 0; j < nf; ++j) iperm[perm[j]] = j;
     HIP_TRY(p, hipMemcpyAsync(p->perm, perm.data(), nf * sizeof(int), hipMemcpyHostToDevice, p->stream));
     HIP_TRY(p, hipMemcpyAsync(p->iperm, iperm.data(), nf * sizeof(int), hipMemcpyHostToDevice, p->stream));
-    // G_d and itd in sorted order (G_d lands in the G+ buffer, free until the G assembly)
-    MK_TRY(copy_in(p, p->stage, Gd, ntr * d.nt, on_device, "mk_set_focal: Gd"));
-    if (on_device) {
-        bool ok = true;
-        MK_TRY(device_all_finite(p, p->stage, (int64_t)(ntr * d.nt), &ok));
-        if (!ok) return fail(p, MK_ERR_ARG, "mk_set_focal: Gd holds a non-finite value");
+    // G_d and itd in sorted order (G_d lands in the G+ buffer, free until the G
+    // assembly); device arrays are gathered in place, host arrays through the
+    // staging buffers.  A non-finite device G_d shows up as a non-finite norm
+    // below (the FP64 sum of squares of finite floats cannot overflow).
+    p->focal_set = false;
+    const float* gsrc = Gd;
+    if (!on_device) {
+        MK_TRY(copy_in(p, p->stage, Gd, ntr * d.nt, 0, "mk_set_focal: Gd"));
+        gsrc = p->stage;
     }
-    HIP_TRY(p, launch_gather(p->stage, p->gp, p->perm, nf, (int64_t)d.nr * d.nt, p->stream));
-    int32_t* itd_stage = p->itd + (size_t)d.nf_max * d.nr;
-    MK_TRY(copy_in(p, itd_stage, itd, ntr, on_device, "mk_set_focal: itd"));
-    HIP_TRY(p, launch_gather(reinterpret_cast<const float*>(itd_stage), reinterpret_cast<float*>(p->itd),
+    HIP_TRY(p, launch_gather(gsrc, p->gp, p->perm, nf, (int64_t)d.nr * d.nt, p->stream));
+    const int32_t* isrc = itd;
+    if (!on_device) {
+        int32_t* itd_stage = p->itd + (size_t)d.nf_max * d.nr;
+        MK_TRY(copy_in(p, itd_stage, itd, ntr, 0, "mk_set_focal: itd"));
+        isrc = itd_stage;
+    }
+    HIP_TRY(p, launch_gather(reinterpret_cast<const float*>(isrc), reinterpret_cast<float*>(p->itd),
                              p->perm, nf, d.nr, p->stream));
     if (band) {
         std::vector<int32_t> sb(2 * (size_t)nf);
@@ -629,6 +626,8 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
     std::vector<double> n0(nf);
     HIP_TRY(p, hipMemcpyAsync(n0.data(), p->norm0, nf * sizeof(double), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
+    for (int j = 0; j < nf; ++j)
+        if (!std::isfinite(n0[j])) return fail(p, MK_ERR_ARG, "mk_set_focal: Gd holds a non-finite value");
     p->norm0_host.assign(nf, 0.0);
     for (int j = 0; j < nf; ++j) p->norm0_host[perm[j]] = n0[j];
     p->gd_norm_host = p->norm0_host;
@@ -763,10 +762,20 @@ mk_status mk_get(mk_plan_t p, int32_t field, float* out, int on_device) {
     if ((field == MK_GPLUS || field == MK_GMINUS) && !p->g_valid) MK_TRY(assemble_G(p));
     const size_t per = (size_t)p->d.nr * p->d.nt;
     const size_t n = (size_t)p->nf * per;
-    // back to the caller's focal order
-    HIP_TRY(p, launch_gather(src, p->stage, p->iperm, p->nf, (int64_t)per, p->stream));
-    HIP_TRY(p, hipMemcpyAsync(out, p->stage, n * sizeof(float),
-                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream));
+    // back to the caller's focal order: straight into a device destination,
+    // through the staging buffer for a host one, a plain copy when the plan
+    // kept the caller's order
+    bool identity = true;
+    for (int j = 0; j < p->nf; ++j) identity = identity && p->perm_host[j] == j;
+    if (identity) {
+        HIP_TRY(p, hipMemcpyAsync(out, src, n * sizeof(float),
+                                  on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream));
+    } else if (on_device) {
+        HIP_TRY(p, launch_gather(src, out, p->iperm, p->nf, (int64_t)per, p->stream));
+    } else {
+        HIP_TRY(p, launch_gather(src, p->stage, p->iperm, p->nf, (int64_t)per, p->stream));
+        HIP_TRY(p, hipMemcpyAsync(out, p->stage, n * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+    }
     if (!on_device) HIP_TRY(p, hipStreamSynchronize(p->stream));
     return MK_OK;
 }

@@ -34,6 +34,18 @@ def test_small_problems(seed, n, nt, nf):
     assert g["passes"] == 8
 
 
+@pytest.mark.parametrize("nt", [128, 256, 1024, 2048, 4096])
+def test_one_wave_per_trace(nt):
+    """2048 traces: the one-wave-per-trace epilogue at every transform length
+    (the fused pass at nt 2048 and 4096), with the G assembly."""
+    say(f"one wave per trace nt={nt}")
+    p = small_problem(seed=40 + nt % 97, n=32, nt=nt, nf=64, niter=5, rho_target=0.6)
+    g = run_gpu(p)
+    r = run_oracle(p)
+    assert_parity(g, r, label=f"wave-per-trace nt{nt}")
+    _norm_check(g["norms"], r["norms"])
+
+
 def test_hand_derived_spike_cases(golden_dir):
     """The closed-form worked examples of tests/golden, run on the GPU."""
     import cmath
@@ -148,6 +160,42 @@ def test_error_paths():
     with pytest.raises(mk.MKError) as ei:
         mk.mk_set_focal(plan, p.Gd, p.itd, p.shift, np.array([[0, 40]], np.int32))
     assert ei.value.status == mk.MK_ERR_ARG
+    mk.mk_destroy(plan)
+
+
+def test_device_inputs_and_outputs():
+    """Device G_d / itd / bands and device outputs: the same values as the host
+    path; a non-finite device G_d is refused and leaves no focal points set."""
+    mk = require_gpu()
+    import torch
+
+    say("device inputs and outputs")
+    p = small_problem(seed=12, n=24, nt=128, nf=5, niter=4)
+    band = np.array([[2, 60], [0, 64], [5, 40], [1, 64], [3, 50]], np.int32)
+    plan = mk.mk_plan(24, 24, 128, p.geom.dt, p.geom.dx, band=p.band, nf_max=5)
+    mk.mk_load_R(plan, p.Rhat)
+    mk.mk_set_focal(plan, p.Gd, p.itd, p.shift, band)
+    mk.mk_iterate(plan, 4)
+    host = {k: mk.mk_get(plan, k, np.zeros(p.Gd.shape, np.float32)) for k in ("f1plus", "Gminus")}
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()      # noqa: E731
+    mk.mk_set_focal(plan, d(p.Gd), d(p.itd), p.shift, d(band))
+    mk.mk_iterate(plan, 4)
+    for k in ("f1plus", "Gminus"):
+        out = torch.empty(p.Gd.shape, dtype=torch.float32, device="cuda")
+        mk.mk_get(plan, k, out)
+        assert np.array_equal(out.cpu().numpy(), host[k]), k
+    for bad in (np.inf, np.nan):
+        g = p.Gd.copy()
+        g[3, 7, 11] = bad
+        with pytest.raises(mk.MKError) as ei:
+            mk.mk_set_focal(plan, d(g), d(p.itd), p.shift, d(band))
+        assert ei.value.status == mk.MK_ERR_ARG
+        with pytest.raises(mk.MKError) as ei:
+            mk.mk_iterate(plan, 1)
+        assert ei.value.status == mk.MK_ERR_STATE
+    mk.mk_set_focal(plan, d(p.Gd), d(p.itd), p.shift, d(band))
+    mk.mk_iterate(plan, 4)
+    assert np.array_equal(mk.mk_get(plan, "f1plus", np.zeros(p.Gd.shape, np.float32)), host["f1plus"])
     mk.mk_destroy(plan)
 
 

@@ -108,6 +108,16 @@ def test_network_tail_matches_reference(tune, hidden):
     _compare(g, _ref(p, 0, 2, Pr), "net", tol=2e-5)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+def test_tail_one_wave_per_trace(mode):
+    """2048 traces at nt 2048: the restart kernels in their one-wave-per-trace
+    (fused) form, geometric tail and restart alone."""
+    say(f"tail one wave per trace, mode {mode}")
+    p = small_problem(seed=77, n=32, nt=2048, nf=64, niter=8)
+    g = _gpu(p, mode, 2)
+    _compare(g, _ref(p, mode, 2), f"wave-per-trace mode {mode}", tol=2e-5)
+
+
 def test_tail_state_errors():
     mk = require_gpu()
     p = small_problem(seed=74, n=8, nt=64, nf=1)
