@@ -177,8 +177,9 @@ def _dip_tables(geom: Geometry, model: LayerModel, tmax: float):
 
 
 def reflection_response(geom: Geometry, model: LayerModel, band: Tuple[int, int],
-                        threads: Optional[int] = None) -> np.ndarray:
-    """R-hat in receivers x frequencies x shots layout, complex64 [n][B][n]."""
+                        threads: Optional[int] = None, rows: Optional[Sequence[int]] = None) -> np.ndarray:
+    """R-hat in receivers x frequencies x shots layout, complex64 [n][B][n]
+    (only the receiver rows ``rows``, in that order, when given)."""
     lo, hi = band
     w = np.arange(lo, hi + 1)
     freqs = w / (geom.nt * geom.dt)
@@ -187,11 +188,13 @@ def reflection_response(geom: Geometry, model: LayerModel, band: Tuple[int, int]
     flat = _flat_offset_table(geom, model, freqs, tmax) * wav[None, :]   # [h][B]
     dips = _dip_tables(geom, model, tmax)
     n = geom.n
-    out = np.empty((n, w.size, n), dtype=np.complex64)
+    rlist = list(range(n)) if rows is None else [int(r) for r in rows]
+    out = np.empty((len(rlist), w.size, n), dtype=np.complex64)
     sidx = np.arange(n)
     twopi_f = (2.0 * np.pi) * freqs
 
-    def row(r: int) -> None:
+    def row(j: int) -> None:
+        r = rlist[j]
         acc = flat[np.abs(r - sidx)].T.copy()                          # [B][s]
         for tau, amp in dips:
             ph = twopi_f[:, None] * tau[r][None, :]
@@ -200,15 +203,15 @@ def reflection_response(geom: Geometry, model: LayerModel, band: Tuple[int, int]
             acc[0].imag = 0.0
         if hi == geom.nt // 2:
             acc[-1].imag = 0.0                                          # rfft of a real trace
-        out[r] = acc
+        out[j] = acc
 
     nthreads = threads or min(16, os.cpu_count() or 1)
-    if n * w.size * n < 4_000_000 or nthreads == 1:
-        for r in range(n):
-            row(r)
+    if len(rlist) * w.size * n < 4_000_000 or nthreads == 1:
+        for j in range(len(rlist)):
+            row(j)
     else:
         with ThreadPoolExecutor(max_workers=nthreads) as ex:
-            list(ex.map(row, range(n)))
+            list(ex.map(row, range(len(rlist))))
     return out
 
 

@@ -16,7 +16,7 @@ from typing import Optional, Tuple
 
 import numpy as np
 
-from .layered import (Geometry, LayerModel, Problem, _dip_tables, _flat_offset_table, direct_arrivals,
+from .layered import (CONFIGS, Geometry, LayerModel, Problem, _dip_tables, _flat_offset_table, direct_arrivals,
                       random_layer_model, ricker_spectrum)
 
 
@@ -113,3 +113,67 @@ def medium_problem_gpu(seed: int, nf: int = 64, rho_target: float = 0.7, n: int 
     shift = int(math.ceil(1.0 / (geom.fpeak * geom.dt)))
     return Problem(name=f"medium{seed}", geom=geom, model=model, Rhat=R, band=band, Gd=Gd, itd=itd, shift=shift,
                    niter=32, xf=xf, zf=zf, rho=rho_target, rscale=scale)
+
+
+def large_setup():
+    """Geometry, earth model and focal grid of the 2001 x 2001 workload: the
+    draws of ``layered.make_config("large")``, with 2048 focal points on a
+    64 x 32 grid (x over the middle 60 %, depths 200-1200 m)."""
+    cfg = CONFIGS["large"]
+    rng = np.random.default_rng(cfg["seed"])
+    geom = Geometry(n=cfg["n"], dx=cfg["dx"], nt=cfg["nt"], dt=cfg["dt"])
+    L = (geom.n - 1) * geom.dx
+    model = random_layer_model(rng, cfg["nlayers"], cfg["zrange"], ndips=cfg["ndips"], xrange=(0.3 * L, 0.7 * L),
+                               nabove=cfg["nabove"], zsplit=cfg["zsplit"])
+    gx, gz = np.meshgrid(np.linspace(0.2 * L, 0.8 * L, 64), np.linspace(200.0, 1200.0, 32))
+    return geom, model, gx.ravel(), gz.ravel()
+
+
+def rho_all_bins_gpu(R, c: float, chunk: int = 64, iters: int = 25, seed: int = 7) -> float:
+    """c times the largest singular value over every frequency slice of R
+    (batched power iteration, ``chunk`` bins at a time)."""
+    import torch
+
+    B = R.shape[1]
+    g = torch.Generator(device=R.device).manual_seed(seed)
+    best = 0.0
+    for w0 in range(0, B, chunk):
+        A = R[:, w0:w0 + chunk, :].permute(1, 0, 2).contiguous()                  # [b][r][s]
+        b, _, ns = A.shape
+        v = torch.complex(torch.randn(b, ns, 1, device=R.device, generator=g),
+                          torch.randn(b, ns, 1, device=R.device, generator=g))
+        v = v / torch.linalg.vector_norm(v, dim=1, keepdim=True)
+        s = torch.zeros(b, device=R.device)
+        for _ in range(iters):
+            u = torch.bmm(A, v)                                                     # A v
+            vh = torch.bmm(u.conj().transpose(1, 2).contiguous(), A)               # (A^H u)^H
+            v = vh.conj().transpose(1, 2).contiguous()
+            nv = torch.linalg.vector_norm(v, dim=1, keepdim=True)
+            s = torch.sqrt(nv.reshape(-1))
+            v = v / torch.clamp(nv, min=1e-30)
+        best = max(best, float(s.max().item()))
+        del A
+    return c * best
+
+
+def large_focal(geom: Geometry, model: LayerModel, xf, zf, idx):
+    """G_d and itd of the focal points ``idx`` of the large workload's grid."""
+    idx = np.asarray(idx, dtype=np.int64)
+    return direct_arrivals(geom, model, np.asarray(xf)[idx], np.asarray(zf)[idx])
+
+
+def large_problem_gpu(focal_idx, rho_target: float = 0.7, device="cuda") -> Problem:
+    """The 2001 x 2001, nt 2048 workload with R (complex64, 32.8 GB) on the GPU,
+    scaled so that c times its largest singular value is ``rho_target``, and
+    G_d for the focal points ``focal_idx`` of the 64 x 32 grid."""
+    geom, model, xf, zf = large_setup()
+    band = (0, geom.nt // 2)
+    R = reflection_response_gpu(geom, model, band, device)
+    rho = rho_all_bins_gpu(R, geom.c)
+    scale = rho_target / rho if rho > 0 else 1.0
+    R *= scale
+    Gd, itd = large_focal(geom, model, xf, zf, focal_idx)
+    shift = int(math.ceil(1.0 / (geom.fpeak * geom.dt)))
+    idx = np.asarray(focal_idx, dtype=np.int64)
+    return Problem(name="large", geom=geom, model=model, Rhat=R, band=band, Gd=Gd, itd=itd, shift=shift,
+                   niter=32, xf=np.asarray(xf)[idx], zf=np.asarray(zf)[idx], rho=rho_target, rscale=scale)
