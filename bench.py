@@ -73,6 +73,16 @@ def contract_bytes(nr: int, ns: int, B: int, ncols: int, r_bytes: int = 8, x_byt
     return r_bytes * nr * ns * B + x_bytes * ns * B * ncols + 8 * nr * B * ncols
 
 
+def rel_l2(a, b) -> float:
+    """||a - b||_2 / ||b||_2 in FP64 (0 when both vanish)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb, na = np.linalg.norm(b), np.linalg.norm(a - b)
+    return 0.0 if nb == 0.0 and na == 0.0 else (float("inf") if nb == 0.0 else float(na / nb))
+
+
+# ---- the CPU oracle leg: every use of the FP64 oracle in this file ---------
+
 def cpu_baseline(p, passes: int) -> dict:
     """The FP64 oracle on this host: one whole solve (passes + G assembly)."""
     from oracle import SynthesisOperator, marchenko
@@ -97,6 +107,18 @@ def cpu_baseline(p, passes: int) -> dict:
                    f"assembly (2 more syntheses), nf={p.nf}, numpy FP64 (pocketfft + OpenBLAS zgemm); "
                    f"{t2 - t1:.1f} s, R upcast {t1 - t0:.1f} s not counted"),
     }
+
+
+def oracle_reference(pb, sample, niter):
+    """The FP64 oracle's fields for the sampled focal points of the batch (the
+    accuracy reference of the batched and combined paths)."""
+    from oracle import SynthesisOperator, marchenko
+
+    sub = type(pb)(**{**pb.__dict__, "Gd": pb.Gd[sample], "itd": pb.itd[sample]})
+    return marchenko(SynthesisOperator(pb.Rhat, pb.band, pb.c, pb.geom.nt), sub.Gd, sub.itd, sub.shift, niter)
+
+
+# ---- the GPU paths ------------------------------------------------------------
 
 
 class Runner:
@@ -198,8 +220,6 @@ TAIL_WEIGHTS = os.path.join(ROOT, "paper_2106_04649_amd", "tailnet_medium_k4.npz
 
 
 def _errs(got, ref, n):
-    from oracle import rel_l2
-
     return {k: max(rel_l2(got[k][j], ref[k][j]) for j in range(n)) for k in ("f1plus", "f1minus", "Gplus", "Gminus")}
 
 
@@ -270,6 +290,128 @@ def combined_path(pb, args, sample, ref, batched, tol=1e-3):
     return out
 
 
+def large_run(args) -> dict:
+    """The 2001 x 2001, nt 2048 workload at full size: 2048 focal points of
+    the 64 x 32 grid in batches, the mixed path (FP16 R, one 16-bit plane of
+    X, 4 recorded passes, geometric tail and restart, more passes) against
+    plain complex64 R on this GPU.  Each path's pass count is the smallest
+    reaching `tol` relative L2 (every field, every focal point) against 32
+    plain complex64 passes on 8 focal points spread over the grid; the whole
+    grid is then solved with those schedules, G+/G- included, inputs in HBM."""
+    import torch
+
+    from mkgen.torchgen import direct_arrivals_gpu, large_problem_gpu, large_setup
+    from paper_2106_04649_amd import mk
+
+    tol, NB, NF = 1e-3, args.large_batch, 2048
+    t = time.perf_counter()
+    p = large_problem_gpu([0])
+    geom, model, xf, zf = large_setup()
+    n, nt = geom.n, geom.nt
+    log(f"large: R {tuple(p.Rhat.shape)} built in {time.perf_counter() - t:.1f} s")
+    stream = torch.cuda.current_stream()
+    names = ("f1plus", "f1minus", "Gplus", "Gminus")
+
+    def plan_for(rprec, flags):
+        plan = mk.mk_plan(n, n, nt, geom.dt, geom.dx, band=p.band, nf_max=NB, rprec=rprec, flags=flags,
+                          stream=stream.cuda_stream)
+        mk.mk_load_R(plan, p.Rhat)
+        return plan
+
+    def focal(idx):
+        Gd, itd = direct_arrivals_gpu(geom, model, xf[idx], zf[idx])
+        return Gd, torch.from_numpy(itd).cuda()
+
+    def fields(plan, nfb):
+        return {k: mk.mk_get(plan, k, torch.empty((nfb, n, nt), device="cuda")) for k in names}
+
+    def err(got, ref):
+        worst = 0.0
+        for k in names:
+            d = torch.linalg.vector_norm((got[k] - ref[k]).reshape(got[k].shape[0], -1).double(), dim=1)
+            r = torch.linalg.vector_norm(ref[k].reshape(ref[k].shape[0], -1).double(), dim=1)
+            worst = max(worst, float((d / torch.clamp(r, min=1e-300)).max().item()))
+        return worst
+
+    plain = plan_for(0, 0)
+    mixed = plan_for(1, mk.MK_FLAG_FAST_X)
+    mk.mk_tail_record(mixed, 4, 1024)
+    p.Rhat = None
+    torch.cuda.empty_cache()
+
+    # ---- schedules on 8 focal points ----------------------------------------
+    idx8 = np.linspace(0, NF - 1, 8).round().astype(int)
+    G8, I8 = focal(idx8)
+    mk.mk_set_focal(plain, G8, I8, p.shift)
+    mk.mk_iterate(plain, 32, want_norms=False)
+    ref = fields(plain, 8)
+    P = None
+    for cand in range(4, 33):
+        mk.mk_set_focal(plain, G8, I8, p.shift)
+        mk.mk_iterate(plain, cand, want_norms=False)
+        if err(fields(plain, 8), ref) <= tol:
+            P = cand
+            break
+    extra, e_mixed = None, None
+    for cand in (0, 1, 2, 3, 4, 6, 8, 10, 12, 16):
+        mk.mk_set_focal(mixed, G8, I8, p.shift)
+        mk.mk_iterate(mixed, 4, want_norms=False)
+        mk.mk_tail_apply(mixed, 1)
+        if cand:
+            mk.mk_iterate(mixed, cand, want_norms=False)
+        e = err(fields(mixed, 8), ref)
+        if e <= tol:
+            extra, e_mixed = cand, e
+            break
+    log(f"large: schedules plain {P} passes, mixed 4 + 2 + {extra}")
+    del ref
+    torch.cuda.empty_cache()
+
+    # ---- the whole grid ------------------------------------------------------
+    outp = torch.empty((NB, n, nt), device="cuda")
+    outm = torch.empty_like(outp)
+
+    def solve(plan, Gd, itd, is_mixed):
+        mk.mk_set_focal(plan, Gd, itd, p.shift)
+        if is_mixed:
+            mk.mk_iterate(plan, 4, want_norms=False)
+            mk.mk_tail_apply(plan, 1)
+            if extra:
+                mk.mk_iterate(plan, extra, want_norms=False)
+        else:
+            mk.mk_iterate(plan, P, want_norms=False)
+        nfb = Gd.shape[0]
+        mk.mk_get(plan, "Gplus", outp[:nfb])
+        mk.mk_get(plan, "Gminus", outm[:nfb])
+
+    times = {"plain": 0.0, "mixed": 0.0}
+    if P is not None and extra is not None:
+        for b0 in range(0, NF, NB):
+            idx = np.arange(b0, min(NF, b0 + NB))
+            Gd, itd = focal(idx)
+            for name, plan in (("plain", plain), ("mixed", mixed)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                solve(plan, Gd, itd, name == "mixed")
+                torch.cuda.synchronize()
+                times[name] += time.perf_counter() - t0
+            log(f"large: focal points {b0}..{idx[-1]} done")
+    mk.mk_destroy(plain)
+    mk.mk_destroy(mixed)
+    rec = {
+        "config": "large: 2001 x 2001 shots/receivers at 5 m, nt 2048 at 2 ms, complex64 R 32.8 GB / "
+                  "FP16 R 16.4 GB, 2048 focal points on a 64 x 32 grid (x 2000-8000 m, z 200-1200 m)",
+        "batch": NB, "tol": tol,
+        "schedule": {"plain_fp32_passes": P, "mixed_syntheses": None if extra is None else 4 + 2 + extra,
+                     "mixed_extra_passes": extra, "mixed_err_vs_plain32": e_mixed},
+        "seconds": {k: round(v, 3) for k, v in times.items()},
+    }
+    if times["mixed"] > 0:
+        rec["focal_per_s"] = {k: round(NF / v, 1) for k, v in times.items()}
+        rec["mixed_over_plain"] = round(times["plain"] / times["mixed"], 3)
+    return rec
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,6 +428,9 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-combined", action="store_true", help="skip the FP16 + learned-tail schedule search")
     ap.add_argument("--graph", action="store_true", help="replay the passes as HIP graphs")
+    ap.add_argument("--large", action="store_true",
+                    help="instead of the headline: the 2001 x 2001 workload, mixed path against plain FP32")
+    ap.add_argument("--large-batch", type=int, default=256, help="focal points per plan in --large")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -295,6 +440,11 @@ def main() -> int:
         return 2
 
     import torch
+
+    if args.large:
+        torch.cuda.set_device(0)
+        print(json.dumps(large_run(args)), flush=True)
+        return 0
 
     if args.copy_calib:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -348,15 +498,11 @@ def main() -> int:
     # ---- a batch of focal points: plain FP32 vs FP16 R -----------------------
     batched = None
     if not args.no_batched and args.batch_nf > 1:
-        from oracle import SynthesisOperator, marchenko, rel_l2
-
         log(f"generating the batch (nf={args.batch_nf})")
         pb = make_config("medium", nf=args.batch_nf)
         batched = {"nf": pb.nf, "paths": {}}
         sample = [0, pb.nf - 1]
-        sub = type(pb)(**{**pb.__dict__, "Gd": pb.Gd[sample], "itd": pb.itd[sample]})
-        ref = marchenko(SynthesisOperator(pb.Rhat, pb.band, pb.c, pb.geom.nt), sub.Gd, sub.itd,
-                        sub.shift, args.niter)
+        ref = oracle_reference(pb, sample, args.niter)
         for name, rprec in (("fp32", 0), ("fp16", 1)):
             r = Runner(pb, rprec=rprec, flags=gflags, niter=args.niter)
             w = r.time(args.steps, args.warmup)

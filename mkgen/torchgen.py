@@ -177,3 +177,35 @@ def large_problem_gpu(focal_idx, rho_target: float = 0.7, device="cuda") -> Prob
     idx = np.asarray(focal_idx, dtype=np.int64)
     return Problem(name="large", geom=geom, model=model, Rhat=R, band=band, Gd=Gd, itd=itd, shift=shift,
                    niter=32, xf=np.asarray(xf)[idx], zf=np.asarray(zf)[idx], rho=rho_target, rscale=scale)
+
+
+def direct_arrivals_gpu(geom: Geometry, model: LayerModel, xf, zf, device="cuda"):
+    """``layered.direct_arrivals`` evaluated on the GPU: G_d [nf][n][nt] float32
+    (a CUDA tensor) and itd [nf][n] int32 (numpy).  Same formula; the values
+    agree to float32 rounding."""
+    import torch
+
+    xf = np.asarray(xf, dtype=np.float64)
+    zf = np.asarray(zf, dtype=np.float64)
+    nf = xf.size
+    w = np.arange(geom.nw)
+    freqs = torch.from_numpy(w / (geom.nt * geom.dt)).to(device)
+    wav = torch.from_numpy(ricker_spectrum(w / (geom.nt * geom.dt), geom.fpeak) / geom.dt).to(device)
+    x = torch.from_numpy(geom.x).to(device)
+    t1v = np.empty(nf)
+    vr = np.empty(nf)
+    for f in range(nf):
+        t1v[f], vr[f] = model.vertical_time_and_vrms(float(zf[f]))
+    t1 = torch.from_numpy(t1v).to(device)[:, None]
+    vrms = torch.from_numpy(vr).to(device)[:, None]
+    td = torch.sqrt(t1 ** 2 + ((x[None, :] - torch.from_numpy(xf).to(device)[:, None]) / vrms) ** 2)   # [nf][n]
+    amp = torch.sqrt(t1 / td)
+    Gd = torch.empty((nf, geom.n, geom.nt), dtype=torch.float32, device=device)
+    for f0 in range(0, nf, 16):
+        f1 = min(nf, f0 + 16)
+        ph = -2.0 * math.pi * freqs[None, None, :] * td[f0:f1, :, None]
+        spec = (wav[None, None, :] * amp[f0:f1, :, None]) * torch.exp(1j * ph)
+        spec[..., -1] = spec[..., -1].real
+        Gd[f0:f1] = torch.fft.irfft(spec, geom.nt, dim=-1).to(torch.float32)
+    itd = torch.round(td / geom.dt).to(torch.int32).cpu().numpy()
+    return Gd, itd
