@@ -46,15 +46,25 @@ __global__ __launch_bounds__(256) void k_tail_apply(const float* __restrict__ hi
     const int L = itd[tr] - shift;
     const int hT = T >> 1;
     float ge = 0.f, go = 0.f, se = 0.f;
+    constexpr int U = 8;                       // samples per lane whose loads are in flight together
     if (mode == 1) {
         // ratio of the norms of the last two iterates of each parity
         float n[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int u = lane; u < T; u += 64)
+        for (int u0 = 0; u0 < T; u0 += 64 * U) {
+            float v[U][4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const float v = h[(size_t)(k - 4 + c) * T + u];
-                n[c] += v * v;
+            for (int j = 0; j < U; ++j) {
+                const int u = min(u0 + lane + 64 * j, T - 1);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v[j][c] = h[(size_t)(k - 4 + c) * T + u];
             }
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                if (u0 + lane + 64 * j < T) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) n[c] += v[j][c] * v[j][c];
+                }
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) n[c] = sqrtf(wave_sum_f(n[c]));
         // k even: channels k-4, k-2 are even passes; k-3, k-1 odd passes
@@ -67,21 +77,39 @@ __global__ __launch_bounds__(256) void k_tail_apply(const float* __restrict__ hi
     }
     float* fp = f1p + (size_t)tr * nt;
     float* fm = f1m + (size_t)tr * nt;
-    for (int u = lane; u < T; u += 64) {
-        const int t = u - hT;
-        if (!(t < L && -t < L) || t == nt / 2 || -t == nt / 2) continue;
-        float te, to;
-        if (mode == 1) {
-            te = ge * h[(size_t)(k - 2) * T + u];
-            to = go * h[(size_t)(k - 1) * T + u];
-        } else {
-            te = se * y[((size_t)tr * 2 + 0) * T + u];
-            to = se * y[((size_t)tr * 2 + 1) * T + u];
+    // window samples t = u - T/2 with |t| < L (t = +-nt/2 excluded); every
+    // read of a group is issued before the first update (addresses of samples
+    // outside the window are clamped to the trace's first sample and unused)
+    for (int u0 = 0; u0 < T; u0 += 64 * U) {
+        float te[U], to[U], pv[U], mv[U];
+        int ip[U], im[U];
+        bool in[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int u = u0 + lane + 64 * j;
+            const int t = u - hT;
+            in[j] = (u < T) & (t < L) & (-t < L) & (t != nt / 2) & (-t != nt / 2);
+            const int uc = min(u, T - 1);
+            if (mode == 1) {
+                te[j] = h[(size_t)(k - 2) * T + uc];
+                to[j] = h[(size_t)(k - 1) * T + uc];
+            } else {
+                te[j] = y[((size_t)tr * 2 + 0) * T + uc];
+                to[j] = y[((size_t)tr * 2 + 1) * T + uc];
+            }
+            ip[j] = in[j] ? ((t % nt) + nt) % nt : 0;
+            im[j] = in[j] ? ((-t % nt) + nt) % nt : 0;
+            pv[j] = fp[ip[j]];
+            mv[j] = fm[im[j]];
         }
-        const int ip = ((t % nt) + nt) % nt;
-        const int im = ((-t % nt) + nt) % nt;
-        fp[ip] += to;                         // odd passes feed f1+
-        fm[im] -= te;                         // even passes feed f1- -= N(-t)
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (!in[j]) continue;
+            const float e = mode == 1 ? ge * te[j] : se * te[j];
+            const float o = mode == 1 ? go * to[j] : se * to[j];
+            fp[ip[j]] = pv[j] + o;               // odd passes feed f1+
+            fm[im[j]] = mv[j] - e;               // even passes feed f1- -= N(-t)
+        }
     }
 }
 

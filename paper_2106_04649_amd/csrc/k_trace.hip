@@ -473,7 +473,9 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
     constexpr int TQN = NT / 4, TQP = (TQN + 255) / 256;
     constexpr bool GMODE = MODE == TM_GFWD || MODE == TM_GOUT;
     constexpr bool YIN = MODE == TM_ITER || MODE == TM_GOUT || MODE == TM_RST1 || MODE == TM_RST2;
-    constexpr bool FUSED = (MODE == TM_ITER || MODE == TM_RST1) && TPT == 64 && (M == 1024 || M == 2048);
+    constexpr bool FUSED = (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2) && TPT == 64 &&
+                           (M == 1024 || M == 2048);
+    constexpr bool NEGCONJ = FUSED && MODE != TM_RST2;    // the next field is a time reverse
     // the span-16 twiddle table lives in the padding of the four trace regions
     constexpr int ZT = (TPT == 64 && M >= 1024) ? ZS : 0;
     __shared__ float2 lds[TPB * ZS];
@@ -595,7 +597,7 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
             const float q0 = win(2 * idx) ? s * x[e].x : 0.f;
             const float q1 = win(2 * idx + 1) ? s * x[e].y : 0.f;
             x[e] = make_float2(q0, q1);
-            nacc += (double)q0 * q0 + (double)q1 * q1;
+            if constexpr (MODE != TM_RST2) nacc += (double)q0 * q0 + (double)q1 * q1;
         }
         if constexpr (MODE == TM_ITER) {
             // Even passes add Q to f1- element by element.  Odd passes
@@ -646,11 +648,46 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
                     }
                 }
             }
-        } else {                                // TM_RST1: f1- := theta S f1+ = Q
+        } else if constexpr (MODE == TM_RST1) {  // f1- := theta S f1+ = Q
             if (valid) {
 #pragma unroll
                 for (int e = 0; e < QN; ++e)
                     reinterpret_cast<float2*>(a.f1m + tbase)[lane + 64 * e] = x[e];
+            }
+        } else {
+            // TM_RST2: N'' = -Q(-t); f1+ := N_-1 + N''; the residual rho = N_-1 + N'' - f1+
+            // (old) feeds the next pass, unreversed.  Sample 2 idx of element
+            // idx = l + 64 e reverses to element M - idx (x): lane 64 - l of
+            // e' = QN - 1 - e, or lane 0 of (QN - e) mod QN; sample 2 idx + 1 to
+            // element M - idx - 1 (y): lane 63 - l of QN - 1 - e.
+            const float2* n0p = reinterpret_cast<const float2*>(a.n0 + tbase);
+            float2* fpp = reinterpret_cast<float2*>(a.f1p + tbase);
+            float2 xr[QN];
+#pragma unroll
+            for (int e = 0; e < QN; ++e) {
+                const float ra = __shfl(x[QN - 1 - e].x, (64 - lane) & 63, 64);
+                const float rb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[(QN - e) % QN].x), 0));
+                const float ry = __shfl(x[QN - 1 - e].y, 63 - lane, 64);
+                xr[e] = make_float2(lane == 0 ? rb : ra, ry);
+            }
+            constexpr int FCH = 8;              // elements whose reads are in flight together
+#pragma unroll
+            for (int e0 = 0; e0 < QN; e0 += FCH) {
+                float2 b0[FCH], fo[FCH];
+#pragma unroll
+                for (int c = 0; c < FCH; ++c) {
+                    b0[c] = n0p[lane + 64 * (e0 + c)];
+                    fo[c] = fpp[lane + 64 * (e0 + c)];
+                }
+#pragma unroll
+                for (int c = 0; c < FCH; ++c) {
+                    const int e = e0 + c;
+                    const float2 nf2 = make_float2(b0[c].x - xr[e].x, b0[c].y - xr[e].y);
+                    const float2 rho = make_float2(nf2.x - fo[c].x, nf2.y - fo[c].y);
+                    nacc += (double)rho.x * rho.x + (double)rho.y * rho.y;
+                    if (valid) fpp[lane + 64 * e] = nf2;
+                    x[e] = rho;
+                }
             }
         }
         fwd_first_pass<NT>(z, x, lane);
@@ -881,7 +918,7 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
         const bool in = (k >= flo) & (k <= fhi);
         return make_float2(in ? e2.x + wd.y : 0.f, in ? e2.y - wd.x : 0.f);
     };
-    const float cj = FUSED ? -1.f : 1.f;      // fused pass: X = -conj(FFT Q)
+    const float cj = NEGCONJ ? -1.f : 1.f;    // fused pass: X = -conj(FFT Q)
     if (a.xprec == XP_F32) {
         float2* Xt = reinterpret_cast<float2*>(a.X) + xoff;
 #pragma unroll

@@ -108,12 +108,12 @@ def test_network_tail_matches_reference(tune, hidden):
     _compare(g, _ref(p, 0, 2, Pr), "net", tol=2e-5)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
-def test_tail_one_wave_per_trace(mode):
-    """2048 traces at nt 2048: the restart kernels in their one-wave-per-trace
-    (fused) form, geometric tail and restart alone."""
-    say(f"tail one wave per trace, mode {mode}")
-    p = small_problem(seed=77, n=32, nt=2048, nf=64, niter=8)
+@pytest.mark.parametrize("mode,nt", [(1, 2048), (2, 2048), (1, 4096)])
+def test_tail_one_wave_per_trace(mode, nt):
+    """2048 traces at nt 2048 and 4096: the restart kernels in their
+    one-wave-per-trace (fused) form, geometric tail and restart alone."""
+    say(f"tail one wave per trace, mode {mode}, nt {nt}")
+    p = small_problem(seed=77, n=32, nt=nt, nf=64, niter=8)
     g = _gpu(p, mode, 2)
     _compare(g, _ref(p, mode, 2), f"wave-per-trace mode {mode}", tol=2e-5)
 
