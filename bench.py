@@ -257,11 +257,13 @@ def combined_path(pb, args, sample, ref, batched, tol=1e-3):
         for mode, base in ((0, "learned"), (1, "geometric"), (2, "no_tail")):
             name = base + sfx
             sched[name] = None
+            tried = {}
             for extra in (0, 1, 2, 3, 4, 6, 8, 12):
                 run.tail = (params, k, T, mode, extra)
                 e = errors(run)
+                tried[extra] = float(f"{max(e.values()):.3e}")
                 if max(e.values()) <= tol:
-                    sched[name] = {"extra": extra, "syntheses": k + 2 + extra, "err": e}
+                    sched[name] = {"extra": extra, "syntheses": k + 2 + extra, "err": e, "tried": tried}
                     break
             if sched[name] is not None:
                 timing[name] = run.time(args.steps, args.warmup) / args.steps
