@@ -607,7 +607,6 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
         HIP_TRY(p, hipStreamSynchronize(p->stream));    // host vectors go out of scope
     }
     p->has_fband = band != nullptr;
-    drop_graphs(p);                    // captured passes depend on nf, bands and choices
     p->perm_host = perm;
     p->nf = nf;
     p->shift = shift;
@@ -673,7 +672,9 @@ mk_status replay_passes(mk_plan_t p, int n, int parity0) {
     const int i0 = 0;
     hipGraphExec_t exec = nullptr;
     for (auto& g : p->graphs)
-        if (g.niter == n && g.parity == parity0) exec = g.exec;
+        if (g.niter == n && g.parity == parity0 && g.nf == p->nf && g.fband == p->has_fband &&
+            g.shift == p->shift && g.variant == p->series_choice.variant && g.xprec == p->series_choice.xprec)
+            exec = g.exec;
     if (!exec) {
         hipStream_t cs = p->capture_stream ? p->capture_stream : p->stream;
         hipStream_t keep = p->stream;
@@ -695,7 +696,9 @@ mk_status replay_passes(mk_plan_t p, int n, int parity0) {
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return hip_fail(p, e, "hipGraphInstantiate");
-        p->graphs.push_back({n, parity0, exec});
+        if (p->graphs.size() >= 32) drop_graphs(p);      // bound the cache of executables
+        p->graphs.push_back({n, parity0, p->nf, p->has_fband, p->shift, p->series_choice.variant,
+                             p->series_choice.xprec, exec});
     }
     hipError_t e = hipGraphLaunch(exec, p->stream);
     if (e != hipSuccess) return hip_fail(p, e, "hipGraphLaunch");

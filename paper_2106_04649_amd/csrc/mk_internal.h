@@ -138,9 +138,16 @@ struct mk_plan_s {
     ContractChoice series_choice, g_choice;
 
     // graph replay (MK_FLAG_GRAPH): one executable per (passes, start parity)
+    // and per state the captured launches hold by value (batch width, bands,
+    // mute margin, contraction choice)
     struct GraphEntry {
         int niter;
         int parity;
+        int nf;
+        bool fband;
+        int shift;
+        int variant;
+        int xprec;
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;

@@ -50,3 +50,31 @@ def test_graph_replays_match_eager(rprec, nf, use_stream):
             assert np.array_equal(fa[k], fb[k]), f"{k} differs at replay {rep}"
     mk.mk_destroy(eager)
     mk.mk_destroy(graph)
+
+
+def test_graph_cache_follows_focal_state():
+    """Replays across focal sets that change the batch width, the mute margin
+    and the bands (each needs its own executable) equal the eager passes."""
+    mk = require_gpu()
+    say("graph cache across focal states")
+    p = small_problem(seed=62, n=40, nt=128, nf=6, niter=8)
+    eager = mk.mk_plan(40, 40, 128, p.geom.dt, p.geom.dx, nf_max=6)
+    graph = mk.mk_plan(40, 40, 128, p.geom.dt, p.geom.dx, nf_max=6, flags=mk.MK_FLAG_GRAPH)
+    for pl in (eager, graph):
+        mk.mk_load_R(pl, p.Rhat)
+    band = np.array([[0, 40], [3, 64], [0, 64], [5, 30], [0, 50], [2, 64]], np.int32)
+    states = [(6, p.shift, None), (4, p.shift, None), (6, p.shift + 3, None), (6, p.shift, band),
+              (4, p.shift, None), (6, p.shift, None)]
+    for nf, shift, bd in states:
+        res = []
+        for pl in (eager, graph):
+            mk.mk_set_focal(pl, p.Gd[:nf], p.itd[:nf], shift, None if bd is None else bd[:nf])
+            n1 = mk.mk_iterate(pl, 3)
+            n2 = mk.mk_iterate(pl, 4)
+            res.append((np.concatenate([n1, n2]), _fields(mk, pl, (nf,) + p.Gd.shape[1:])))
+        (na, fa), (nb, fb) = res
+        assert np.array_equal(na, nb), (nf, shift, bd is not None)
+        for k in FIELD_NAMES:
+            assert np.array_equal(fa[k], fb[k]), (k, nf, shift, bd is not None)
+    mk.mk_destroy(eager)
+    mk.mk_destroy(graph)
