@@ -27,6 +27,7 @@
 // focal count (uneven per-focal bands, focal points sorted by band end)
 // ends before a tile skip it.
 #include <type_traits>
+#include <utility>
 
 #include "mk_internal.h"
 
@@ -235,8 +236,10 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
 // and each wave keeps two chunks of R in flight.  Three LDS buffers and three
 // register sets rotate with the chunk index; the chunk loop is unrolled by
 // three so that they rotate by name: no load is conditional or copied while
-// in flight, which keeps the compiler's wait counts exact.  Rows are whole
-// chunks: ns_pad is a multiple of 32 shots.
+// in flight, which keeps the compiler's wait counts exact.  The 128-row tiles
+// (one wave per SIMD, where a barrier costs most) close only every other
+// chunk, with four LDS buffers.  Rows are whole chunks: ns_pad is a multiple
+// of 32 shots.
 //
 // X is stored into LDS in both forms of the real embedding, (Re, -Im) and
 // (Im, Re), so a lane reads its A fragment ready to use; the 16 lanes of a
@@ -253,6 +256,12 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
 // columns and rows are independent), so no masking or branching is needed
 // and every address stays inside the buffers.
 constexpr int kChunkBytes = 128;    // bytes of every row per chunk
+
+// f(integral_constant<int, J>) for every J of the sequence, in order
+template <int... J, typename F>
+__device__ __forceinline__ void for_each_index(std::integer_sequence<int, J...>, F&& f) {
+    (f(std::integral_constant<int, J>{}), ...);
+}
 constexpr int kLdsRcv = 256;        // receivers per block
 
 // both embedding forms of a 16-byte X vector: form 0 (Re, -Im), form 1 (Im, Re)
@@ -287,7 +296,10 @@ __global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
     constexpr int NVEC = ROWS * VPR;              // staging vectors per chunk
     constexpr int NV = (NVEC + 255) / 256;        // per thread
     static_assert(NVEC % 256 == 0 || NVEC < 256, "staging vectors fill whole sweeps");
-    __shared__ __attribute__((aligned(16))) unsigned char lds[3 * BUFB];
+    // RA = 8 (one wave per SIMD) puts a barrier after every other chunk, which
+    // takes four LDS buffers; the others close every chunk with one (three)
+    constexpr bool PAIRED = RA >= 8;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[(PAIRED ? 4 : 3) * BUFB];
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -414,37 +426,79 @@ __global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
     auto run = [&](auto act_tag) {
         constexpr bool ACT = decltype(act_tag)::value;
         v4u rb[3][2][4];
-        v4u xs[3][NV];
-        auto chunk = [&](int c, auto q_tag) {
-            constexpr int Q = decltype(q_tag)::value;      // c % 3
-            constexpr int Q1 = (Q + 1) % 3, Q2 = (Q + 2) % 3;
-            const int c2 = min(c + 2, nch - 1);           // past the end: reload the last chunk (unused)
-            stage_load(c2, xs[Q2]);
-            if constexpr (ACT) load_chunk(c2, rb[Q2]);
-            __builtin_amdgcn_sched_barrier(0);            // keep the loads ahead of the K steps
+        if constexpr (!PAIRED) {
+            v4u xs[3][NV];
+            auto chunk = [&](int c, auto q_tag) {
+                constexpr int Q = decltype(q_tag)::value;      // c % 3
+                constexpr int Q1 = (Q + 1) % 3, Q2 = (Q + 2) % 3;
+                const int c2 = min(c + 2, nch - 1);           // past the end: reload the last chunk (unused)
+                stage_load(c2, xs[Q2]);
+                if constexpr (ACT) load_chunk(c2, rb[Q2]);
+                __builtin_amdgcn_sched_barrier(0);            // keep the loads ahead of the K steps
+                if constexpr (ACT) {
+                    kstep(Q, lane_off, rb[Q][0]);
+                    kstep(Q, lane_off + 16, rb[Q][1]);
+                }
+                stage_store(Q1, xs[Q1]);
+                lds_barrier();
+            };
+            stage_load(0, xs[0]);
+            stage_store(0, xs[0]);
+            stage_load(min(1, nch - 1), xs[1]);
             if constexpr (ACT) {
-                kstep(Q, lane_off, rb[Q][0]);
-                kstep(Q, lane_off + 16, rb[Q][1]);
+                load_chunk(0, rb[0]);
+                load_chunk(min(1, nch - 1), rb[1]);
             }
-            stage_store(Q1, xs[Q1]);
             lds_barrier();
-        };
-        stage_load(0, xs[0]);
-        stage_store(0, xs[0]);
-        stage_load(min(1, nch - 1), xs[1]);
-        if constexpr (ACT) {
-            load_chunk(0, rb[0]);
-            load_chunk(min(1, nch - 1), rb[1]);
+            int c = 0;
+            for (; c + 3 <= nch; c += 3) {
+                chunk(c, std::integral_constant<int, 0>{});
+                chunk(c + 1, std::integral_constant<int, 1>{});
+                chunk(c + 2, std::integral_constant<int, 2>{});
+            }
+            if (c < nch) chunk(c, std::integral_constant<int, 0>{});
+            if (c + 1 < nch) chunk(c + 1, std::integral_constant<int, 1>{});
+        } else {
+            // chunk j: X(j + 3) -> registers, R(j + 2) -> registers, the K
+            // steps of chunk j (LDS buffer j % 4, R registers j % 3), X(j + 2)
+            // -> buffer (j + 2) % 4; a barrier after odd chunks only.  Buffer
+            // (j + 2) % 4 was last read in chunk j - 2, and every wave has
+            // passed the barrier after chunk j - 2 or j - 1 (whichever is odd)
+            // before any wave writes it; the barrier after chunk 2i + 1
+            // publishes X(2i + 2) and X(2i + 3).  J = j mod 12 names every
+            // ring slot at compile time.
+            v4u xs[4][NV];
+            auto chunk = [&](int j, auto jt) {
+                constexpr int J = decltype(jt)::value;
+                const int cx = min(j + 3, nch - 1), cr = min(j + 2, nch - 1);   // past the end: unused
+                stage_load(cx, xs[(J + 3) % 4]);
+                if constexpr (ACT) load_chunk(cr, rb[(J + 2) % 3]);
+                __builtin_amdgcn_sched_barrier(0);            // keep the loads ahead of the K steps
+                if constexpr (ACT) {
+                    kstep(J % 4, lane_off, rb[J % 3][0]);
+                    kstep(J % 4, lane_off + 16, rb[J % 3][1]);
+                }
+                stage_store((J + 2) % 4, xs[(J + 2) % 4]);
+                if constexpr ((J & 1) != 0) lds_barrier();
+            };
+            stage_load(0, xs[0]);
+            stage_store(0, xs[0]);
+            stage_load(min(1, nch - 1), xs[1]);
+            stage_store(1, xs[1]);
+            stage_load(min(2, nch - 1), xs[2]);
+            if constexpr (ACT) {
+                load_chunk(0, rb[0]);
+                load_chunk(min(1, nch - 1), rb[1]);
+            }
+            lds_barrier();
+            int c = 0;
+            for (; c + 12 <= nch; c += 12)
+                for_each_index(std::make_integer_sequence<int, 12>{},
+                               [&](auto jt) { chunk(c + decltype(jt)::value, jt); });
+            for_each_index(std::make_integer_sequence<int, 11>{}, [&](auto jt) {
+                if (c + decltype(jt)::value < nch) chunk(c + decltype(jt)::value, jt);
+            });
         }
-        lds_barrier();
-        int c = 0;
-        for (; c + 3 <= nch; c += 3) {
-            chunk(c, std::integral_constant<int, 0>{});
-            chunk(c + 1, std::integral_constant<int, 1>{});
-            chunk(c + 2, std::integral_constant<int, 2>{});
-        }
-        if (c < nch) chunk(c, std::integral_constant<int, 0>{});
-        if (c + 1 < nch) chunk(c + 1, std::integral_constant<int, 1>{});
     };
     if (r0 < nr) run(std::true_type{});
     else run(std::false_type{});

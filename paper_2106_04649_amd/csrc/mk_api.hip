@@ -140,11 +140,10 @@ int xprec_of(int rprec, int variant, bool fast_x = false) {
 int heuristic_variant(mk_plan_t p, int ncols) {
     if (p->r_tiled) {                    // LDS-staged tiles, the only readers of tiled R
         if (ncols <= 16) return 1 + 7;   // 32 focal-real rows x 256 receivers
-        // one 16-bit plane of X leaves room for 128 x 256 tiles: one focal tile
-        // per R tile at up to 64 columns (453 against 473 us at 601^2, 64
-        // columns); wider batches keep two waves per SIMD (9.9 against 10.3 ms
-        // at 2001^2, 256 columns)
-        if (ncols >= 48 && ncols <= 64 && p->d.rprec != MK_R_C64 && (p->d.flags & MK_FLAG_FAST_X)) return 1 + 5;
+        // one 16-bit plane of X leaves room for 128 x 256 tiles (barrier after
+        // every other chunk): 451 against 475 us at 601^2 and 64 columns, 9.36
+        // against 9.76 ms at 2001^2 and 256 columns
+        if (ncols >= 48 && p->d.rprec != MK_R_C64 && (p->d.flags & MK_FLAG_FAST_X)) return 1 + 5;
         return 1 + 6;                    // 64 x 256
     }
     if (ncols <= kGemvMaxCols) return 0;
