@@ -86,6 +86,91 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ x, c
     }
 }
 
+// The same convolution for the network's dilations (1, 4, 16): 256 samples
+// x (4 * OPT) outputs per block, four consecutive samples per thread, so that
+// one tap of one channel is one aligned 16-byte LDS read for the thread's
+// four samples (dilation 1: two reads cover all five taps) and every weight
+// feeds four products.  The order of the sum (channel, then tap) is the one
+// k_conv_fwd uses: both give the same bits.
+template <int OPT, int D>
+__global__ __launch_bounds__(256) void k_conv_fwd_q(const float* __restrict__ x, const float* __restrict__ W,
+                                                    const float* __restrict__ b, float* __restrict__ y, int C,
+                                                    int O, int T, int relu) {
+    constexpr int HALO = D * kHalf;               // 2, 8, 32: rows stay 16-byte aligned
+    constexpr int WR = 256 + 2 * HALO;            // floats per staged channel
+    constexpr int NXV = D == 1 ? 8 : 4 * kTaps;
+    extern __shared__ float4 xs4[];               // [C][WR]
+    float* xs = reinterpret_cast<float*>(xs4);
+    const int n = blockIdx.x;
+    const int t0 = blockIdx.y * 256;
+    const int og = __builtin_amdgcn_readfirstlane(blockIdx.z * 4 + (threadIdx.x >> 6));
+    const int q = threadIdx.x & 63;
+    const float* xn = x + (size_t)n * C * T;
+    for (int i = threadIdx.x; i < C * WR; i += 256) {
+        const int c = i / WR, u = i - c * WR;
+        const int t = t0 - HALO + u;
+        xs[i] = (t >= 0 && t < T) ? xn[(size_t)c * T + t] : 0.f;
+    }
+    __syncthreads();
+    const int o0 = og * OPT;
+    if (o0 >= O) return;
+    float acc[OPT][4];
+#pragma unroll
+    for (int i = 0; i < OPT; ++i) {
+        const float bi = (o0 + i < O && b) ? b[o0 + i] : 0.f;
+#pragma unroll
+        for (int sm = 0; sm < 4; ++sm) acc[i][sm] = bi;
+    }
+    const int nout = min(OPT, O - o0);            // uniform
+    for (int c = 0; c < C; ++c) {
+        // sample t0 + 4q + sm, tap j reads staged x at 4q + sm + D j
+        const float* xr = xs + c * WR + 4 * q;
+        float xv[NXV];
+        if constexpr (D == 1) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float4 v = *reinterpret_cast<const float4*>(xr + 4 * h);
+                xv[4 * h] = v.x, xv[4 * h + 1] = v.y, xv[4 * h + 2] = v.z, xv[4 * h + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kTaps; ++j) {
+                const float4 v = *reinterpret_cast<const float4*>(xr + D * j);
+                xv[4 * j] = v.x, xv[4 * j + 1] = v.y, xv[4 * j + 2] = v.z, xv[4 * j + 3] = v.w;
+            }
+        }
+        auto xat = [&](int sm, int j) { return D == 1 ? xv[sm + j] : xv[4 * j + sm]; };
+#pragma unroll
+        for (int i = 0; i < OPT; ++i) {
+            if (nout == OPT || i < nout) {
+                const float* w5 = W + ((size_t)(o0 + i) * C + c) * kTaps;
+#pragma unroll
+                for (int j = 0; j < kTaps; ++j) {
+                    const float wj = w5[j];
+#pragma unroll
+                    for (int sm = 0; sm < 4; ++sm) acc[i][sm] = fmaf(wj, xat(sm, j), acc[i][sm]);
+                }
+            }
+        }
+    }
+    const int t = t0 + 4 * q;
+#pragma unroll
+    for (int i = 0; i < OPT; ++i) {
+        if (o0 + i >= O) continue;
+        float v[4];
+#pragma unroll
+        for (int sm = 0; sm < 4; ++sm) v[sm] = relu ? fmaxf(acc[i][sm], 0.f) : acc[i][sm];
+        float* yr = y + ((size_t)n * O + o0 + i) * T;
+        if ((T & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0 && t + 3 < T) {
+            *reinterpret_cast<float4*>(yr + t) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+#pragma unroll
+            for (int sm = 0; sm < 4; ++sm)
+                if (t + sm < T) yr[t + sm] = v[sm];
+        }
+    }
+}
+
 // Wt[c][o][j'] = W[o][c][K-1-j']: the input gradient is a forward conv of
 // the output gradient with these weights.
 __global__ void k_flip_weights(const float* __restrict__ W, float* __restrict__ Wt, int O, int C) {
@@ -203,8 +288,33 @@ __global__ void k_round_bf16(const float* __restrict__ w, float* __restrict__ wq
     if (i < n) wq[i] = round_bf16(w[i]);
 }
 
+template <int D>
+hipError_t conv_fwd_q(const float* x, const float* W, const float* b, float* y, int N, int C, int O, int T,
+                      int relu, size_t lds, hipStream_t s) {
+    const int gt = (T + 255) / 256;
+    if (O >= 64) {
+        hipLaunchKernelGGL((k_conv_fwd_q<16, D>), dim3(N, gt, (O + 63) / 64), dim3(256), lds, s, x, W, b, y, C, O,
+                           T, relu);
+    } else if (O >= 16) {
+        hipLaunchKernelGGL((k_conv_fwd_q<4, D>), dim3(N, gt, (O + 15) / 16), dim3(256), lds, s, x, W, b, y, C, O,
+                           T, relu);
+    } else {
+        hipLaunchKernelGGL((k_conv_fwd_q<1, D>), dim3(N, gt, (O + 3) / 4), dim3(256), lds, s, x, W, b, y, C, O, T,
+                           relu);
+    }
+    return hipGetLastError();
+}
+
 hipError_t conv_fwd(const float* x, const float* W, const float* b, float* y, int N, int C, int O, int T,
                     int d, int relu, hipStream_t s) {
+    if (d == 1 || d == 4 || d == 16) {
+        const size_t lq = (size_t)C * (256 + 2 * d * kHalf) * sizeof(float);
+        if (lq <= 65536) {
+            if (d == 1) return conv_fwd_q<1>(x, W, b, y, N, C, O, T, relu, lq, s);
+            if (d == 4) return conv_fwd_q<4>(x, W, b, y, N, C, O, T, relu, lq, s);
+            return conv_fwd_q<16>(x, W, b, y, N, C, O, T, relu, lq, s);
+        }
+    }
     const int halo = d * kHalf;
     const size_t lds = (size_t)C * (64 + 2 * halo) * sizeof(float);
     if (lds > 65536) return hipErrorInvalidValue;
@@ -219,6 +329,166 @@ hipError_t conv_fwd(const float* x, const float* W, const float* b, float* y, in
         hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), lds, s, x, W, b, y, C, O, T, d, relu);
     }
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The whole network on one 256-sample tile of one trace (hidden width 16),
+// with the tail it predicts added to f1+ and f1- on the spot.  Each layer's
+// output stays in LDS over the span the next layer reads,
+//
+//   y on [t0, t0 + 256), a2 on [t0 - 32, t0 + 288), a1 on [t0 - 40, t0 + 296),
+//   x on [t0 - 42, t0 + 298),
+//
+// zero outside [0, T) exactly as the layer-by-layer form pads each input.
+// Layers 1 and 2 are products of a 16 x 5C weight block with a 5C x 16
+// shifted-sample block: they run on the FP32 matrix cores
+// (v_mfma_f32_16x16x4_f32, 16 outputs x 16 samples x 4 (channel, tap) pairs
+// per instruction; in step s the four lane groups g feed tap s / Q of
+// channels s % Q + Q g, so a group's LDS row differs from the next by a fixed
+// stride).  Layer 3 (two outputs) runs on the vector ALUs.  A tile that shares
+// no sample with the trace's mute window is skipped: the tail is only used
+// inside the window, and two tiles never touch the same sample of f1.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kFH = 16;                        // hidden width of this form
+constexpr int kFT = 256;                       // output samples per block
+constexpr int kX0 = 42, kA10 = 40, kA20 = 32;  // reach of x, a1, a2 left of t0
+constexpr int kXN = kFT + 2 * kX0;             // 340 staged input samples
+constexpr int kA1N = kFT + 2 * kA10;           // 336 = 21 tiles of 16
+constexpr int kA2N = kFT + 2 * kA20;           // 320 = 20 tiles of 16
+// row strides: a group's rows sit 16 banks apart (64 x 4-byte banks) for
+// the matrix-core operand reads and the accumulator stores
+constexpr int kXW = 400, kA1W = 340, kA2W = 324;
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, const float* __restrict__ hist,
+                                                  const float* __restrict__ scale, const int32_t* __restrict__ itd,
+                                                  int shift, int k, int T, int nt, float* __restrict__ f1p,
+                                                  float* __restrict__ f1m) {
+    constexpr int KP = 4 * Q;                  // input channels padded to a multiple of 4
+    constexpr int U2 = KP * kXW > kFH * kA2W ? KP * kXW : kFH * kA2W;
+    __shared__ float a1s[kFH * kA1W];
+    __shared__ float u2[U2];                   // x, then a2
+    const int tr = blockIdx.x;
+    const int t0 = blockIdx.y * kFT;
+    const int hT = T >> 1;
+    const int L = itd[tr] - shift;
+    // window samples u = t + T/2 with |t| < L
+    if (L <= 0 || t0 >= hT + L || t0 + kFT <= hT - L + 1) return;
+    const float se = scale[tr];
+    const float inv = se > 0.f ? 1.f / se : 0.f;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i16 = lane & 15, g = lane >> 4;
+    const float* W1 = P;
+    const float* B1 = W1 + kFH * k * kTaps;
+    const float* W2 = B1 + kFH;
+    const float* B2 = W2 + kFH * kFH * kTaps;
+    const float* W3 = B2 + kFH;
+    const float* B3 = W3 + 2 * kFH * kTaps;
+
+    // weights in the A-operand layout: lane (i16, g) holds output i16's
+    // weight for the (channel, tap) pair its group feeds in each step
+    float w1[5 * Q], w2[20];
+#pragma unroll
+    for (int s = 0; s < 5 * Q; ++s) {
+        const int c = s % Q + Q * g;
+        w1[s] = c < k ? W1[(i16 * k + c) * kTaps + s / Q] : 0.f;
+    }
+#pragma unroll
+    for (int s = 0; s < 20; ++s) w2[s] = W2[(i16 * kFH + s % 4 + 4 * g) * kTaps + s / 4];
+    v4f bias1, bias2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias1[r] = B1[4 * g + r], bias2[r] = B2[4 * g + r];
+
+    float* xs = u2;
+    const float* h = hist + (size_t)tr * k * T;
+    for (int i = threadIdx.x; i < KP * kXN; i += 256) {
+        const int c = i / kXN, u = i - c * kXN;
+        const int t = t0 - kX0 + u;
+        xs[c * kXW + u] = (c < k && t >= 0 && t < T) ? h[(size_t)c * T + t] * inv : 0.f;
+    }
+    __syncthreads();
+
+    // layer 1: a1 = relu(conv(x)), tiles wv, wv + 4, ... of 21
+    {
+        const float* xb = xs + Q * g * kXW + i16;
+        auto tile = [&](int nb) {
+            v4f acc = bias1;
+#pragma unroll
+            for (int s = 0; s < 5 * Q; ++s)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w1[s], xb[(s % Q) * kXW + nb + s / Q], acc, 0, 0, 0);
+            const int t = t0 - kA10 + nb + i16;
+            const bool ok = t >= 0 && t < T;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a1s[(4 * g + r) * kA1W + nb + i16] = ok ? fmaxf(acc[r], 0.f) : 0.f;
+        };
+        v4f acc[5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) acc[m] = bias1;
+#pragma unroll
+        for (int s = 0; s < 5 * Q; ++s)
+#pragma unroll
+            for (int m = 0; m < 5; ++m)
+                acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    w1[s], xb[(s % Q) * kXW + 16 * (wv + 4 * m) + s / Q], acc[m], 0, 0, 0);
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            const int nb = 16 * (wv + 4 * m);
+            const int t = t0 - kA10 + nb + i16;
+            const bool ok = t >= 0 && t < T;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a1s[(4 * g + r) * kA1W + nb + i16] = ok ? fmaxf(acc[m][r], 0.f) : 0.f;
+        }
+        if (wv == 0) tile(16 * 20);
+    }
+    __syncthreads();
+
+    // layer 2: a2 = relu(conv(a1)), 20 tiles, five per wave (x is dead: a2 takes its place)
+    float* a2s = u2;
+    {
+        const float* ab = a1s + 4 * g * kA1W + i16;
+        v4f acc[5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) acc[m] = bias2;
+#pragma unroll
+        for (int s = 0; s < 20; ++s)
+#pragma unroll
+            for (int m = 0; m < 5; ++m)
+                acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    w2[s], ab[(s % 4) * kA1W + 16 * (wv + 4 * m) + 4 * (s / 4)], acc[m], 0, 0, 0);
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            const int nb = 16 * (wv + 4 * m);
+            const int t = t0 - kA20 + nb + i16;
+            const bool ok = t >= 0 && t < T;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a2s[(4 * g + r) * kA2W + nb + i16] = ok ? fmaxf(acc[m][r], 0.f) : 0.f;
+        }
+    }
+    __syncthreads();
+
+    // layer 3 (channel, then tap, as the layer-by-layer kernels sum) and the
+    // tail: f1+ += s y_odd, f1- -= s y_even(-t) inside the window
+    const int sidx = threadIdx.x;
+    const int u = t0 + sidx;
+    float ye = B3[0], yo = B3[1];
+    for (int c = 0; c < kFH; ++c) {
+        const float* ar = a2s + c * kA2W + sidx;
+#pragma unroll
+        for (int j = 0; j < kTaps; ++j) {
+            const float a = ar[16 * j];
+            ye = fmaf(W3[c * kTaps + j], a, ye);
+            yo = fmaf(W3[(kFH + c) * kTaps + j], a, yo);
+        }
+    }
+    const int t = u - hT;
+    if (u < T && t < L && -t < L && t != nt / 2 && -t != nt / 2) {
+        const int ip = ((t % nt) + nt) % nt, im = ((-t % nt) + nt) % nt;
+        float* fp = f1p + (size_t)tr * nt;
+        float* fm = f1m + (size_t)tr * nt;
+        fp[ip] = fp[ip] + se * yo;
+        fm[im] = fm[im] - se * ye;
+    }
 }
 
 }  // namespace
@@ -247,6 +517,22 @@ hipError_t net_forward(const float* P, const float* x, int N, int k, int H, int 
     if (e == hipSuccess) e = conv_fwd(a1, P + o[2], P + o[3], a2, N, H, H, T, kNetDil[1], 1, s);
     if (e == hipSuccess) e = conv_fwd(a2, P + o[4], P + o[5], y, N, H, 2, T, kNetDil[2], 0, s);
     return e;
+}
+
+bool net_tail_fused(int k, int H) { return H == kFH && k >= 1 && k <= 16; }
+
+hipError_t net_tail_apply(const float* P, const float* hist, const float* scale, const int32_t* itd, int shift,
+                          int ntr, int k, int H, int T, int nt, float* f1p, float* f1m, hipStream_t s) {
+    if (!net_tail_fused(k, H)) return hipErrorInvalidValue;
+    if (ntr <= 0 || T <= 0) return hipSuccess;
+    const dim3 grid(ntr, (T + kFT - 1) / kFT);
+    switch ((k + 3) / 4) {
+        case 1: hipLaunchKernelGGL(k_net_tail<1>, grid, dim3(256), 0, s, P, hist, scale, itd, shift, k, T, nt, f1p, f1m); break;
+        case 2: hipLaunchKernelGGL(k_net_tail<2>, grid, dim3(256), 0, s, P, hist, scale, itd, shift, k, T, nt, f1p, f1m); break;
+        case 3: hipLaunchKernelGGL(k_net_tail<3>, grid, dim3(256), 0, s, P, hist, scale, itd, shift, k, T, nt, f1p, f1m); break;
+        default: hipLaunchKernelGGL(k_net_tail<4>, grid, dim3(256), 0, s, P, hist, scale, itd, shift, k, T, nt, f1p, f1m); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t net_backward(const float* P, const float* x, const float* a1, const float* a2, const float* gy,

@@ -16,7 +16,8 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 }
 
 // x[tr][c][u] = hist[tr][c][u] / s_tr with s_tr the RMS of the first iterate
-// over the window (0 for a silent trace, which the network then skips).
+// over the window (0 for a silent trace, which the network then skips); with
+// x NULL only s_tr is written (the fused network scales as it stages).
 __global__ __launch_bounds__(256) void k_tail_prep(const float* __restrict__ hist, int ntr, int k, int T,
                                                    float* __restrict__ x, float* __restrict__ scale) {
     const int lane = threadIdx.x & 63;
@@ -28,8 +29,10 @@ __global__ __launch_bounds__(256) void k_tail_prep(const float* __restrict__ his
     ss = wave_sum_f(ss);
     const float s = sqrtf(ss / (float)T);
     const float inv = s > 1e-30f ? 1.f / s : 0.f;
-    float* xo = x + (size_t)tr * k * T;
-    for (int i = lane; i < k * T; i += 64) xo[i] = h[i] * inv;
+    if (x) {
+        float* xo = x + (size_t)tr * k * T;
+        for (int i = lane; i < k * T; i += 64) xo[i] = h[i] * inv;
+    }
     if (lane == 0) scale[tr] = inv > 0.f ? s : 0.f;
 }
 

@@ -866,26 +866,25 @@ mk_status mk_tail_load(mk_plan_t p, const float* params, int32_t count) {
     HIP_TRY(p, hipMemcpyAsync(p->tail_w, params, count * sizeof(float), hipMemcpyHostToDevice, p->stream));
     HIP_TRY(p, net_round_bf16(p->tail_w, p->tail_w, count, p->stream));
     p->tail_nw = count;
-    if (p->tail_work && p->tail_hidden < H) {       // activations sized for a narrower network
-        HIP_TRY(p, hipFree(p->tail_work));
-        p->tail_work = nullptr;
-    }
-    if (!p->tail_work) {
-        const int ntr = p->d.nf_max * p->d.nr;
+    const int ntr = p->d.nf_max * p->d.nr;
+    if (!net_tail_fused(p->hist_k, H)) {            // layer by layer: activations in HBM, in chunks
+        if (p->tail_work && p->tail_hidden < H) {   // activations sized for a narrower network
+            HIP_TRY(p, hipFree(p->tail_work));
+            p->tail_work = nullptr;
+        }
         p->tail_chunk = std::min(ntr, 4096);
-        HIP_TRY(p, dalloc(&p->tail_work, 2 * (size_t)p->tail_chunk * H * p->hist_T));
-        p->tail_hidden = H;
+        if (!p->tail_work) {
+            HIP_TRY(p, dalloc(&p->tail_work, 2 * (size_t)p->tail_chunk * H * p->hist_T));
+            p->tail_hidden = H;
+        }
+        if (!p->tail_x) {
+            const size_t c = (size_t)p->tail_chunk, T = (size_t)p->hist_T;
+            HIP_TRY(p, dalloc(&p->tail_x, c * 16 * T));             // room for k <= 16
+            HIP_TRY(p, dalloc(&p->tail_y, c * 2 * T));
+        }
     }
     p->tail_net_hidden = H;
-    if (!p->tail_x) {
-        const int ntr = p->d.nf_max * p->d.nr;
-        p->tail_chunk = std::min(ntr, 4096);
-        const size_t c = (size_t)p->tail_chunk, T = (size_t)p->hist_T, k = (size_t)p->hist_k;
-        HIP_TRY(p, dalloc(&p->tail_x, c * 16 * T));                 // room for k <= 16
-        HIP_TRY(p, dalloc(&p->tail_y, c * 2 * T));
-        HIP_TRY(p, dalloc(&p->tail_scale, (size_t)ntr));
-        (void)k;
-    }
+    if (!p->tail_scale) HIP_TRY(p, dalloc(&p->tail_scale, (size_t)ntr));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
     return MK_OK;
 }
@@ -920,7 +919,11 @@ mk_status mk_tail_apply(mk_plan_t p, int32_t mode, double* rel_resid) {
         return fail(p, MK_ERR_ARG, "mk_tail_apply: geometric extrapolation needs an even k >= 4");
     const int nr = p->d.nr, nt = p->d.nt, k = p->hist_k, T = p->hist_T;
     const int ntr = p->nf * nr;
-    if (mode == 0) {
+    if (mode == 0 && net_tail_fused(k, p->tail_net_hidden)) {
+        HIP_TRY(p, launch_tail_prep(p->hist, ntr, k, T, nullptr, p->tail_scale, p->stream));
+        HIP_TRY(p, net_tail_apply(p->tail_w, p->hist, p->tail_scale, p->itd, p->shift, ntr, k,
+                                  p->tail_net_hidden, T, nt, p->f1p, p->f1m, p->stream));
+    } else if (mode == 0) {
         const int H = p->tail_net_hidden;
         const size_t act = (size_t)p->tail_chunk * H * T;
         for (int c0 = 0; c0 < ntr; c0 += p->tail_chunk) {

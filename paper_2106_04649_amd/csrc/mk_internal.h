@@ -114,9 +114,9 @@ struct mk_plan_s {
     int hist_k = 0, hist_T = 0;
     float* tail_w = nullptr;   // BF16-rounded parameters
     int tail_nw = 0;
-    float* tail_x = nullptr;   // [chunk][k][T] normalised input
-    float* tail_work = nullptr;   // [2][chunk][hidden][T]
-    float* tail_y = nullptr;   // [chunk][2][T]
+    float* tail_x = nullptr;   // [chunk][k][T] normalised input (layer-by-layer form only)
+    float* tail_work = nullptr;   // [2][chunk][hidden][T] (layer-by-layer form only)
+    float* tail_y = nullptr;   // [chunk][2][T] (layer-by-layer form only)
     float* tail_scale = nullptr;  // [nf_max][nr]
     int tail_chunk = 0;
     int pass_base = 0;         // passes before the current series (a restart starts a new one)
@@ -217,6 +217,7 @@ hipError_t launch_repack_tiled(int prec, const float* Rin, void* Rout, const flo
 size_t tiled_R_bytes(int prec, int nr, int B, int ns_pad);
 bool contract_variant_reads_tiled(int variant);
 hipError_t launch_check_finite(const float* x, int64_t n, int* flag, hipStream_t s);
+// x may be NULL: then only the per-trace scales are written
 hipError_t launch_tail_prep(const float* hist, int ntr, int k, int T, float* x, float* scale, hipStream_t s);
 hipError_t launch_tail_apply(const float* hist, const float* y, const float* scale, const int32_t* itd, int shift,
                              int ntr, int k, int T, int nt, int mode, float* f1p, float* f1m, hipStream_t s);
@@ -227,6 +228,11 @@ constexpr int kNetDil[3] = {1, 4, 16};
 int net_param_count(int k, int H);
 hipError_t net_forward(const float* P, const float* x, int N, int k, int H, int T, float* a1, float* a2,
                        float* y, hipStream_t s);
+// the whole network plus the tail's application in one kernel per 256-sample
+// tile (hidden width 16, k <= 16); other widths go layer by layer
+bool net_tail_fused(int k, int H);
+hipError_t net_tail_apply(const float* P, const float* hist, const float* scale, const int32_t* itd, int shift,
+                          int ntr, int k, int H, int T, int nt, float* f1p, float* f1m, hipStream_t s);
 hipError_t net_backward(const float* P, const float* x, const float* a1, const float* a2, const float* gy,
                         int N, int k, int H, int T, float* G, float* g1, float* g2, float* wt, hipStream_t s);
 hipError_t net_mse(const float* y, const float* tgt, const float* mask, int N, int T, float* gy,

@@ -15,18 +15,18 @@ pytestmark = pytest.mark.gpu
 K, T = 4, 64
 
 
-def _gpu(p, mode, m, params=None, tune=None, rprec=0):
+def _gpu(p, mode, m, params=None, tune=None, rprec=0, k=K, T=T):
     mk = require_gpu()
     nr, nt = p.Rhat.shape[0], p.geom.nt
     plan = mk.mk_plan(nr, nr, nt, p.geom.dt, p.geom.dx, band=p.band, nf_max=p.nf, rprec=rprec)
     mk.mk_load_R(plan, p.Rhat)
     if tune is not None:
         mk.mk_tune(plan, tune)
-    mk.mk_tail_record(plan, K, T)
+    mk.mk_tail_record(plan, k, T)
     if params is not None:
         mk.mk_tail_load(plan, params)
     mk.mk_set_focal(plan, p.Gd, p.itd, p.shift)
-    mk.mk_iterate(plan, K)
+    mk.mk_iterate(plan, k)
     hist = mk.mk_tail_history(plan)
     res = mk.mk_tail_apply(plan, mode)
     norms = mk.mk_iterate(plan, m) if m else None
@@ -36,10 +36,10 @@ def _gpu(p, mode, m, params=None, tune=None, rprec=0):
     return out
 
 
-def _ref(p, mode, m, P=None):
+def _ref(p, mode, m, P=None, k=K, T=T):
     S = SynthesisOperator(p.Rhat, p.band, p.c, p.geom.nt)
-    a = marchenko(S, p.Gd, p.itd, p.shift, K, keep_iterates=True)
-    hist = ot.history(a["iterates"], K, T)
+    a = marchenko(S, p.Gd, p.itd, p.shift, k, keep_iterates=True)
+    hist = ot.history(a["iterates"], k, T)
     f1p, f1m = a["f1plus"], a["f1minus"]
     if mode == 1:
         te, to = ot.geometric_tails(hist)
@@ -87,11 +87,9 @@ def test_no_tail_restart_equals_plain_passes():
     np.testing.assert_allclose(g["norms"], plain["norms"][K + 2:], rtol=1e-3)
 
 
-@pytest.mark.parametrize("tune,hidden", [(None, 64), (1, 64), (None, 12)])
-def test_network_tail_matches_reference(tune, hidden):
-    say(f"network tail, contraction {tune}, hidden {hidden}")
-    rng = np.random.default_rng(5)
-    P = tn.init_params(rng, k=K, hidden=hidden)
+def _bf16_net(rng, k, hidden):
+    """Random network weights (FP32 vector) and their BF16-rounded FP64 copy."""
+    P = tn.init_params(rng, k=k, hidden=hidden)
     P["W3"] *= 5.0
     P["b3"] = 0.01 * rng.standard_normal(2)
     flat = np.concatenate([P["W1"].ravel(), P["b1"], P["W2"].ravel(), P["b2"], P["W3"].ravel(), P["b3"]])
@@ -103,9 +101,31 @@ def test_network_tail_matches_reference(tune, hidden):
         n = P[key].size
         Pr[key] = rounded[o:o + n].astype(np.float64).reshape(P[key].shape)
         o += n
+    return flat, Pr
+
+
+@pytest.mark.parametrize("tune,hidden", [(None, 64), (1, 64), (None, 12), (None, 16)])
+def test_network_tail_matches_reference(tune, hidden):
+    """Hidden width 16 takes the one-kernel form (matrix-core layers 1 and 2,
+    the tail applied in the same kernel), the others go layer by layer."""
+    say(f"network tail, contraction {tune}, hidden {hidden}")
+    flat, Pr = _bf16_net(np.random.default_rng(5), K, hidden)
     p = small_problem(seed=73, n=20, nt=128, nf=3, niter=8)
     g = _gpu(p, 0, 2, params=flat, tune=tune)
     _compare(g, _ref(p, 0, 2, Pr), "net", tol=2e-5)
+
+
+@pytest.mark.parametrize("k,T,nt,n,nf", [(6, 128, 128, 20, 3), (13, 32, 256, 16, 2), (4, 600, 2048, 24, 8),
+                                         (8, 1024, 2048, 16, 4)])
+def test_fused_network_tail_shapes(k, T, nt, n, nf):
+    """The one-kernel network tail (hidden 16) over input widths that pad to
+    4, 8, 12 and 16 channels, windows of one to four 256-sample tiles with a
+    ragged last tile, and mute windows that leave some tiles out."""
+    say(f"fused network tail k {k} T {T} nt {nt} n {n} nf {nf}")
+    flat, Pr = _bf16_net(np.random.default_rng(9 + k), k, 16)
+    p = small_problem(seed=80 + k, n=n, nt=nt, nf=nf, niter=k + 4)
+    g = _gpu(p, 0, 2, params=flat, k=k, T=T)
+    _compare(g, _ref(p, 0, 2, Pr, k=k, T=T), f"fused k{k}", tol=2e-5)
 
 
 @pytest.mark.parametrize("mode,nt", [(1, 2048), (2, 2048), (1, 4096)])
