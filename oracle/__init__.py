@@ -14,3 +14,4 @@ from .marchenko import (  # noqa: F401
     signed_time,
     rel_l2,
 )
+from .imaging import double_focused, image  # noqa: F401,E402
