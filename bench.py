@@ -112,10 +112,12 @@ def cpu_baseline(p, passes: int) -> dict:
 def oracle_reference(pb, sample, niter):
     """The FP64 oracle's fields for the sampled focal points of the batch (the
     accuracy reference of the batched and combined paths)."""
-    from oracle import SynthesisOperator, marchenko
+    from oracle import SynthesisOperator, image, marchenko
 
     sub = type(pb)(**{**pb.__dict__, "Gd": pb.Gd[sample], "itd": pb.itd[sample]})
-    return marchenko(SynthesisOperator(pb.Rhat, pb.band, pb.c, pb.geom.nt), sub.Gd, sub.itd, sub.shift, niter)
+    out = marchenko(SynthesisOperator(pb.Rhat, pb.band, pb.c, pb.geom.nt), sub.Gd, sub.itd, sub.shift, niter)
+    out["image"] = image(out["Gminus"], out["f1plus"], pb.c)
+    return out
 
 
 # ---- the GPU paths ------------------------------------------------------------
@@ -195,6 +197,20 @@ class Runner:
             self.mk.mk_get(self.plan, k, self.out_p)
             out[k] = self.out_p[focal_idx].cpu().numpy()
         return out
+
+    def image(self, reps=10):
+        """mk_image on the current fields: the image per focal point and the
+        average time per call from events on the plan's stream (its two
+        kernels and the copy of nf doubles back)."""
+        torch, mk = self.torch, self.mk
+        img = mk.mk_image(self.plan)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        for _ in range(reps):
+            img = mk.mk_image(self.plan)
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        return img, e0.elapsed_time(e1) / reps / 1e3
 
     def destroy(self):
         self.mk.mk_destroy(self.plan)
@@ -522,6 +538,7 @@ def main() -> int:
             w = r.time(args.steps, args.warmup)
             r.norms()
             got = r.fields(sample)
+            img, img_s = r.image()
             r.destroy()
             err = {k: max(rel_l2(got[k][j], ref[k][j]) for j in range(len(sample)))
                    for k in ("f1plus", "f1minus", "Gplus", "Gminus")}
@@ -529,6 +546,15 @@ def main() -> int:
                    "focal_iters_per_s": round(args.niter * args.steps * pb.nf / w, 1),
                    "ms_per_step": round(w * 1e3 / args.steps, 3),
                    "max_rel_l2_vs_oracle": {k: float(f"{v:.3e}") for k, v in err.items()}}
+            # double-focusing image: error against the oracle's, relative to
+            # c ||G-|| ||f1+|| (the bilinear form's bound)
+            ibytes = 2.0 * pb.nf * nr * nt * 4
+            ierr = max(abs(img[s] - ref["image"][j]) / (pb.c * np.linalg.norm(ref["Gminus"][j]) *
+                                                          np.linalg.norm(ref["f1plus"][j]))
+                       for j, s in enumerate(sample))
+            ent["image"] = {"us_per_call": round(img_s * 1e6, 1), "gbs": round(ibytes / img_s / 1e9, 1),
+                            "frac_hbm": round(ibytes / img_s / 1e9 / HBM_PEAK_GBS, 3),
+                            "err_vs_oracle_rel_bound": float(f"{ierr:.3e}")}
             if not args.no_profile:
                 avg_s, times, variant = profile_contract(pb, rprec)
                 flops = 8.0 * nr * nr * B * pb.nf

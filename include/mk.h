@@ -174,6 +174,21 @@ mk_status mk_iterate(mk_plan_t plan, int32_t niter, double* norms);
 mk_status mk_get(mk_plan_t plan, int32_t field, float* out, int on_device);
 
 /*
+ * mk_image -- the double-focusing image of every focal point (Theory
+ * section, imaging paragraph; the last step of Algorithm 1): G- and f1+ of a
+ * focal point convolved in time and integrated over the receivers give
+ * G^{-,+}(x_F, x_F, t), whose zero-time sample is the local reflectivity,
+ *     image[f] = dx * dt * sum_r sum_k G-[f][r][k] * f1+[f][r][(-k) mod nt].
+ * Runs the G assembly first when G- is not current.  Products and sums in
+ * FP64 (each product of two FP32 samples is exact), summed in a fixed order.
+ * image: host array of nf doubles, in the caller's focal order; the caller
+ * owns it.  Synchronises.
+ * Errors: MK_ERR_ARG (null plan or image), MK_ERR_STATE (no focal set),
+ * MK_ERR_HIP.
+ */
+mk_status mk_image(mk_plan_t plan, double* image);
+
+/*
  * mk_tune -- choose how the contraction (the space integral of Eq. (1),
  * segmented dot products of Algorithm 2) runs.  mode -1: built-in
  * heuristic; -2: autotune (time every variant once per column count at its
@@ -209,7 +224,7 @@ mk_status mk_passes(mk_plan_t plan, int32_t* passes);
  * events on the plan's stream when the plan has MK_FLAG_PROFILE.
  * kind: 0 contraction (the space integral of Eq. (1)), 1 per-pass epilogue
  * (inverse FFT, reverse, mute, accumulate, forward FFT), 2 norm reduction,
- * 3 first forward transform, 4 G assembly.  Synchronises.  reset != 0
+ * 3 first forward transform, 4 G assembly, 5 image.  Synchronises.  reset != 0
  * clears the counters after reading.
  * Errors: MK_ERR_ARG, MK_ERR_UNSUPPORTED (plan without MK_FLAG_PROFILE).
  */

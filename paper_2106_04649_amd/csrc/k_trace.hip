@@ -996,6 +996,53 @@ __global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ x, int 
     if (lane == 0) npart[trace] = acc;
 }
 
+// Double-focusing image (Theory section, imaging): the zero-time sample of
+// G- convolved in time with f1+ and integrated over the receivers.  First
+// stage, one wave per trace: sum_k G-[k] f1+[(-k) mod nt] in FP64 (a product
+// of two FP32 values is exact in FP64).  Eight loads of each field in flight
+// per lane; f1+ is read backwards, which still fills whole lines.
+__global__ __launch_bounds__(256) void k_image_part(const float* __restrict__ gm, const float* __restrict__ f1p,
+                                                    int ntr, int nt, double* __restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int trace = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (trace >= ntr) return;
+    const float* g = gm + (size_t)trace * nt;
+    const float* f = f1p + (size_t)trace * nt;
+    constexpr int U = 8;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < nt; k0 += 64 * U) {
+        float gv[U], fv[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int k = min(k0 + lane + 64 * j, nt - 1);
+            gv[j] = g[k];
+            fv[j] = f[k == 0 ? 0 : nt - k];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (k0 + lane + 64 * j < nt) acc = fma((double)gv[j], (double)fv[j], acc);
+    }
+    acc = wave_sum_d(acc);
+    if (lane == 0) part[trace] = acc;
+}
+
+// Second stage: out[f] = scale * sum_r part[f][r], one block per focal point,
+// in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_image_reduce(const double* __restrict__ part, int nr, double scale,
+                                                      double* __restrict__ out) {
+    __shared__ double sh[256];
+    const double* p = part + (size_t)blockIdx.x * nr;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nr; i += 256) acc += p[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = scale * sh[0];
+}
+
 // dst[j] = src[perm[j]] for blocks of `per` elements of type T; block row
 // blockIdx.y is block j.
 template <typename T>
@@ -1081,6 +1128,15 @@ hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out,
 hipError_t launch_sumsq(const float* x, int ntr, int nt, double* npart, hipStream_t s) {
     if (ntr <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sumsq, dim3((ntr + 3) / 4), dim3(256), 0, s, x, ntr, nt, npart);
+    return hipGetLastError();
+}
+
+hipError_t launch_image(const float* gm, const float* f1p, int nf, int nr, int nt, double scale, double* part,
+                        double* out, hipStream_t s) {
+    if (nf <= 0 || nr <= 0) return hipSuccess;
+    const int ntr = nf * nr;
+    hipLaunchKernelGGL(k_image_part, dim3((ntr + 3) / 4), dim3(256), 0, s, gm, f1p, ntr, nt, part);
+    hipLaunchKernelGGL(k_image_reduce, dim3(nf), dim3(256), 0, s, part, nr, scale, out);
     return hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ void free_plan_memory(mk_plan_t p) {
     void* bufs[] = {p->R, p->rscale, p->X, p->Y, p->f1p, p->f1m, p->gp, p->gm, p->stage, p->itd,
                     p->fband, p->perm, p->iperm, p->ncols, p->npart, p->norm0, p->gdnorm, p->nlast, p->xscale,
                     p->norms, p->tw, p->flag, p->n0, p->hist, p->tail_w, p->tail_x, p->tail_work,
-                    p->tail_y, p->tail_scale};
+                    p->tail_y, p->tail_scale, p->img};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& pe : p->pending) {
@@ -454,6 +454,7 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     if ((e = dalloc(&p->norm0, nfm)) != hipSuccess) return bail(e, "norm0");
     if ((e = dalloc(&p->gdnorm, nfm)) != hipSuccess) return bail(e, "gdnorm");
     if ((e = dalloc(&p->nlast, nfm)) != hipSuccess) return bail(e, "nlast");
+    if ((e = dalloc(&p->img, nfm)) != hipSuccess) return bail(e, "image");
     if ((e = dalloc(&p->xscale, 3 * nfm)) != hipSuccess) return bail(e, "X scales");
     if ((e = dalloc(&p->tw, (size_t)d.nt + 256)) != hipSuccess) return bail(e, "twiddles");
     if ((e = dalloc(&p->flag, 1)) != hipSuccess) return bail(e, "flag");
@@ -787,6 +788,23 @@ mk_status mk_get(mk_plan_t p, int32_t field, float* out, int on_device) {
     return MK_OK;
 }
 
+mk_status mk_image(mk_plan_t p, double* image) {
+    if (!p) return fail(nullptr, MK_ERR_ARG, "mk_image: plan is NULL");
+    if (!image) return fail(p, MK_ERR_ARG, "mk_image: image is NULL");
+    if (!p->focal_set) return fail(p, MK_ERR_STATE, "mk_image: no focal points set");
+    if (!p->g_valid) MK_TRY(assemble_G(p));
+    hipEvent_t ev = nullptr;
+    HIP_TRY(p, prof_begin(p, &ev));
+    HIP_TRY(p, launch_image(p->gm, p->f1p, p->nf, p->d.nr, p->d.nt, p->d.dx * p->d.dt, p->npart, p->img,
+                            p->stream));
+    HIP_TRY(p, prof_end(p, ev, 5));
+    std::vector<double> v(p->nf);
+    HIP_TRY(p, hipMemcpyAsync(v.data(), p->img, p->nf * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    for (int j = 0; j < p->nf; ++j) image[p->perm_host[j]] = v[j];
+    return MK_OK;
+}
+
 mk_status mk_passes(mk_plan_t p, int32_t* passes) {
     if (!p || !passes) return fail(p, MK_ERR_ARG, "mk_passes: NULL argument");
     *passes = p->passes;
@@ -969,7 +987,7 @@ mk_status mk_tail_apply(mk_plan_t p, int32_t mode, double* rel_resid) {
 
 mk_status mk_profile(mk_plan_t p, int32_t kind, double* total_ms, int64_t* launches, int reset) {
     if (!p) return fail(nullptr, MK_ERR_ARG, "mk_profile: plan is NULL");
-    if (kind < 0 || kind > 4) return fail(p, MK_ERR_ARG, "mk_profile: unknown kernel kind");
+    if (kind < 0 || kind > 5) return fail(p, MK_ERR_ARG, "mk_profile: unknown kernel kind");
     if (!(p->d.flags & MK_FLAG_PROFILE))
         return fail(p, MK_ERR_UNSUPPORTED, "mk_profile: plan was created without MK_FLAG_PROFILE");
     HIP_TRY(p, prof_resolve(p));

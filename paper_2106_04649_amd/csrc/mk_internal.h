@@ -102,6 +102,7 @@ struct mk_plan_s {
     double* norm0 = nullptr;   // [nf_max] norm the 16-bit X of the series is scaled by (||G_d||, then ||rho||)
     double* gdnorm = nullptr;  // [nf_max] ||G_d||: scale of the 16-bit X of the G assembly (f1 fields)
     double* nlast = nullptr;   // [nf_max] norm of the last N (scales 16-bit X)
+    double* img = nullptr;     // [nf_max] double-focusing image, sorted focal order
     float* xscale = nullptr;   // [3 nf_max] scale stored with 16-bit X
     double* norms = nullptr;   // [norm_cap][nf_max]
     int norm_cap = 0;
@@ -164,7 +165,7 @@ struct mk_plan_s {
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
-    ProfileSlot prof[5];
+    ProfileSlot prof[6];
 
     std::string err;
 };
@@ -193,6 +194,9 @@ hipError_t launch_trace(int mode, int nt, const TraceArgs& a, hipStream_t s);
 hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out, double* out2,
                               hipStream_t s);
 hipError_t launch_sumsq(const float* x, int ntr, int nt, double* npart, hipStream_t s);
+// out[f] = scale * sum_r sum_k gm[f][r][k] f1p[f][r][(-k) mod nt] (FP64); part holds nf * nr doubles
+hipError_t launch_image(const float* gm, const float* f1p, int nf, int nr, int nt, double scale, double* part,
+                        double* out, hipStream_t s);
 hipError_t launch_gather(const float* src, float* dst, const int* perm, int nf, int64_t per,
                          hipStream_t s);
 hipError_t launch_contract_gemv(const ContractArgs& c, hipStream_t s);

@@ -6,7 +6,7 @@ torch stream, and turns status codes into exceptions.  If the library is
 missing it raises: there is no fallback path.
 
 Functions carry the ABI's names: mk_plan, mk_load_R, mk_set_focal,
-mk_iterate, mk_get, mk_passes, mk_profile, mk_destroy.
+mk_iterate, mk_get, mk_image, mk_passes, mk_profile, mk_destroy.
 """
 
 from __future__ import annotations
@@ -25,7 +25,7 @@ MK_R_C64, MK_R_F16S, MK_R_BF16S = 0, 1, 2
 MK_F1PLUS, MK_F1MINUS, MK_GPLUS, MK_GMINUS = 0, 1, 2, 3
 MK_FLAG_GRAPH, MK_FLAG_PROFILE, MK_FLAG_AUTOTUNE, MK_FLAG_FAST_X, MK_FLAG_ROW_R = 0x1, 0x2, 0x4, 0x8, 0x10
 FIELDS = {"f1plus": MK_F1PLUS, "f1minus": MK_F1MINUS, "Gplus": MK_GPLUS, "Gminus": MK_GMINUS}
-KERNEL_KINDS = {"contract": 0, "epilogue": 1, "norms": 2, "init": 3, "gassembly": 4}
+KERNEL_KINDS = {"contract": 0, "epilogue": 1, "norms": 2, "init": 3, "gassembly": 4, "image": 5}
 
 
 class mk_plan_desc(ctypes.Structure):
@@ -71,6 +71,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mk_iterate": (i32, [P, i32, P]),
         "mk_get": (i32, [P, i32, P, ctypes.c_int]),
         "mk_passes": (i32, [P, ctypes.POINTER(i32)]),
+        "mk_image": (i32, [P, ctypes.POINTER(ctypes.c_double)]),
         "mk_tune": (i32, [P, i32]),
         "mk_contract_variant": (i32, [P, i32, ctypes.POINTER(i32)]),
         "mk_profile": (i32, [P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
@@ -220,6 +221,13 @@ def mk_get(plan: Plan, field, out=None):
             raise TypeError("out must be a C-contiguous float32 array")
         ptr, dev = out.ctypes.data, 0
     _check(load_library().mk_get(plan.handle, fid, ptr, dev), plan.handle)
+    return out
+
+
+def mk_image(plan: Plan) -> np.ndarray:
+    """Double-focusing image per focal point (float64 [nf], the caller's focal order)."""
+    out = np.zeros(plan.nf, dtype=np.float64)
+    _check(load_library().mk_image(plan.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), plan.handle)
     return out
 
 

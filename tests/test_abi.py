@@ -85,6 +85,7 @@ def test_null_arguments(lib):
     assert lib.mk_iterate(None, 1, None) == mk.MK_ERR_ARG
     assert lib.mk_get(None, 0, None, 0) == mk.MK_ERR_ARG
     assert lib.mk_passes(None, None) == mk.MK_ERR_ARG
+    assert lib.mk_image(None, None) == mk.MK_ERR_ARG
     assert lib.mk_profile(None, 0, None, None, 0) == mk.MK_ERR_ARG
     assert lib.mk_destroy(None) == mk.MK_OK
 
