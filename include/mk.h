@@ -64,7 +64,9 @@ typedef enum {
     MK_F1PLUS = 0,   /* f1+ : N_{-1} plus the odd-pass terms  (Algorithm 1)    */
     MK_F1MINUS = 1,  /* f1- : minus the time-reversed even-pass terms          */
     MK_GPLUS = 2,    /* G+  : f1+(-t) - S[f1-(-t)]   (one extra synthesis)     */
-    MK_GMINUS = 3    /* G-  : S[f1+] - f1-           (last lines of Alg. 1)    */
+    MK_GMINUS = 3,   /* G-  : S[f1+] - f1-           (last lines of Alg. 1)    */
+    MK_F2PLUS = 4,   /* f2+ : N_{-1} plus every pass's N_i (Alg. 1, second loop) */
+    MK_PMINUS = 5    /* p-  : sum of every pass's synthesis RN_i (Alg. 1)        */
 } mk_field;
 
 /* Plan flags. */
@@ -166,10 +168,16 @@ mk_status mk_iterate(mk_plan_t plan, int32_t niter, double* norms);
  * MK_GPLUS / MK_GMINUS run the G assembly of the Theory section and the
  * last lines of Algorithm 1: both are formed together from one batched
  * synthesis of f1+ and f1-(-t), with the final subtraction in FP64; the
- * result is cached until the series changes.  Synchronises when out is a
- * host pointer.
+ * result is cached until the series changes.  MK_F2PLUS and MK_PMINUS are
+ * the auxiliary fields of Algorithm 1's second loop (the Theory section
+ * names them as the route to the total G): f2+ = f1+(t) - f1-(-t), which
+ * holds N_{-1} and every N_i; p- = S[f2+ - N_last], formed from the G
+ * assembly and one more synthesis of the last N (so it costs one pass's
+ * contraction).  Both are defined for a plain series only.  The first request
+ * of either allocates an nf_max x nr x nt buffer.  Synchronises when out is
+ * a host pointer.
  * Errors: MK_ERR_ARG (null out, unknown field), MK_ERR_STATE (no focal
- * set), MK_ERR_HIP.
+ * set; MK_F2PLUS or MK_PMINUS after mk_tail_apply), MK_ERR_OOM, MK_ERR_HIP.
  */
 mk_status mk_get(mk_plan_t plan, int32_t field, float* out, int on_device);
 

@@ -472,7 +472,7 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
     constexpr int PM = (M + TPT - 1) / TPT;
     constexpr int TQN = NT / 4, TQP = (TQN + 255) / 256;
     constexpr bool GMODE = MODE == TM_GFWD || MODE == TM_GOUT;
-    constexpr bool YIN = MODE == TM_ITER || MODE == TM_GOUT || MODE == TM_RST1 || MODE == TM_RST2;
+    constexpr bool YIN = MODE == TM_ITER || MODE == TM_GOUT || MODE == TM_RST1 || MODE == TM_RST2 || MODE == TM_POUT;
     constexpr bool FUSED = (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2) && TPT == 64 &&
                            (M == 1024 || M == 2048);
     constexpr bool NEGCONJ = FUSED && MODE != TM_RST2;    // the next field is a time reverse
@@ -887,6 +887,35 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
                 }
             }
             return;
+        } else if constexpr (MODE == TM_POUT) {
+            // p- = sum of the syntheses RN_0 .. RN_{n-1} = S[f2+ - N_last] with
+            // f2+ = f1+ - f1-(-t): S f1+ = G- + f1-, S f1-(-t) = f1+(-t) - G+,
+            // and this launch's Y is S N_last.  Combined in FP64.
+            float2 fpr[PM];
+            if constexpr (TPT == 64 && M >= 64) {
+                load_reversed<NT>(a.f1p + tbase, lane, fpr);      // f1+(-t)
+            } else {
+#pragma unroll
+                for (int p = 0; p < PM; ++p) {
+                    const int m = min(lane + TPT * p, M - 1);
+                    const float* q = a.f1p + tbase;
+                    fpr[p] = make_float2(q[(NT - 2 * m) & (NT - 1)], q[NT - 2 * m - 1]);
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < PM; ++p) {
+                const int m = lane + TPT * p;
+                if (m < M && valid) {
+                    const float2 zm = z[zi(m)];
+                    const float2 gm2 = reinterpret_cast<const float2*>(a.gm + tbase)[m];
+                    const float2 gp2 = reinterpret_cast<const float2*>(a.gp + tbase)[m];
+                    const float2 fm2 = reinterpret_cast<const float2*>(a.f1m + tbase)[m];
+                    const double v0 = ((double)gm2.x + fm2.x) + ((double)gp2.x - fpr[p].x) - (double)(s * zm.x);
+                    const double v1 = ((double)gm2.y + fm2.y) + ((double)gp2.y - fpr[p].y) - (double)(s * zm.y);
+                    reinterpret_cast<float2*>(a.aux + tbase)[m] = make_float2((float)v0, (float)v1);
+                }
+            }
+            return;
         }
 
         // ---- time -> spectrum (TM_INIT, TM_ITER, TM_GFWD, TM_FWDF, restart) ----
@@ -996,6 +1025,18 @@ __global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ x, int 
     if (lane == 0) npart[trace] = acc;
 }
 
+// f2+ = N_-1 + sum of every pass's N_i (Algorithm 1, second loop): the odd
+// passes are in f1+ and f1- holds minus the time reverse of the even ones,
+// so f2+(t) = f1+(t) - f1-(-t).  One thread per sample.
+__global__ __launch_bounds__(256) void k_f2p(const float* __restrict__ f1p, const float* __restrict__ f1m,
+                                             int64_t ntr, int nt, float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= ntr * nt) return;
+    const int64_t tr = i / nt;
+    const int k = (int)(i - tr * nt);
+    out[i] = f1p[i] - f1m[tr * nt + (k == 0 ? 0 : nt - k)];
+}
+
 // Double-focusing image (Theory section, imaging): the zero-time sample of
 // G- convolved in time with f1+ and integrated over the receivers.  First
 // stage, one wave per trace: sum_k G-[k] f1+[(-k) mod nt] in FP64 (a product
@@ -1086,6 +1127,7 @@ hipError_t launch_trace_tpt(int mode, const TraceArgs& a, hipStream_t s) {
         case TM_FWDF: hipLaunchKernelGGL((k_trace<NT, TM_FWDF, TPT>), grid, block, 0, s, a); break;
         case TM_RST1: hipLaunchKernelGGL((k_trace<NT, TM_RST1, TPT>), grid, block, 0, s, a); break;
         case TM_RST2: hipLaunchKernelGGL((k_trace<NT, TM_RST2, TPT>), grid, block, 0, s, a); break;
+        case TM_POUT: hipLaunchKernelGGL((k_trace<NT, TM_POUT, TPT>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1128,6 +1170,13 @@ hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out,
 hipError_t launch_sumsq(const float* x, int ntr, int nt, double* npart, hipStream_t s) {
     if (ntr <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sumsq, dim3((ntr + 3) / 4), dim3(256), 0, s, x, ntr, nt, npart);
+    return hipGetLastError();
+}
+
+hipError_t launch_f2p(const float* f1p, const float* f1m, int64_t ntr, int nt, float* out, hipStream_t s) {
+    if (ntr <= 0) return hipSuccess;
+    const int64_t n = ntr * nt;
+    hipLaunchKernelGGL(k_f2p, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f1p, f1m, ntr, nt, out);
     return hipGetLastError();
 }
 

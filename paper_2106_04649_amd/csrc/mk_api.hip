@@ -69,7 +69,7 @@ void free_plan_memory(mk_plan_t p) {
     void* bufs[] = {p->R, p->rscale, p->X, p->Y, p->f1p, p->f1m, p->gp, p->gm, p->stage, p->itd,
                     p->fband, p->perm, p->iperm, p->ncols, p->npart, p->norm0, p->gdnorm, p->nlast, p->xscale,
                     p->norms, p->tw, p->flag, p->n0, p->hist, p->tail_w, p->tail_x, p->tail_work,
-                    p->tail_y, p->tail_scale, p->img};
+                    p->tail_y, p->tail_scale, p->img, p->aux};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& pe : p->pending) {
@@ -270,6 +270,7 @@ TraceArgs trace_args(mk_plan_t p, int nfo) {
     a.f1m = p->f1m;
     a.gp = p->gp;
     a.gm = p->gm;
+    a.aux = p->aux;
     a.itd = p->itd;
     a.fband = p->has_fband ? p->fband : nullptr;
     a.npart = p->npart;
@@ -365,6 +366,29 @@ mk_status assemble_G(mk_plan_t p) {
     MK_TRY(run_contract(p, p->g_choice, Xg, p->xscale + nf, 2 * nf, 2, 4));
     MK_TRY(run_trace(p, TM_GOUT, a, 4));
     p->g_valid = true;
+    return MK_OK;
+}
+
+// f2+ and p- (Algorithm 1, second loop) into p->aux.  f2+ = f1+ - f1-(-t)
+// holds every N_i; p- = S[f2+ - N_last] comes from the G assembly's two
+// syntheses and one synthesis of the last N, whose spectrum X still holds.
+// After a tail or restart the fields are no longer partial sums of one
+// series, so both are refused there.
+mk_status aux_field(mk_plan_t p, int field) {
+    if (p->tail_applied)
+        return fail(p, MK_ERR_STATE, "mk_get: f2+ and p- are defined for a plain series (no tail applied)");
+    if (!p->aux) {
+        HIP_TRY(p, hipStreamSynchronize(p->stream));
+        HIP_TRY(p, dalloc(&p->aux, (size_t)p->d.nf_max * p->d.nr * p->d.nt));
+    }
+    if (field == MK_F2PLUS) {
+        HIP_TRY(p, launch_f2p(p->f1p, p->f1m, (int64_t)p->nf * p->d.nr, p->d.nt, p->aux, p->stream));
+        return MK_OK;
+    }
+    if (!p->g_valid) MK_TRY(assemble_G(p));
+    MK_TRY(run_contract(p, p->series_choice, p->X, p->xscale, p->nf, 1, 4));
+    TraceArgs a = trace_args(p, p->nf);
+    MK_TRY(run_trace(p, TM_POUT, a, 4));
     return MK_OK;
 }
 
@@ -758,7 +782,7 @@ mk_status mk_iterate(mk_plan_t p, int32_t niter, double* norms) {
 mk_status mk_get(mk_plan_t p, int32_t field, float* out, int on_device) {
     if (!p) return fail(nullptr, MK_ERR_ARG, "mk_get: plan is NULL");
     if (!out) return fail(p, MK_ERR_ARG, "mk_get: out is NULL");
-    if (field < MK_F1PLUS || field > MK_GMINUS) return fail(p, MK_ERR_ARG, "mk_get: unknown field");
+    if (field < MK_F1PLUS || field > MK_PMINUS) return fail(p, MK_ERR_ARG, "mk_get: unknown field");
     if (!p->focal_set) return fail(p, MK_ERR_STATE, "mk_get: no focal points set");
     const float* src = nullptr;
     switch (field) {
@@ -766,8 +790,13 @@ mk_status mk_get(mk_plan_t p, int32_t field, float* out, int on_device) {
         case MK_F1MINUS: src = p->f1m; break;
         case MK_GPLUS: src = p->gp; break;
         case MK_GMINUS: src = p->gm; break;
+        default: break;
     }
     if ((field == MK_GPLUS || field == MK_GMINUS) && !p->g_valid) MK_TRY(assemble_G(p));
+    if (field == MK_F2PLUS || field == MK_PMINUS) {
+        MK_TRY(aux_field(p, field));
+        src = p->aux;
+    }
     const size_t per = (size_t)p->d.nr * p->d.nt;
     const size_t n = (size_t)p->nf * per;
     // back to the caller's focal order: straight into a device destination,

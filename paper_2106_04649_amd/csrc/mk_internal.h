@@ -18,7 +18,8 @@ enum TraceMode : int {
     TM_GOUT = 3,   // G- = irfft(Y[2f]) - f1-;  G+ = f1+(-t) - irfft(Y[2f+1])
     TM_FWDF = 4,   // X[f] = rfft(f1+[f])                      (restart, first synthesis)
     TM_RST1 = 5,   // RN = irfft(Y); f1- := theta RN; N' = -RN(-t) windowed; X = rfft(N')
-    TM_RST2 = 6    // N'' = mute(-RN(-t)); rho = N_-1 + N'' - f1+; f1+ := N_-1 + N''; X = rfft(rho)
+    TM_RST2 = 6,   // N'' = mute(-RN(-t)); rho = N_-1 + N'' - f1+; f1+ := N_-1 + N''; X = rfft(rho)
+    TM_POUT = 7    // aux = p- = (G- + f1-) + (G+ - f1+(-t)) - irfft(Y), Y = S N_last
 };
 
 // Storage of the contraction input X.  The X2 forms keep a 16-bit "hi" plane
@@ -40,6 +41,7 @@ struct TraceArgs {
     float* f1m;
     float* gp;
     float* gm;
+    float* aux;        // [nf][nr][nt] TM_POUT output
     const int32_t* itd;
     const int32_t* fband;
     double* npart;
@@ -103,6 +105,7 @@ struct mk_plan_s {
     double* gdnorm = nullptr;  // [nf_max] ||G_d||: scale of the 16-bit X of the G assembly (f1 fields)
     double* nlast = nullptr;   // [nf_max] norm of the last N (scales 16-bit X)
     double* img = nullptr;     // [nf_max] double-focusing image, sorted focal order
+    float* aux = nullptr;      // [nf_max][nr][nt] f2+ or p- for mk_get (allocated on first request)
     float* xscale = nullptr;   // [3 nf_max] scale stored with 16-bit X
     double* norms = nullptr;   // [norm_cap][nf_max]
     int norm_cap = 0;
@@ -194,6 +197,8 @@ hipError_t launch_trace(int mode, int nt, const TraceArgs& a, hipStream_t s);
 hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out, double* out2,
                               hipStream_t s);
 hipError_t launch_sumsq(const float* x, int ntr, int nt, double* npart, hipStream_t s);
+// out = f1p(t) - f1m(-t) per trace (f2+)
+hipError_t launch_f2p(const float* f1p, const float* f1m, int64_t ntr, int nt, float* out, hipStream_t s);
 // out[f] = scale * sum_r sum_k gm[f][r][k] f1p[f][r][(-k) mod nt] (FP64); part holds nf * nr doubles
 hipError_t launch_image(const float* gm, const float* f1p, int nf, int nr, int nt, double scale, double* part,
                         double* out, hipStream_t s);
