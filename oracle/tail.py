@@ -64,13 +64,17 @@ def geometric_tails(hist: np.ndarray):
     return te, to
 
 
-def net_tails(hist: np.ndarray, P: dict):
-    """Tails from the network: input normalised by the RMS of N_0 on the window."""
+def net_tails(hist: np.ndarray, P: dict, f16: bool = False):
+    """Tails from the network: input normalised by the RMS of N_0 on the window;
+    ``f16`` selects the inference form with half-precision activations."""
     nf, nr, k, T = hist.shape
     h = hist.reshape(nf * nr, k, T).astype(np.float64)
     s = np.sqrt((h[:, 0, :] ** 2).mean(axis=-1))
     inv = np.where(s > 1e-30, 1.0 / np.where(s > 1e-30, s, 1.0), 0.0)
-    y, _ = tailnet.forward(P, h * inv[:, None, None])
+    if f16:
+        y = tailnet.forward_f16(P, h * inv[:, None, None])
+    else:
+        y, _ = tailnet.forward(P, h * inv[:, None, None])
     s = np.where(inv > 0, s, 0.0)
     te = (s[:, None] * y[:, 0, :]).reshape(nf, nr, T)
     to = (s[:, None] * y[:, 1, :]).reshape(nf, nr, T)

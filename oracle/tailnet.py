@@ -83,6 +83,26 @@ def forward(P: Dict[str, np.ndarray], x: np.ndarray, dil=ARCH["dil"]) -> Tuple[n
     return y, [x, a1, h1, a2, h2]
 
 
+FP16_MAX = 65504.0
+
+
+def to_f16(v: np.ndarray) -> np.ndarray:
+    """Round to the nearest IEEE half (ties to even), saturating at +-65504,
+    back in float64: the storage step of the inference form below."""
+    return np.clip(np.asarray(v, dtype=np.float64), -FP16_MAX, FP16_MAX).astype(np.float16).astype(np.float64)
+
+
+def forward_f16(P: Dict[str, np.ndarray], x: np.ndarray, dil=ARCH["dil"]) -> np.ndarray:
+    """The inference form of the tail network with half-precision activations:
+    the input and both hidden activations (after the ReLU) are stored as
+    halves, every product and sum is exact arithmetic on those values (float64
+    here; float32 accumulation on the GPU), the weights are used as given."""
+    h0 = to_f16(x)
+    h1 = to_f16(np.maximum(conv(h0, P["W1"], P["b1"], dil[0]), 0.0))
+    h2 = to_f16(np.maximum(conv(h1, P["W2"], P["b2"], dil[1]), 0.0))
+    return conv(h2, P["W3"], P["b3"], dil[2])
+
+
 def loss_and_grad(P: Dict[str, np.ndarray], x: np.ndarray, target: np.ndarray, mask: np.ndarray,
                   dil=ARCH["dil"]) -> Tuple[float, Dict[str, np.ndarray]]:
     """Masked mean squared error and its gradient with respect to every parameter."""

@@ -73,3 +73,55 @@ def test_adam_first_step_is_lr_times_sign():
     tn.adam_step(P, G, M, V, step=1, lr=0.01, eps=0.0 + 1e-30)
     # after bias correction, the first step moves each weight by lr * sign(g)
     np.testing.assert_allclose(P["w"], [1.0 - 0.01, -2.0 + 0.01, 3.0], atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the inference form with half-precision activations
+# ---------------------------------------------------------------------------
+
+
+def test_half_rounding_hand_values():
+    u = 2.0 ** -10                      # spacing of halves in [1, 2)
+    cases = [(1 + u / 2, 1.0), (1 + 1.5 * u, 1 + 2 * u), (1 + u / 4, 1.0), (1 + 0.75 * u, 1 + u),
+             (70000.0, 65504.0), (-1e6, -65504.0), (2.0 ** -25, 0.0), (3 * 2.0 ** -26, 2.0 ** -24),
+             (-(1 + 1.5 * u), -(1 + 2 * u))]
+    for v, want in cases:
+        assert tn.to_f16(np.array([v]))[0] == want, v
+
+
+def _unit_net(w1=1.0, w2=1.0):
+    """k = 1, hidden 1: centre taps only, so y = (c0, c1) * w2 * w1 * x."""
+    def centre(o, c, v):
+        W = np.zeros((o, c, 5))
+        W[:, :, 2] = v
+        return W
+    W3 = np.zeros((2, 1, 5))
+    W3[0, 0, 2], W3[1, 0, 2] = 1.0, 2.0
+    return {"W1": centre(1, 1, w1), "b1": np.zeros(1), "W2": centre(1, 1, w2), "b2": np.zeros(1),
+            "W3": W3, "b3": np.zeros(2)}
+
+
+def test_half_form_rounds_input_and_both_activations():
+    e = 2.0 ** -12                       # below half a half-ulp at 1: rounds away
+    x = np.full((1, 1, 8), 1.0)
+    for P, xin in ((_unit_net(), x * (1 + e)),          # the input is stored as a half
+                   (_unit_net(w1=1 + e), x),            # so is the first activation
+                   (_unit_net(w2=1 + e), x)):           # and the second
+        y, _ = tn.forward(P, xin)
+        assert not np.allclose(y[0, 0], 1.0, rtol=0, atol=1e-6)
+        y16 = tn.forward_f16(P, xin)
+        np.testing.assert_array_equal(y16[0, 0], np.ones(8))
+        np.testing.assert_array_equal(y16[0, 1], np.full(8, 2.0))
+
+
+def test_half_form_equals_plain_form_on_exact_values():
+    """Integer weights, inputs and biases small enough that every activation
+    is an integer below 2048: both forms agree exactly."""
+    rng = np.random.default_rng(7)
+    P = {"W1": rng.integers(-1, 2, (6, 3, 5)).astype(float), "b1": rng.integers(-2, 3, 6).astype(float),
+         "W2": rng.integers(-1, 2, (6, 6, 5)).astype(float), "b2": rng.integers(-2, 3, 6).astype(float),
+         "W3": rng.integers(-1, 2, (2, 6, 5)).astype(float), "b3": rng.integers(-2, 3, 2).astype(float)}
+    x = rng.integers(-3, 4, (2, 3, 40)).astype(float)
+    y, (_, a1, _, a2, _) = tn.forward(P, x)
+    assert np.abs(a1).max() < 2048 and np.abs(a2).max() < 2048
+    np.testing.assert_array_equal(tn.forward_f16(P, x), y)
