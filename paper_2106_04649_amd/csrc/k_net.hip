@@ -12,6 +12,8 @@
 // BF16-rounded weights (the stored form of the trained network); training
 // keeps FP32 master weights and Adam moments.  All reductions run in a fixed
 // order, so every kernel is deterministic.
+#include <type_traits>
+
 #include "mk_internal.h"
 
 namespace {
@@ -333,22 +335,27 @@ hipError_t conv_fwd(const float* x, const float* W, const float* b, float* y, in
 
 // ---------------------------------------------------------------------------
 // The whole network on one 256-sample tile of one trace (hidden width 16),
-// with the tail it predicts added to f1+ and f1- on the spot.  Each layer's
-// output stays in LDS over the span the next layer reads,
+// in its inference form with half-precision activations, with the tail it
+// predicts added to f1+ and f1- on the spot.  Each layer's output stays in
+// LDS over the span the next layer reads,
 //
 //   y on [t0, t0 + 256), a2 on [t0 - 32, t0 + 288), a1 on [t0 - 40, t0 + 296),
 //   x on [t0 - 42, t0 + 298),
 //
 // zero outside [0, T) exactly as the layer-by-layer form pads each input.
-// Layers 1 and 2 are products of a 16 x 5C weight block with a 5C x 16
-// shifted-sample block: they run on the FP32 matrix cores
-// (v_mfma_f32_16x16x4_f32, 16 outputs x 16 samples x 4 (channel, tap) pairs
-// per instruction; in step s the four lane groups g feed tap s / Q of
-// channels s % Q + Q g, so a group's LDS row differs from the next by a fixed
-// stride).  Layer 3 (two outputs) runs on the vector ALUs.  A tile that shares
-// no sample with the trace's mute window is skipped: the tail is only used
-// inside the window, and two tiles never touch the same sample of f1.
+// The input and both hidden activations are stored as halves (round to
+// nearest even, saturating at 65504); the weights (BF16-rounded FP32 values,
+// exact in half precision within its range) are converted once.  Each layer
+// is a product of a 16 x 5C weight block with a 5C x 16 block of shifted
+// samples on v_mfma_f32_16x16x32_f16 with FP32 accumulation (a product of two
+// halves is exact in FP32).  Activations are stored sample-major, channels
+// contiguous, so the eight K values a lane feeds (eight channels at one tap,
+// or four channels at two adjacent taps) are one or two LDS reads.  A tile
+// that shares no sample with the trace's mute window is skipped: the tail is
+// only used inside the window, and two tiles never touch the same f1 sample.
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 
 constexpr int kFH = 16;                        // hidden width of this form
 constexpr int kFT = 256;                       // output samples per block
@@ -356,19 +363,85 @@ constexpr int kX0 = 42, kA10 = 40, kA20 = 32;  // reach of x, a1, a2 left of t0
 constexpr int kXN = kFT + 2 * kX0;             // 340 staged input samples
 constexpr int kA1N = kFT + 2 * kA10;           // 336 = 21 tiles of 16
 constexpr int kA2N = kFT + 2 * kA20;           // 320 = 20 tiles of 16
-// row strides: a group's rows sit 16 banks apart (64 x 4-byte banks) for
-// the matrix-core operand reads and the accumulator stores
-constexpr int kXW = 400, kA1W = 340, kA2W = 324;
+constexpr int kHP = 24;                        // halves per sample row of 16 channels:
+                                               // 48-byte rows, 16 lanes' 16-byte reads hit distinct banks
 
-template <int Q>
-__global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, const float* __restrict__ hist,
+__device__ __forceinline__ _Float16 to_half_sat(float v) {
+    return (_Float16)fminf(fmaxf(v, -65504.f), 65504.f);
+}
+
+// K pairing of one matrix-core step of a C-channel layer: lane group g,
+// element e -> (channel, tap).  C = 16: tap 2m + g/2, channels 8 (g & 1) + e;
+// C = 8: tap 4m + g, channel e; C = 4: taps 8m + 2g + e/4, channel e & 3.
+template <int C>
+__device__ __forceinline__ void kpair(int m, int g, int e, int& c, int& j) {
+    if constexpr (C == 16) { j = 2 * m + (g >> 1); c = 8 * (g & 1) + e; }
+    else if constexpr (C == 8) { j = 4 * m + g; c = e; }
+    else { j = 8 * m + 2 * g + (e >> 2); c = e & 3; }
+}
+template <int C> constexpr int ksteps() { return C == 16 ? 3 : C == 8 ? 2 : 1; }
+
+// A operand of step m for output row i16 (rows >= nout and pairs past the
+// five taps or the cin real channels are zero): W [nout][cin][5] FP32
+template <int C>
+__device__ __forceinline__ h8 weights_a(const float* __restrict__ W, int cin, int nout, int i16, int g, int m) {
+    h8 a;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        int c, j;
+        kpair<C>(m, g, e, c, j);
+        const bool ok = i16 < nout && c < cin && j < kTaps;
+        a[e] = ok ? (_Float16)W[(i16 * cin + c) * kTaps + j] : (_Float16)0.f;
+    }
+    return a;
+}
+
+// B operand of step m: the activation rows act[(s + d j) * pitch + c] of
+// sample s of the tile (taps past the fifth read tap 4: their weights are 0)
+template <int C, int D, int PITCH>
+__device__ __forceinline__ h8 acts_b(const _Float16* act, int s, int g, int m) {
+    if constexpr (C == 4) {
+        const int j0 = min(8 * m + 2 * g, kTaps - 1), j1 = min(8 * m + 2 * g + 1, kTaps - 1);
+        const h4 lo = *reinterpret_cast<const h4*>(act + (s + D * j0) * PITCH);
+        const h4 hi = *reinterpret_cast<const h4*>(act + (s + D * j1) * PITCH);
+        return h8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    } else {
+        int c, j;
+        kpair<C>(m, g, 0, c, j);
+        j = min(j, kTaps - 1);
+        return *reinterpret_cast<const h8*>(act + (s + D * j) * PITCH + c);
+    }
+}
+
+// The three layers' A operands in the per-lane order the matrix cores take
+// them, written once per loaded network: step q of the table holds 64 lanes
+// x 8 halves, so a block reads each step with one 16-byte load per lane.
+// Steps: layer 1 (ksteps<KP>), layer 2 (3), layer 3 (3).
+template <int KP>
+__global__ __launch_bounds__(64) void k_pack_tail(const float* __restrict__ P, int k, h8* __restrict__ out) {
+    constexpr int S1 = ksteps<KP>(), S2 = ksteps<kFH>();
+    const int lane = threadIdx.x, i16 = lane & 15, g = lane >> 4, q = blockIdx.x;
+    const float* W1 = P;
+    const float* W2 = W1 + kFH * k * kTaps + kFH;
+    const float* W3 = W2 + kFH * kFH * kTaps + kFH;
+    h8 a;
+    if (q < S1) a = weights_a<KP>(W1, k, kFH, i16, g, q);
+    else if (q < S1 + S2) a = weights_a<kFH>(W2, kFH, kFH, i16, g, q - S1);
+    else a = weights_a<kFH>(W3, kFH, 2, i16, g, q - S1 - S2);
+    out[q * 64 + lane] = a;
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, const h8* __restrict__ wpk,
+                                                  const float* __restrict__ hist,
                                                   const float* __restrict__ scale, const int32_t* __restrict__ itd,
                                                   int shift, int k, int T, int nt, float* __restrict__ f1p,
                                                   float* __restrict__ f1m) {
-    constexpr int KP = 4 * Q;                  // input channels padded to a multiple of 4
-    constexpr int U2 = KP * kXW > kFH * kA2W ? KP * kXW : kFH * kA2W;
-    __shared__ float a1s[kFH * kA1W];
-    __shared__ float u2[U2];                   // x, then a2
+    constexpr int XP = KP == 16 ? kHP : KP;    // halves per staged input sample
+    constexpr int S1 = ksteps<KP>(), S2 = ksteps<kFH>();
+    constexpr int U2 = kXN * XP > kA2N * kHP ? kXN * XP : kA2N * kHP;
+    __shared__ __attribute__((aligned(16))) _Float16 a1s[kA1N * kHP];
+    __shared__ __attribute__((aligned(16))) _Float16 u2[U2];     // x, then a2
     const int tr = blockIdx.x;
     const int t0 = blockIdx.y * kFT;
     const int hT = T >> 1;
@@ -379,115 +452,142 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     const float inv = se > 0.f ? 1.f / se : 0.f;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i16 = lane & 15, g = lane >> 4;
-    const float* W1 = P;
-    const float* B1 = W1 + kFH * k * kTaps;
-    const float* W2 = B1 + kFH;
-    const float* B2 = W2 + kFH * kFH * kTaps;
-    const float* W3 = B2 + kFH;
-    const float* B3 = W3 + 2 * kFH * kTaps;
+    const float* B1 = P + kFH * k * kTaps;
+    const float* B2 = B1 + kFH + kFH * kFH * kTaps;
+    const float* B3 = B2 + kFH + 2 * kFH * kTaps;
 
-    // weights in the A-operand layout: lane (i16, g) holds output i16's
-    // weight for the (channel, tap) pair its group feeds in each step
-    float w1[5 * Q], w2[20];
+    h8 w1[S1], w2[S2], w3[S2];
 #pragma unroll
-    for (int s = 0; s < 5 * Q; ++s) {
-        const int c = s % Q + Q * g;
-        w1[s] = c < k ? W1[(i16 * k + c) * kTaps + s / Q] : 0.f;
+    for (int m = 0; m < S1; ++m) w1[m] = wpk[m * 64 + lane];
+#pragma unroll
+    for (int m = 0; m < S2; ++m) {
+        w2[m] = wpk[(S1 + m) * 64 + lane];
+        w3[m] = wpk[(S1 + S2 + m) * 64 + lane];
     }
+    v4f bias1, bias2, bias3;
 #pragma unroll
-    for (int s = 0; s < 20; ++s) w2[s] = W2[(i16 * kFH + s % 4 + 4 * g) * kTaps + s / 4];
-    v4f bias1, bias2;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bias1[r] = B1[4 * g + r], bias2[r] = B2[4 * g + r];
+    for (int r = 0; r < 4; ++r) {
+        bias1[r] = B1[4 * g + r];
+        bias2[r] = B2[4 * g + r];
+        bias3[r] = 4 * g + r < 2 ? B3[4 * g + r] : 0.f;
+    }
 
-    float* xs = u2;
+    // Every global load of the block is issued here, before any use: the
+    // input samples (one thread per sample, all channels) and the f1 samples
+    // this block updates (tile wv + 4 m, sample i16; lanes of every group
+    // load the same addresses as group 0, which alone stores).
     const float* h = hist + (size_t)tr * k * T;
-    for (int i = threadIdx.x; i < KP * kXN; i += 256) {
-        const int c = i / kXN, u = i - c * kXN;
+    constexpr int NU = (kXN + 255) / 256;
+    float xv[NU][KP];
+#pragma unroll
+    for (int it = 0; it < NU; ++it) {
+        const int u = threadIdx.x + 256 * it;
         const int t = t0 - kX0 + u;
-        xs[c * kXW + u] = (c < k && t >= 0 && t < T) ? h[(size_t)c * T + t] * inv : 0.f;
-    }
-    __syncthreads();
-
-    // layer 1: a1 = relu(conv(x)), tiles wv, wv + 4, ... of 21
-    {
-        const float* xb = xs + Q * g * kXW + i16;
-        auto tile = [&](int nb) {
-            v4f acc = bias1;
+        const bool in = u < kXN && t >= 0 && t < T;
+        const float* hc = h + (in ? t : 0);
 #pragma unroll
-            for (int s = 0; s < 5 * Q; ++s)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w1[s], xb[(s % Q) * kXW + nb + s / Q], acc, 0, 0, 0);
-            const int t = t0 - kA10 + nb + i16;
-            const bool ok = t >= 0 && t < T;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) a1s[(4 * g + r) * kA1W + nb + i16] = ok ? fmaxf(acc[r], 0.f) : 0.f;
-        };
-        v4f acc[5];
-#pragma unroll
-        for (int m = 0; m < 5; ++m) acc[m] = bias1;
-#pragma unroll
-        for (int s = 0; s < 5 * Q; ++s)
-#pragma unroll
-            for (int m = 0; m < 5; ++m)
-                acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                    w1[s], xb[(s % Q) * kXW + 16 * (wv + 4 * m) + s / Q], acc[m], 0, 0, 0);
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {
-            const int nb = 16 * (wv + 4 * m);
-            const int t = t0 - kA10 + nb + i16;
-            const bool ok = t >= 0 && t < T;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) a1s[(4 * g + r) * kA1W + nb + i16] = ok ? fmaxf(acc[m][r], 0.f) : 0.f;
+        for (int c = 0; c < KP; ++c) {
+            const float v = hc[(size_t)(c < k ? c : 0) * T];          // always a valid address
+            xv[it][c] = (in && c < k) ? v : 0.f;
         }
-        if (wv == 0) tile(16 * 20);
     }
-    __syncthreads();
+    float* fp = f1p + (size_t)tr * nt;
+    float* fm = f1m + (size_t)tr * nt;
+    int ip[4], im[4];
+    bool upd[4];
+    float pv[4], mv[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int u = t0 + 16 * (wv + 4 * m) + i16;
+        const int t = u - hT;
+        upd[m] = u < T && t < L && -t < L && t != nt / 2 && -t != nt / 2;
+        ip[m] = upd[m] ? ((t % nt) + nt) % nt : 0;
+        im[m] = upd[m] ? ((-t % nt) + nt) % nt : 0;
+        pv[m] = fp[ip[m]];
+        mv[m] = fm[im[m]];
+    }
 
-    // layer 2: a2 = relu(conv(a1)), 20 tiles, five per wave (x is dead: a2 takes its place)
-    float* a2s = u2;
-    {
-        const float* ab = a1s + 4 * g * kA1W + i16;
-        v4f acc[5];
+    // stage x = hist * inv as halves, sample-major; padding channels are zero
+    _Float16* xs = u2;
 #pragma unroll
-        for (int m = 0; m < 5; ++m) acc[m] = bias2;
+    for (int it = 0; it < NU; ++it) {
+        const int u = threadIdx.x + 256 * it;
+        if (u < kXN) {
 #pragma unroll
-        for (int s = 0; s < 20; ++s)
-#pragma unroll
-            for (int m = 0; m < 5; ++m)
-                acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                    w2[s], ab[(s % 4) * kA1W + 16 * (wv + 4 * m) + 4 * (s / 4)], acc[m], 0, 0, 0);
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {
-            const int nb = 16 * (wv + 4 * m);
-            const int t = t0 - kA20 + nb + i16;
-            const bool ok = t >= 0 && t < T;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) a2s[(4 * g + r) * kA2W + nb + i16] = ok ? fmaxf(acc[m][r], 0.f) : 0.f;
+            for (int c0 = 0; c0 < KP; c0 += 4)
+                *reinterpret_cast<h4*>(xs + u * XP + c0) =
+                    h4{to_half_sat(xv[it][c0] * inv), to_half_sat(xv[it][c0 + 1] * inv),
+                       to_half_sat(xv[it][c0 + 2] * inv), to_half_sat(xv[it][c0 + 3] * inv)};
         }
     }
     __syncthreads();
 
-    // layer 3 (channel, then tap, as the layer-by-layer kernels sum) and the
-    // tail: f1+ += s y_odd, f1- -= s y_even(-t) inside the window
-    const int sidx = threadIdx.x;
-    const int u = t0 + sidx;
-    float ye = B3[0], yo = B3[1];
-    for (int c = 0; c < kFH; ++c) {
-        const float* ar = a2s + c * kA2W + sidx;
+    // NT tiles of a hidden layer at once (tiles wv + 4 i): every operand read
+    // is issued before the first product, the products of different tiles
+    // interleave, and rows 4 g + r of each result go to LDS as halves
+    auto hidden_layer = [&](auto cin_tag, auto d_tag, auto pitch_tag, auto nt_tag, const _Float16* in, const h8* w,
+                            v4f bias, _Float16* out, int tile0, int tstep, int tfirst) {
+        constexpr int C = decltype(cin_tag)::value, D = decltype(d_tag)::value, PIN = decltype(pitch_tag)::value;
+        constexpr int NTL = decltype(nt_tag)::value, NS = ksteps<C>();
+        h8 b[NTL][NS];
 #pragma unroll
-        for (int j = 0; j < kTaps; ++j) {
-            const float a = ar[16 * j];
-            ye = fmaf(W3[c * kTaps + j], a, ye);
-            yo = fmaf(W3[(kFH + c) * kTaps + j], a, yo);
+        for (int i = 0; i < NTL; ++i)
+#pragma unroll
+            for (int q = 0; q < NS; ++q) b[i][q] = acts_b<C, D, PIN>(in, 16 * (tile0 + tstep * i) + i16, g, q);
+        v4f acc[NTL];
+#pragma unroll
+        for (int i = 0; i < NTL; ++i) acc[i] = bias;
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+#pragma unroll
+            for (int i = 0; i < NTL; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[q], b[i][q], acc[i], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < NTL; ++i) {
+            const int sidx = 16 * (tile0 + tstep * i) + i16;
+            const int t = tfirst + sidx;
+            const bool ok = t >= 0 && t < T;
+            h4 o;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[r] = ok ? to_half_sat(fmaxf(acc[i][r], 0.f)) : (_Float16)0.f;
+            *reinterpret_cast<h4*>(out + sidx * kHP + 4 * g) = o;
         }
-    }
-    const int t = u - hT;
-    if (u < T && t < L && -t < L && t != nt / 2 && -t != nt / 2) {
-        const int ip = ((t % nt) + nt) % nt, im = ((-t % nt) + nt) % nt;
-        float* fp = f1p + (size_t)tr * nt;
-        float* fm = f1m + (size_t)tr * nt;
-        fp[ip] = fp[ip] + se * yo;
-        fm[im] = fm[im] - se * ye;
+    };
+
+    // layer 1: 21 tiles; layer 2: 20 tiles (x is dead: a2 takes its place)
+    hidden_layer(std::integral_constant<int, KP>{}, std::integral_constant<int, 1>{},
+                 std::integral_constant<int, XP>{}, std::integral_constant<int, 5>{}, xs, w1, bias1, a1s, wv, 4,
+                 t0 - kA10);
+    if (wv == 0)
+        hidden_layer(std::integral_constant<int, KP>{}, std::integral_constant<int, 1>{},
+                     std::integral_constant<int, XP>{}, std::integral_constant<int, 1>{}, xs, w1, bias1, a1s, 20, 0,
+                     t0 - kA10);
+    __syncthreads();
+    _Float16* a2s = u2;
+    hidden_layer(std::integral_constant<int, kFH>{}, std::integral_constant<int, 4>{},
+                 std::integral_constant<int, kHP>{}, std::integral_constant<int, 5>{}, a1s, w2, bias2, a2s, wv, 4,
+                 t0 - kA20);
+    __syncthreads();
+
+    // layer 3 (rows 0 and 1 of a padded 16-row product) and the tail:
+    // f1+ += s y_odd, f1- -= s y_even(-t) inside the window
+    h8 b3[4][S2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < S2; ++q) b3[m][q] = acts_b<kFH, 16, kHP>(a2s, 16 * (wv + 4 * m) + i16, g, q);
+    v4f y[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) y[m] = bias3;
+#pragma unroll
+    for (int q = 0; q < S2; ++q)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) y[m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[q], b3[m][q], y[m], 0, 0, 0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if (g == 0 && upd[m]) {
+            fp[ip[m]] = pv[m] + se * y[m][1];
+            fm[im[m]] = mv[m] - se * y[m][0];
+        }
     }
 }
 
@@ -521,17 +621,37 @@ hipError_t net_forward(const float* P, const float* x, int N, int k, int H, int 
 
 bool net_tail_fused(int k, int H) { return H == kFH && k >= 1 && k <= 16; }
 
-hipError_t net_tail_apply(const float* P, const float* hist, const float* scale, const int32_t* itd, int shift,
-                          int ntr, int k, int H, int T, int nt, float* f1p, float* f1m, hipStream_t s) {
+size_t net_tail_pack_bytes(int k) {
+    const int s1 = k <= 4 ? ksteps<4>() : k <= 8 ? ksteps<8>() : ksteps<16>();
+    return (size_t)(s1 + 2 * ksteps<kFH>()) * 64 * sizeof(h8);
+}
+
+hipError_t net_tail_pack(const float* P, int k, int H, void* out, hipStream_t s) {
+    if (!net_tail_fused(k, H)) return hipErrorInvalidValue;
+    h8* o = static_cast<h8*>(out);
+    const int s2 = 2 * ksteps<kFH>();
+    if (k <= 4)
+        hipLaunchKernelGGL(k_pack_tail<4>, dim3(ksteps<4>() + s2), dim3(64), 0, s, P, k, o);
+    else if (k <= 8)
+        hipLaunchKernelGGL(k_pack_tail<8>, dim3(ksteps<8>() + s2), dim3(64), 0, s, P, k, o);
+    else
+        hipLaunchKernelGGL(k_pack_tail<16>, dim3(ksteps<16>() + s2), dim3(64), 0, s, P, k, o);
+    return hipGetLastError();
+}
+
+hipError_t net_tail_apply(const float* P, const void* wpack, const float* hist, const float* scale,
+                          const int32_t* itd, int shift, int ntr, int k, int H, int T, int nt, float* f1p,
+                          float* f1m, hipStream_t s) {
     if (!net_tail_fused(k, H)) return hipErrorInvalidValue;
     if (ntr <= 0 || T <= 0) return hipSuccess;
+    const h8* w = static_cast<const h8*>(wpack);
     const dim3 grid(ntr, (T + kFT - 1) / kFT);
-    switch ((k + 3) / 4) {
-        case 1: hipLaunchKernelGGL(k_net_tail<1>, grid, dim3(256), 0, s, P, hist, scale, itd, shift, k, T, nt, f1p, f1m); break;
-        case 2: hipLaunchKernelGGL(k_net_tail<2>, grid, dim3(256), 0, s, P, hist, scale, itd, shift, k, T, nt, f1p, f1m); break;
-        case 3: hipLaunchKernelGGL(k_net_tail<3>, grid, dim3(256), 0, s, P, hist, scale, itd, shift, k, T, nt, f1p, f1m); break;
-        default: hipLaunchKernelGGL(k_net_tail<4>, grid, dim3(256), 0, s, P, hist, scale, itd, shift, k, T, nt, f1p, f1m); break;
-    }
+    if (k <= 4)
+        hipLaunchKernelGGL(k_net_tail<4>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p, f1m);
+    else if (k <= 8)
+        hipLaunchKernelGGL(k_net_tail<8>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p, f1m);
+    else
+        hipLaunchKernelGGL(k_net_tail<16>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p, f1m);
     return hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ void free_plan_memory(mk_plan_t p) {
     void* bufs[] = {p->R, p->rscale, p->X, p->Y, p->f1p, p->f1m, p->gp, p->gm, p->stage, p->itd,
                     p->fband, p->perm, p->iperm, p->ncols, p->npart, p->norm0, p->gdnorm, p->nlast, p->xscale,
                     p->norms, p->tw, p->flag, p->n0, p->hist, p->tail_w, p->tail_x, p->tail_work,
-                    p->tail_y, p->tail_scale, p->img, p->aux};
+                    p->tail_y, p->tail_scale, p->img, p->aux, p->tail_wpk};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& pe : p->pending) {
@@ -932,6 +932,10 @@ mk_status mk_tail_load(mk_plan_t p, const float* params, int32_t count) {
     }
     p->tail_net_hidden = H;
     if (!p->tail_scale) HIP_TRY(p, dalloc(&p->tail_scale, (size_t)ntr));
+    if (net_tail_fused(p->hist_k, H)) {
+        if (!p->tail_wpk) HIP_TRY(p, hipMalloc(&p->tail_wpk, net_tail_pack_bytes(16)));   // room for any k
+        HIP_TRY(p, net_tail_pack(p->tail_w, p->hist_k, H, p->tail_wpk, p->stream));
+    }
     HIP_TRY(p, hipStreamSynchronize(p->stream));
     return MK_OK;
 }
@@ -968,7 +972,7 @@ mk_status mk_tail_apply(mk_plan_t p, int32_t mode, double* rel_resid) {
     const int ntr = p->nf * nr;
     if (mode == 0 && net_tail_fused(k, p->tail_net_hidden)) {
         HIP_TRY(p, launch_tail_prep(p->hist, ntr, k, T, nullptr, p->tail_scale, p->stream));
-        HIP_TRY(p, net_tail_apply(p->tail_w, p->hist, p->tail_scale, p->itd, p->shift, ntr, k,
+        HIP_TRY(p, net_tail_apply(p->tail_w, p->tail_wpk, p->hist, p->tail_scale, p->itd, p->shift, ntr, k,
                                   p->tail_net_hidden, T, nt, p->f1p, p->f1m, p->stream));
     } else if (mode == 0) {
         const int H = p->tail_net_hidden;

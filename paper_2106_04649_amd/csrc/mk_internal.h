@@ -117,6 +117,7 @@ struct mk_plan_s {
     float* hist = nullptr;     // [nf_max][nr][hist_k][hist_T]
     int hist_k = 0, hist_T = 0;
     float* tail_w = nullptr;   // BF16-rounded parameters
+    void* tail_wpk = nullptr;  // the same weights packed for the one-kernel form
     int tail_nw = 0;
     float* tail_x = nullptr;   // [chunk][k][T] normalised input (layer-by-layer form only)
     float* tail_work = nullptr;   // [2][chunk][hidden][T] (layer-by-layer form only)
@@ -240,8 +241,12 @@ hipError_t net_forward(const float* P, const float* x, int N, int k, int H, int 
 // the whole network plus the tail's application in one kernel per 256-sample
 // tile (hidden width 16, k <= 16); other widths go layer by layer
 bool net_tail_fused(int k, int H);
-hipError_t net_tail_apply(const float* P, const float* hist, const float* scale, const int32_t* itd, int shift,
-                          int ntr, int k, int H, int T, int nt, float* f1p, float* f1m, hipStream_t s);
+// the weights in the matrix cores' per-lane order (net_tail_pack_bytes(k) bytes), written once per network
+size_t net_tail_pack_bytes(int k);
+hipError_t net_tail_pack(const float* P, int k, int H, void* out, hipStream_t s);
+hipError_t net_tail_apply(const float* P, const void* wpack, const float* hist, const float* scale,
+                          const int32_t* itd, int shift, int ntr, int k, int H, int T, int nt, float* f1p,
+                          float* f1m, hipStream_t s);
 hipError_t net_backward(const float* P, const float* x, const float* a1, const float* a2, const float* gy,
                         int N, int k, int H, int T, float* G, float* g1, float* g2, float* wt, hipStream_t s);
 hipError_t net_mse(const float* y, const float* tgt, const float* mask, int N, int T, float* gy,
