@@ -445,11 +445,10 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     const int tr = blockIdx.x;
     const int t0 = blockIdx.y * kFT;
     const int hT = T >> 1;
+    // the loads of the block go out before the window test that needs itd,
+    // so that they are in flight together (a skipped tile wastes them)
     const int L = itd[tr] - shift;
-    // window samples u = t + T/2 with |t| < L
-    if (L <= 0 || t0 >= hT + L || t0 + kFT <= hT - L + 1) return;
     const float se = scale[tr];
-    const float inv = se > 0.f ? 1.f / se : 0.f;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i16 = lane & 15, g = lane >> 4;
     const float* B1 = P + kFH * k * kTaps;
@@ -469,7 +468,9 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     for (int r = 0; r < 4; ++r) {
         bias1[r] = B1[4 * g + r];
         bias2[r] = B2[4 * g + r];
-        bias3[r] = 4 * g + r < 2 ? B3[4 * g + r] : 0.f;
+        // unconditional loads, masked: a selected load becomes a branch that waits for it
+        const float v3 = B3[min(4 * g + r, 1)];
+        bias3[r] = __uint_as_float(__float_as_uint(v3) & (4 * g + r < 2 ? 0xFFFFFFFFu : 0u));
     }
 
     // Every global load of the block is issued here, before any use: the
@@ -487,24 +488,36 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
         const float* hc = h + (in ? t : 0);
 #pragma unroll
         for (int c = 0; c < KP; ++c) {
-            const float v = hc[(size_t)(c < k ? c : 0) * T];          // always a valid address
-            xv[it][c] = (in && c < k) ? v : 0.f;
+            // always a valid address; the value is masked, not selected (a
+            // selected load becomes a branch that waits for it)
+            const float v = hc[(size_t)(c < k ? c : 0) * T];
+            xv[it][c] = __uint_as_float(__float_as_uint(v) & ((in && c < k) ? 0xFFFFFFFFu : 0u));
         }
     }
     float* fp = f1p + (size_t)tr * nt;
     float* fm = f1m + (size_t)tr * nt;
     int ip[4], im[4];
-    bool upd[4];
     float pv[4], mv[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        // |t| <= T/2 <= nt/2 for u < T: one wrap at most
+        const int u = t0 + 16 * (wv + 4 * m) + i16;
+        const int t = u - hT;
+        const bool inr = u < T;
+        ip[m] = inr ? (t < 0 ? t + nt : t) : 0;
+        im[m] = inr ? (t > 0 ? nt - t : -t) : 0;
+        pv[m] = fp[ip[m]];
+        mv[m] = fm[im[m]];
+    }
+    // window samples u = t + T/2 with |t| < L
+    if (L <= 0 || t0 >= hT + L || t0 + kFT <= hT - L + 1) return;
+    const float inv = se > 0.f ? 1.f / se : 0.f;
+    bool upd[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int u = t0 + 16 * (wv + 4 * m) + i16;
         const int t = u - hT;
         upd[m] = u < T && t < L && -t < L && t != nt / 2 && -t != nt / 2;
-        ip[m] = upd[m] ? ((t % nt) + nt) % nt : 0;
-        im[m] = upd[m] ? ((-t % nt) + nt) % nt : 0;
-        pv[m] = fp[ip[m]];
-        mv[m] = fm[im[m]];
     }
 
     // stage x = hist * inv as halves, sample-major; padding channels are zero
