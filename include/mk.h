@@ -320,7 +320,11 @@ mk_status mk_tail_history(mk_plan_t plan, float* out, int on_device);
  * A^2 f1+ (A = theta Rev S; two syntheses, counted as two passes), whose
  * residual rho starts a new series carrying the remaining error; later
  * mk_iterate calls continue that series.  mode 0: the loaded network
- * (inputs normalised by the RMS of N_0 per trace); 1: geometric
+ * (inputs normalised by the RMS of N_0 per trace; with hidden width 16 it
+ * runs as one kernel in its half-precision inference form -- input and
+ * hidden activations stored as IEEE halves, FP32 accumulation -- and only
+ * on the 256-sample tiles that meet the mute window; other widths run layer
+ * by layer in FP32); 1: geometric
  * extrapolation of the last two iterates of each parity (needs an even
  * k >= 4); 2: no estimate (exactly two more passes of the plain series).
  * rel_resid: host double [nf] receiving ||rho|| / ||G_d|| per focal point
