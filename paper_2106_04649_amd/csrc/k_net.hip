@@ -363,8 +363,9 @@ constexpr int kX0 = 42, kA10 = 40, kA20 = 32;  // reach of x, a1, a2 left of t0
 constexpr int kXN = kFT + 2 * kX0;             // 340 staged input samples
 constexpr int kA1N = kFT + 2 * kA10;           // 336 = 21 tiles of 16
 constexpr int kA2N = kFT + 2 * kA20;           // 320 = 20 tiles of 16
-constexpr int kHP = 24;                        // halves per sample row of 16 channels:
-                                               // 48-byte rows, 16 lanes' 16-byte reads hit distinct banks
+constexpr int kHP = 16;                        // halves per sample row of 16 channels: 32-byte
+                                               // rows, so the eight lanes a 16-byte read serves per
+                                               // cycle hit distinct banks
 
 __device__ __forceinline__ _Float16 to_half_sat(float v) {
     return (_Float16)fminf(fmaxf(v, -65504.f), 65504.f);
@@ -455,14 +456,11 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     const float* B2 = B1 + kFH + kFH * kFH * kTaps;
     const float* B3 = B2 + kFH + 2 * kFH * kTaps;
 
-    h8 w1[S1], w2[S2], w3[S2];
+    // layer 1's weights now; layers 2 and 3 load theirs where they start
+    // (cache hits), so that fewer registers stay live
+    h8 w1[S1];
 #pragma unroll
     for (int m = 0; m < S1; ++m) w1[m] = wpk[m * 64 + lane];
-#pragma unroll
-    for (int m = 0; m < S2; ++m) {
-        w2[m] = wpk[(S1 + m) * 64 + lane];
-        w3[m] = wpk[(S1 + S2 + m) * 64 + lane];
-    }
     v4f bias1, bias2, bias3;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -496,18 +494,22 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     }
     float* fp = f1p + (size_t)tr * nt;
     float* fm = f1m + (size_t)tr * nt;
-    int ip[4], im[4];
+    // |t| <= T/2 <= nt/2 for u < T: one wrap at most
+    auto f1_ip = [&](int m) {
+        const int u = t0 + 16 * (wv + 4 * m) + i16;
+        const int t = u - hT;
+        return u < T ? (t < 0 ? t + nt : t) : 0;
+    };
+    auto f1_im = [&](int m) {
+        const int u = t0 + 16 * (wv + 4 * m) + i16;
+        const int t = u - hT;
+        return u < T ? (t > 0 ? nt - t : -t) : 0;
+    };
     float pv[4], mv[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        // |t| <= T/2 <= nt/2 for u < T: one wrap at most
-        const int u = t0 + 16 * (wv + 4 * m) + i16;
-        const int t = u - hT;
-        const bool inr = u < T;
-        ip[m] = inr ? (t < 0 ? t + nt : t) : 0;
-        im[m] = inr ? (t > 0 ? nt - t : -t) : 0;
-        pv[m] = fp[ip[m]];
-        mv[m] = fm[im[m]];
+        pv[m] = fp[f1_ip(m)];
+        mv[m] = fm[f1_im(m)];
     }
     // window samples u = t + T/2 with |t| < L
     if (L <= 0 || t0 >= hT + L || t0 + kFT <= hT - L + 1) return;
@@ -576,6 +578,9 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
                      t0 - kA10);
     __syncthreads();
     _Float16* a2s = u2;
+    h8 w2[S2];
+#pragma unroll
+    for (int m = 0; m < S2; ++m) w2[m] = wpk[(S1 + m) * 64 + lane];
     hidden_layer(std::integral_constant<int, kFH>{}, std::integral_constant<int, 4>{},
                  std::integral_constant<int, kHP>{}, std::integral_constant<int, 5>{}, a1s, w2, bias2, a2s, wv, 4,
                  t0 - kA20);
@@ -583,6 +588,9 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
 
     // layer 3 (rows 0 and 1 of a padded 16-row product) and the tail:
     // f1+ += s y_odd, f1- -= s y_even(-t) inside the window
+    h8 w3[S2];
+#pragma unroll
+    for (int m = 0; m < S2; ++m) w3[m] = wpk[(S1 + S2 + m) * 64 + lane];
     h8 b3[4][S2];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -598,8 +606,8 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         if (g == 0 && upd[m]) {
-            fp[ip[m]] = pv[m] + se * y[m][1];
-            fm[im[m]] = mv[m] - se * y[m][0];
+            fp[f1_ip(m)] = pv[m] + se * y[m][1];
+            fm[f1_im(m)] = mv[m] - se * y[m][0];
         }
     }
 }
