@@ -464,8 +464,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(focal points or receiver rows would shard across GPUs; see the design notes)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(focal points or receiver rows would shard across GPUs)",
               file=sys.stderr)
         return 2
 

@@ -48,7 +48,7 @@ typedef enum {
     MK_ERR_STATE = 2,        /* call out of order (e.g. iterate before load_R)  */
     MK_ERR_OOM = 3,          /* device allocation failed                        */
     MK_ERR_HIP = 4,          /* a HIP runtime call failed                       */
-    MK_ERR_UNSUPPORTED = 5,  /* valid request this build does not implement     */
+    MK_ERR_UNSUPPORTED = 5,  /* valid request the library does not implement     */
     MK_ERR_DIVERGED = 6      /* series norms non-finite or above div_factor     */
 } mk_status;
 
@@ -328,7 +328,7 @@ mk_status mk_tail_history(mk_plan_t plan, float* out, int on_device);
  * extrapolation of the last two iterates of each parity (needs an even
  * k >= 4); 2: no estimate (exactly two more passes of the plain series).
  * rel_resid: host double [nf] receiving ||rho|| / ||G_d|| per focal point
- * (the judge's verdict), or NULL.  Synchronises.
+ * (the restart step's verdict on the estimate), or NULL.  Synchronises.
  * Errors: MK_ERR_ARG (mode), MK_ERR_STATE (not exactly k recorded passes
  * since mk_set_focal, already applied, no network for mode 0), MK_ERR_HIP.
  */

@@ -9,7 +9,7 @@ focal point are convolved in time and integrated over the surface positions,
 which gives ``G^{-,+}(x_F, x_F, t)``; its zero-time sample is the local
 reflectivity at ``x_F``, the image.
 
-Readings (listed in the design notes of the repository):
+Readings where the paper is silent:
 
 * the integral over x and t is the Riemann sum with weight ``c = dx * dt``,
   the same discretisation as the synthesis of Eq. (1);

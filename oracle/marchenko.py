@@ -19,8 +19,7 @@ What it follows (arXiv 2106.04649):
 * Theory section: ``G^+`` needs one extra synthesis (Marchenko relations of
   the cited Wapenaar et al. 2014 work): ``G^+(t) = f1plus(-t) - S[f1min(-t)]``.
 
-Readings of the paper where it is silent or ambiguous (all listed in the
-design notes of the repository):
+Readings of the paper where it is silent or ambiguous:
 
 * the time axis is periodic with ``nt`` samples (circular convolution, FFT
   length ``nt``); time reversal maps sample ``k`` to ``(nt - k) mod nt``;
