@@ -450,7 +450,7 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     // so that they are in flight together (a skipped tile wastes them)
     const int L = itd[tr] - shift;
     const float se = scale[tr];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int i16 = lane & 15, g = lane >> 4;
     const float* B1 = P + kFH * k * kTaps;
     const float* B2 = B1 + kFH + kFH * kFH * kTaps;
@@ -514,6 +514,13 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     // window samples u = t + T/2 with |t| < L
     if (L <= 0 || t0 >= hT + L || t0 + kFT <= hT - L + 1) return;
     const float inv = se > 0.f ? 1.f / se : 0.f;
+    // output samples s = u - t0 of this tile the tail is used at: [lo3, hi3]
+    // (not empty: the window test passed); layer 2 is needed on [lo3, hi3 + 64]
+    // and layer 1 on [lo3, hi3 + 80] of their own spans.  A 16-sample tile of
+    // a layer outside its range is not computed: only outputs that are never
+    // used would read it.
+    const int lo3 = max(hT - L + 1 - t0, 0), hi3 = min(hT + L - 1 - t0, kFT - 1);
+    auto needed = [&](int tile, int hi) { return 16 * tile + 15 >= lo3 && 16 * tile <= hi; };
     bool upd[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -569,21 +576,28 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     };
 
     // layer 1: 21 tiles; layer 2: 20 tiles (x is dead: a2 takes its place)
-    hidden_layer(std::integral_constant<int, KP>{}, std::integral_constant<int, 1>{},
-                 std::integral_constant<int, XP>{}, std::integral_constant<int, 5>{}, xs, w1, bias1, a1s, wv, 4,
-                 t0 - kA10);
-    if (wv == 0)
-        hidden_layer(std::integral_constant<int, KP>{}, std::integral_constant<int, 1>{},
-                     std::integral_constant<int, XP>{}, std::integral_constant<int, 1>{}, xs, w1, bias1, a1s, 20, 0,
-                     t0 - kA10);
+    // (one 16-sample tile at a time, each only where it is needed)
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const int tile = wv + 4 * m;
+        if (tile < kA1N / 16 && needed(tile, hi3 + 80))
+            hidden_layer(std::integral_constant<int, KP>{}, std::integral_constant<int, 1>{},
+                         std::integral_constant<int, XP>{}, std::integral_constant<int, 1>{}, xs, w1, bias1, a1s, tile,
+                         0, t0 - kA10);
+    }
     __syncthreads();
     _Float16* a2s = u2;
     h8 w2[S2];
 #pragma unroll
     for (int m = 0; m < S2; ++m) w2[m] = wpk[(S1 + m) * 64 + lane];
-    hidden_layer(std::integral_constant<int, kFH>{}, std::integral_constant<int, 4>{},
-                 std::integral_constant<int, kHP>{}, std::integral_constant<int, 5>{}, a1s, w2, bias2, a2s, wv, 4,
-                 t0 - kA20);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+        const int tile = wv + 4 * m;
+        if (needed(tile, hi3 + 64))
+            hidden_layer(std::integral_constant<int, kFH>{}, std::integral_constant<int, 4>{},
+                         std::integral_constant<int, kHP>{}, std::integral_constant<int, 1>{}, a1s, w2, bias2, a2s,
+                         tile, 0, t0 - kA20);
+    }
     __syncthreads();
 
     // layer 3 (rows 0 and 1 of a padded 16-row product) and the tail:
@@ -591,23 +605,17 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     h8 w3[S2];
 #pragma unroll
     for (int m = 0; m < S2; ++m) w3[m] = wpk[(S1 + S2 + m) * 64 + lane];
-    h8 b3[4][S2];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int q = 0; q < S2; ++q) b3[m][q] = acts_b<kFH, 16, kHP>(a2s, 16 * (wv + 4 * m) + i16, g, q);
-    v4f y[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) y[m] = bias3;
-#pragma unroll
-    for (int q = 0; q < S2; ++q)
-#pragma unroll
-        for (int m = 0; m < 4; ++m) y[m] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[q], b3[m][q], y[m], 0, 0, 0);
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
+        if (!needed(wv + 4 * m, hi3)) continue;
+        v4f y = bias3;
+#pragma unroll
+        for (int q = 0; q < S2; ++q)
+            y = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[q], acts_b<kFH, 16, kHP>(a2s, 16 * (wv + 4 * m) + i16, g, q),
+                                                       y, 0, 0, 0);
         if (g == 0 && upd[m]) {
-            fp[f1_ip(m)] = pv[m] + se * y[m][1];
-            fm[f1_im(m)] = mv[m] - se * y[m][0];
+            fp[f1_ip(m)] = pv[m] + se * y[1];
+            fm[f1_im(m)] = mv[m] - se * y[0];
         }
     }
 }
