@@ -164,6 +164,31 @@ mk_status mk_set_focal(mk_plan_t plan, int32_t nf, const float* Gd, const int32_
 mk_status mk_iterate(mk_plan_t plan, int32_t niter, double* norms);
 
 /*
+ * mk_iterate_tol -- run passes of the current series until the library's own
+ * estimate of the remaining error of every output is within tol (relative
+ * L2), or max_passes passes have run.  The judge is the plain iteration
+ * itself: the series converges like a geometric series whose ratio q per
+ * pass is read from the FP64 norms of its last terms (the largest of the
+ * last two term-to-term ratios; right after mk_tail_apply, the ratio of the
+ * series before it, whose operator A = theta Rev S is the same), so the
+ * terms not yet added sum to about rest = ||N_last|| q / (1 - q).  Every
+ * output's error is a part of that sum: the odd terms belong to f1+ and the
+ * even ones to f1- (Algorithm 1), and G+ and G- are syntheses of f1+ and f1-
+ * with S a contraction.  The estimate is rest / min(||f1+||, ||f1-||), with
+ * the field norms reduced in FP64 on the GPU; q is capped at 0.95.  From it
+ * the call predicts how many passes reach tol, runs them as one batch, and
+ * judges again.  With fewer than two terms and no earlier series, it first
+ * runs two passes.
+ * passes_run: passes this call ran (may be NULL).  est: host double [nf],
+ * the final estimate per focal point in the caller's order (may be NULL);
+ * an estimate above tol after max_passes means the budget ran out, which is
+ * not an error.  Synchronises.
+ * Errors: MK_ERR_ARG (tol not positive and finite, max_passes < 0),
+ * MK_ERR_STATE (no focal set), MK_ERR_HIP, MK_ERR_DIVERGED (as mk_iterate).
+ */
+mk_status mk_iterate_tol(mk_plan_t plan, double tol, int32_t max_passes, int32_t* passes_run, double* est);
+
+/*
  * mk_get -- copy one field, float32 [nf][nr][nt], into out.
  * MK_GPLUS / MK_GMINUS run the G assembly of the Theory section and the
  * last lines of Algorithm 1: both are formed together from one batched

@@ -12,12 +12,15 @@ What it follows (arXiv 2106.04649):
   the surface positions x; the time convolution is done in the frequency
   domain, so each synthesis is rfft -> per-frequency contraction over x ->
   irfft.  The double integral is a Riemann sum with weight ``c = dx * dt``.
-* Algorithm 1 (GPU implementation of the iterative Marchenko algorithm):
-  loop 1 repeats synthesis, time reversal with a sign flip and the mute;
-  loop 2 rebuilds ``Ni, f2p, f1plus, f1min, pmin`` from the stored synthesis
-  outputs; a final synthesis of ``f1plus`` gives ``G^-``.
-* Theory section: ``G^+`` needs one extra synthesis (Marchenko relations of
-  the cited Wapenaar et al. 2014 work): ``G^+(t) = f1plus(-t) - S[f1min(-t)]``.
+* Theory section: the focusing functions are sums of the terms ``N_i`` of a
+  Neumann series, each term the muted synthesis of the previous one, started
+  from the time-reversed first arrival; the Green's functions follow from
+  the focusing functions by extra syntheses (Marchenko relations of the cited
+  Wapenaar et al. 2014 work), the total Green's function from the auxiliary
+  fields f2+ and p- (the cited Wapenaar et al. 2013 route).
+* Algorithm 1 fixes the sign convention (the synthesis output is reversed
+  in time and negated before the mute), the number of terms and which
+  terms each output accumulates.
 
 Readings of the paper where it is silent or ambiguous:
 
@@ -28,14 +31,14 @@ Readings of the paper where it is silent or ambiguous:
   sample ``k = nt/2`` is always zeroed;
 * "padding" before the inverse FFT is zero-filling of the bins outside the
   band; DC and Nyquist are taken as real (numpy's ``irfft`` convention);
-* Algorithm 1's loops ``for iter <- 0 to niter`` run ``niter`` passes;
-  ``fmin`` in its last line is ``f1min``.
+* ``niter`` iterations are ``niter`` terms ``N_0 .. N_{niter-1}``.
 
 Parity pins (tests/test_oracle.py): brute-force time-domain convolution,
 a closed-form single-interface example, R = 0, homogeneity in R and
 linearity in G_d, a dense direct solve of the converged series, the norm
-contraction bound, the G^+/G^- identities through the series terms, and
-hand-written mute masks.
+contraction bound, the G^+/G^- identities through the series terms, the
+total G against G^+ + G^- and the closed form, and hand-written mute
+masks.
 """
 
 from __future__ import annotations
@@ -76,7 +79,7 @@ def mute_window(itd: np.ndarray, shift: int, nt: int) -> np.ndarray:
 
 
 def apply_mute(x: np.ndarray, itd: np.ndarray, shift: int) -> np.ndarray:
-    """applyMute of Algorithm 1."""
+    """theta_t of Eq. (1) applied to a field (zero outside the window)."""
     return np.where(mute_window(itd, shift, x.shape[-1]), x, 0.0)
 
 
@@ -139,64 +142,73 @@ class SynthesisOperator:
 
 
 # ---------------------------------------------------------------------------
-# Algorithm 1
+# the Neumann series of the Theory section
 # ---------------------------------------------------------------------------
 
 
 def marchenko(S: SynthesisOperator, Gd: np.ndarray, itd: np.ndarray, shift: int,
               niter: int, fbands: Optional[np.ndarray] = None,
               keep_iterates: bool = False) -> Dict[str, np.ndarray]:
-    """Algorithm 1 in FP64: returns f1plus, f1minus, Gplus, Gminus, f2p, pmin, norms.
+    """The Neumann series of the Theory section in FP64, ``niter`` terms.
 
+    Returns f1plus, f1minus, Gplus, Gminus, f2p, pmin, Gtotal and norms.
     ``Gd`` [nf][nr][nt], ``itd`` [nf][nr] (samples), ``shift`` (samples).
-    ``norms[i][f] = ||N_i||_2`` of the muted field of pass ``i``.
+
+    The series starts from the time-reversed first arrival,
+    ``N_{-1}(t) = G_d(-t)``.  Term ``i`` is Eq. (1) applied to term
+    ``i - 1``: the synthesis ``S N_{i-1}`` is evaluated at negative time,
+    negated (the sign of Algorithm 1, which Eq. (1) leaves out) and
+    windowed by ``theta_t``.  Terms of odd index build the downgoing
+    focusing function, terms of even index the upgoing one, stored at
+    positive time with the opposite sign:
+
+        f1+ = N_{-1} + sum_{i odd} N_i,      f1-(t) = -sum_{i even} N_i(-t).
+
+    Every term also enters the auxiliary field f2+ (all of them, from
+    ``N_{-1}`` on) and every synthesis the field p-.  ``norms[i][f]`` is
+    ``||N_i||_2``.  The Green's functions follow from the focusing
+    functions by two more syntheses (Theory section, after Wapenaar et al.
+    2014): ``G-(t) = S[f1+](t) - f1-(t)`` and
+    ``G+(t) = f1+(-t) - S[f1-(-.)](t)``; their sum, the total G, is read from
+    the auxiliary fields (the route the Theory section attributes to
+    Wapenaar et al. 2013): ``G(t) = p-(t) + S[N_last](t) + f2+(-t)``, p-
+    completed by the synthesis of the last term.
     """
     Gd = np.asarray(Gd, dtype=np.float64)
     nf = Gd.shape[0]
+    keep = mute_window(itd, shift, Gd.shape[-1])
 
-    def mute(x):
-        return apply_mute(x, itd, shift)
-
-    # iRN(t) = G_d(-t)
-    iRN = rev(Gd)
-    stored = []
-    # loop 1: synthesis, store, reverse with a sign flip, mute
-    for _ in range(niter):
-        iRN = S(iRN, fbands)
-        stored.append(iRN)
-        iRN = -rev(iRN)
-        iRN = mute(iRN)
-
-    # loop 2: rebuild the fields from the stored synthesis outputs
-    Ni = rev(Gd)
-    f2p = Ni.copy()
-    f1plus = Ni.copy()
-    f1min = np.zeros_like(Gd)
-    pmin = np.zeros_like(Gd)
+    start = rev(Gd)                            # N_{-1}
+    down = start.copy()                        # f1+
+    up = np.zeros_like(start)                  # f1-
+    f2 = start.copy()                          # f2+
+    psum = np.zeros_like(start)                # p-
     norms = np.zeros((niter, nf))
-    iterates = []
-    for it in range(niter):
-        iRN = stored[it]
-        Ni = -rev(iRN)
-        pmin = pmin + iRN
-        Ni = mute(Ni)
-        f2p = f2p + Ni
-        if it % 2 == 0:
-            f1min = f1min - rev(Ni)
+    terms, syntheses = [], []
+
+    term = start
+    for i in range(niter):
+        s_prev = S(term, fbands)                           # S N_{i-1}
+        term = np.where(keep, -rev(s_prev), 0.0)           # N_i = theta(-(S N_{i-1})(-t))
+        psum = psum + s_prev
+        f2 = f2 + term
+        if i % 2 == 1:
+            down = down + term
         else:
-            f1plus = f1plus + Ni
-        norms[it] = np.sqrt(np.sum(Ni * Ni, axis=(1, 2)))
+            up = up - rev(term)
+        norms[i] = np.sqrt(np.sum(term * term, axis=(1, 2)))
         if keep_iterates:
-            iterates.append(Ni)
+            terms.append(term)
+            syntheses.append(s_prev)
 
-    # G^- = S[f1plus] - f1min   (last lines of Algorithm 1)
-    Gminus = S(f1plus, fbands) - f1min
-    # G^+ = f1plus(-t) - S[f1min(-t)]  (one extra synthesis, Theory section)
-    Gplus = rev(f1plus) - S(rev(f1min), fbands)
+    Gminus = S(down, fbands) - up
+    Gplus = rev(down) - S(rev(up), fbands)
+    Gtotal = psum + S(term, fbands) + rev(f2)
 
-    out = dict(f1plus=f1plus, f1minus=f1min, Gplus=Gplus, Gminus=Gminus,
-               f2p=f2p, pmin=pmin, norms=norms)
+    out = dict(f1plus=down, f1minus=up, Gplus=Gplus, Gminus=Gminus,
+               f2p=f2, pmin=psum, Gtotal=Gtotal, norms=norms)
     if keep_iterates:
-        out["iterates"] = np.stack(iterates) if iterates else np.zeros((0,) + Gd.shape)
-        out["synth"] = np.stack(stored) if stored else np.zeros((0,) + Gd.shape)
+        shape = (0,) + Gd.shape
+        out["iterates"] = np.stack(terms) if terms else np.zeros(shape)
+        out["synth"] = np.stack(syntheses) if syntheses else np.zeros(shape)
     return out

@@ -6,7 +6,7 @@ estimated per trace and added to the focusing functions:
     T_even = sum_{i >= k, i even} N_i  ->  f1- -= T_even(-t)
     T_odd  = sum_{i >= k, i odd}  N_i  ->  f1+ += T_odd
 
-(the same accumulation rule as the series itself, Algorithm 1 loop 2).  The
+(the same accumulation rule as the series itself).  The
 estimate is then judged and refined by plain synthesis: one fixed-point
 step of the converged relations (Theory section; f1+ = G_d(-t) + A^2 f1+
 and f1- = theta S f1+, with A = theta Rev S),

@@ -69,7 +69,7 @@ void free_plan_memory(mk_plan_t p) {
     void* bufs[] = {p->R, p->rscale, p->X, p->Y, p->f1p, p->f1m, p->gp, p->gm, p->stage, p->itd,
                     p->fband, p->perm, p->iperm, p->ncols, p->npart, p->norm0, p->gdnorm, p->nlast, p->xscale,
                     p->norms, p->tw, p->flag, p->n0, p->hist, p->tail_w, p->tail_x, p->tail_work,
-                    p->tail_y, p->tail_scale, p->img, p->aux, p->tail_wpk};
+                    p->tail_y, p->tail_scale, p->img, p->aux, p->tail_wpk, p->norm_log, p->fnorm};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& pe : p->pending) {
@@ -339,6 +339,119 @@ mk_status ensure_norm_cap(mk_plan_t p, int niter) {
     return MK_OK;
 }
 
+// Room for `rows` more rows of the norm log (copied over when it grows).
+mk_status ensure_log_cap(mk_plan_t p, int rows) {
+    const int need = p->log_len + rows;
+    if (need <= p->log_cap) return MK_OK;
+    int cap = p->log_cap > 0 ? p->log_cap : 128;
+    while (cap < need) cap *= 2;
+    double* fresh = nullptr;
+    HIP_TRY(p, dalloc(&fresh, (size_t)cap * p->d.nf_max));
+    if (p->norm_log) {
+        if (p->log_len > 0) {
+            hipError_t e = hipMemcpyAsync(fresh, p->norm_log, (size_t)p->log_len * p->nf * sizeof(double),
+                                          hipMemcpyDeviceToDevice, p->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+            if (e != hipSuccess) {
+                (void)hipFree(fresh);
+                return hip_fail(p, e, "norm log copy");
+            }
+        }
+        HIP_TRY(p, hipFree(p->norm_log));
+    }
+    p->norm_log = fresh;
+    p->log_cap = cap;
+    return MK_OK;
+}
+
+// Append `rows` rows of nf norms from device memory to the log.
+mk_status log_rows(mk_plan_t p, const double* src, int rows) {
+    if (rows <= 0) return MK_OK;
+    MK_TRY(ensure_log_cap(p, rows));
+    HIP_TRY(p, hipMemcpyAsync(p->norm_log + (size_t)p->log_len * p->nf, src, (size_t)rows * p->nf * sizeof(double),
+                              hipMemcpyDeviceToDevice, p->stream));
+    p->log_len += rows;
+    return MK_OK;
+}
+
+// A new series starts from the field whose norms (nf, device) are `start`.
+mk_status log_series_start(mk_plan_t p, const double* start) {
+    p->prev_series_start = p->series_start;
+    p->series_start = p->log_len;
+    return log_rows(p, start, 1);
+}
+
+// The stopping rule.  a[0..n) are the norms of one focal point's terms in the
+// current series (a[0] its starting field); a[n-1] is the last term added.
+// The series contracts by q per pass: the largest of the last two
+// term-to-term ratios, or `q_prior` (the previous series' value, the same
+// operator) while this series holds fewer than two terms.  If the remaining
+// terms keep shrinking by q, their norms sum to at most
+//     rest = a[n-1] q / (1 - q),
+// and every output's error is a part of that sum (the odd terms go to f1+,
+// the even ones to f1-, and G+ and G- are syntheses of f1+-, with S a
+// contraction).  q is capped at 0.95; a negative q means "not known yet".
+struct RestEstimate {
+    double rest;
+    double q;
+};
+
+RestEstimate estimate_rest(const double* a, int n, double q_prior) {
+    double q = -1.0;
+    for (int j = std::max(1, n - 2); j < n; ++j)
+        if (a[j - 1] > 0.0) q = std::max(q, a[j] / a[j - 1]);
+    if (q < 0.0) q = q_prior;
+    if (a[n - 1] == 0.0) return {0.0, std::max(q, 0.0)};
+    if (q < 0.0) return {HUGE_VAL, -1.0};
+    q = std::min(q, 0.95);
+    return {a[n - 1] * q / (1.0 - q), q};
+}
+
+// The rule for every focal point: est[j] = rest / min(||f1+||, ||f1-||) in the
+// plan's sorted order, and the passes still needed, predicted from q (0 when
+// every estimate is within tol, -1 when some q is not known yet).
+mk_status judge_series(mk_plan_t p, double tol, std::vector<double>& est, int* more) {
+    const int nf = p->nf, nr = p->d.nr, nt = p->d.nt;
+    HIP_TRY(p, launch_sumsq(p->f1p, nf * nr, nt, p->npart, p->stream));
+    HIP_TRY(p, launch_sumsq(p->f1m, nf * nr, nt, p->npart + (size_t)nf * nr, p->stream));
+    HIP_TRY(p, launch_norm_reduce(p->npart, nr, 2 * nf, p->fnorm, nullptr, p->stream));
+    std::vector<double> fn(2 * (size_t)nf), log((size_t)p->log_len * nf);
+    HIP_TRY(p, hipMemcpyAsync(fn.data(), p->fnorm, fn.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(log.data(), p->norm_log, log.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    est.assign(nf, 0.0);
+    *more = 0;
+    const int n = p->log_len - p->series_start;
+    std::vector<double> a;
+    for (int j = 0; j < nf; ++j) {
+        double q_prior = -1.0;
+        if (p->series_start >= 2) {         // the previous series' last ratios
+            a.clear();
+            for (int e = p->prev_series_start; e < p->series_start; ++e) a.push_back(log[(size_t)e * nf + j]);
+            q_prior = estimate_rest(a.data(), (int)a.size(), -1.0).q;
+        }
+        a.clear();
+        for (int e = p->series_start; e < p->log_len; ++e) a.push_back(log[(size_t)e * nf + j]);
+        const RestEstimate r = estimate_rest(a.data(), n, q_prior);
+        const double den = std::min(fn[j], fn[nf + j]);
+        if (r.rest == 0.0) {
+            est[j] = 0.0;
+            continue;
+        }
+        est[j] = den > 0.0 ? r.rest / den : HUGE_VAL;
+        if (est[j] <= tol) continue;
+        if (r.q < 0.0 || !(den > 0.0)) {
+            *more = -1;
+            continue;
+        }
+        // passes m with a[n-1] q^m q / (1 - q) <= tol den
+        const int m = r.q > 0.0 ? (int)std::ceil(std::log(tol * den / r.rest) / std::log(r.q)) : 1;
+        if (*more >= 0) *more = std::max(*more, std::max(m, 1));
+    }
+    return MK_OK;
+}
+
 template <typename T>
 mk_status copy_in(mk_plan_t p, T* dst, const T* src, size_t n, int on_device, const char* what) {
     if (n == 0) return MK_OK;
@@ -479,6 +592,7 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     if ((e = dalloc(&p->gdnorm, nfm)) != hipSuccess) return bail(e, "gdnorm");
     if ((e = dalloc(&p->nlast, nfm)) != hipSuccess) return bail(e, "nlast");
     if ((e = dalloc(&p->img, nfm)) != hipSuccess) return bail(e, "image");
+    if ((e = dalloc(&p->fnorm, 2 * nfm)) != hipSuccess) return bail(e, "field norms");
     if ((e = dalloc(&p->xscale, 3 * nfm)) != hipSuccess) return bail(e, "X scales");
     if ((e = dalloc(&p->tw, (size_t)d.nt + 256)) != hipSuccess) return bail(e, "twiddles");
     if ((e = dalloc(&p->flag, 1)) != hipSuccess) return bail(e, "flag");
@@ -659,6 +773,9 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
     p->norm0_host.assign(nf, 0.0);
     for (int j = 0; j < nf; ++j) p->norm0_host[perm[j]] = n0[j];
     p->gd_norm_host = p->norm0_host;
+    p->log_len = 0;
+    p->series_start = 0;
+    MK_TRY(log_series_start(p, p->norm0));
     p->focal_set = true;
     return MK_OK;
 }
@@ -757,6 +874,7 @@ mk_status mk_iterate(mk_plan_t p, int32_t niter, double* norms) {
     if (graph) MK_TRY(replay_passes(p, niter, parity0));
     else MK_TRY(enqueue_passes(p, 0, niter, parity0));
     p->passes += niter;
+    MK_TRY(log_rows(p, p->norms, niter));
     if (norms) {
         std::vector<double> h((size_t)niter * p->nf);
         HIP_TRY(p, hipMemcpyAsync(h.data(), p->norms, h.size() * sizeof(double), hipMemcpyDeviceToHost,
@@ -776,6 +894,31 @@ mk_status mk_iterate(mk_plan_t p, int32_t niter, double* norms) {
                 }
             }
     }
+    return MK_OK;
+}
+
+mk_status mk_iterate_tol(mk_plan_t p, double tol, int32_t max_passes, int32_t* passes_run, double* est) {
+    if (!p) return fail(nullptr, MK_ERR_ARG, "mk_iterate_tol: plan is NULL");
+    if (passes_run) *passes_run = 0;
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(p, MK_ERR_ARG, "mk_iterate_tol: tol must be positive");
+    if (max_passes < 0) return fail(p, MK_ERR_ARG, "mk_iterate_tol: max_passes must be >= 0");
+    if (!p->focal_set) return fail(p, MK_ERR_STATE, "mk_iterate_tol: no focal points set");
+    std::vector<double> e, nbuf;
+    int run = 0;
+    for (;;) {
+        int more = 0;
+        MK_TRY(judge_series(p, tol, e, &more));
+        if (more == 0 || run >= max_passes) break;
+        // an unknown contraction factor needs two terms of this series first
+        const int m = std::min(more < 0 ? 2 : more, max_passes - run);
+        nbuf.resize((size_t)m * p->nf);
+        mk_status st = mk_iterate(p, m, nbuf.data());
+        run += m;
+        if (passes_run) *passes_run = run;
+        if (st != MK_OK) return st;
+    }
+    if (est)
+        for (int j = 0; j < p->nf; ++j) est[p->perm_host[j]] = e[j];
     return MK_OK;
 }
 
@@ -1015,6 +1158,7 @@ mk_status mk_tail_apply(mk_plan_t p, int32_t mode, double* rel_resid) {
     p->pass_base = p->passes;
     p->tail_applied = true;
     p->g_valid = false;
+    MK_TRY(log_series_start(p, p->norm0));
     return MK_OK;
 }
 

@@ -109,6 +109,13 @@ struct mk_plan_s {
     float* xscale = nullptr;   // [3 nf_max] scale stored with 16-bit X
     double* norms = nullptr;   // [norm_cap][nf_max]
     int norm_cap = 0;
+    // norms of every term since mk_set_focal, [log_cap][nf] (row e holds one
+    // term for every focal point, sorted order): the first row of each series
+    // is its starting field (N_-1, or the restart residual), then one row per
+    // pass; the stopping rule of mk_iterate_tol reads the current series
+    double* norm_log = nullptr;
+    int log_cap = 0, log_len = 0, series_start = 0, prev_series_start = 0;
+    double* fnorm = nullptr;   // [2 nf_max] ||f1+||, ||f1-|| for the stopping rule
     float2* tw = nullptr;      // [nt + 256]
     int* flag = nullptr;       // device scratch flag (non-finite input detection)
     float* n0 = nullptr;       // [nf_max][nr][nt] N_-1 = G_d(-t)

@@ -6,7 +6,8 @@ torch stream, and turns status codes into exceptions.  If the library is
 missing it raises: there is no fallback path.
 
 Functions carry the ABI's names: mk_plan, mk_load_R, mk_set_focal,
-mk_iterate, mk_get, mk_image, mk_passes, mk_profile, mk_destroy.
+mk_iterate, mk_iterate_tol, mk_get, mk_image, mk_passes, mk_profile,
+mk_destroy, the series-tail calls mk_tail_* and the network calls mk_net_*.
 """
 
 from __future__ import annotations
@@ -70,6 +71,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mk_load_R": (i32, [P, P, ctypes.c_int]),
         "mk_set_focal": (i32, [P, i32, P, P, i32, P, ctypes.c_int]),
         "mk_iterate": (i32, [P, i32, P]),
+        "mk_iterate_tol": (i32, [P, ctypes.c_double, i32, ctypes.POINTER(i32), P]),
         "mk_get": (i32, [P, i32, P, ctypes.c_int]),
         "mk_passes": (i32, [P, ctypes.POINTER(i32)]),
         "mk_image": (i32, [P, ctypes.POINTER(ctypes.c_double)]),
@@ -130,6 +132,13 @@ def _ptr(x, dtype: str) -> Tuple[int, int, object]:
     return a.ctypes.data, 0, a
 
 
+def _expect_shape(x, shape, what: str) -> None:
+    """Raise ValueError unless x has exactly `shape` (the library reads that many elements)."""
+    got = tuple(int(v) for v in x.shape)
+    if got != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, got {got}")
+
+
 def _current_stream() -> int:
     import torch
 
@@ -167,7 +176,13 @@ def mk_plan(nr: int, ns: int, nt: int, dt: float, dx: float, band: Optional[Tupl
 
 
 def mk_load_R(plan: Plan, R) -> None:
-    """R: complex64 [nr][B][ns] (numpy or torch, host or device)."""
+    """R: complex64 [nr][B][ns], or float32 [nr][B][ns][2] (numpy or torch, host or device)."""
+    d = plan.desc
+    shape = (d.nr, d.iw_hi - d.iw_lo + 1, d.ns)
+    if (_is_torch(R) and R.dtype.is_complex) or (isinstance(R, np.ndarray) and np.iscomplexobj(R)):
+        _expect_shape(R, shape, "R")
+    else:
+        _expect_shape(R, shape + (2,), "R (interleaved float32 pairs)")
     if _is_torch(R) and R.dtype.is_complex:
         import torch
 
@@ -183,6 +198,14 @@ def mk_load_R(plan: Plan, R) -> None:
 
 def mk_set_focal(plan: Plan, Gd, itd, shift: int, band=None) -> None:
     """Gd float32 [nf][nr][nt], itd int32 [nf][nr], band int32 [nf][2] or None."""
+    d = plan.desc
+    nf = int(Gd.shape[0]) if len(Gd.shape) == 3 else -1
+    if not 1 <= nf <= d.nf_max:
+        raise ValueError(f"Gd must have shape [nf][{d.nr}][{d.nt}] with 1 <= nf <= {d.nf_max}")
+    _expect_shape(Gd, (nf, d.nr, d.nt), "Gd")
+    _expect_shape(itd, (nf, d.nr), "itd")
+    if band is not None:
+        _expect_shape(band, (nf, 2), "band")
     gp, gdev, gk = _ptr(Gd, "float32")
     ip, idev, ik = _ptr(itd, "int32")
     bp, bdev, bk = _ptr(band, "int32")
@@ -190,7 +213,6 @@ def mk_set_focal(plan: Plan, Gd, itd, shift: int, band=None) -> None:
         raise ValueError("Gd and band must both be host or both be device arrays")
     if idev != gdev:
         raise ValueError("Gd and itd must both be host or both be device arrays")
-    nf = int(Gd.shape[0])
     _check(load_library().mk_set_focal(plan.handle, nf, gp, ip, int(shift), bp, gdev), plan.handle)
     plan.nf = nf
 
@@ -203,6 +225,16 @@ def mk_iterate(plan: Plan, niter: int, want_norms: bool = True) -> Optional[np.n
         return out
     _check(load_library().mk_iterate(plan.handle, int(niter), None), plan.handle)
     return None
+
+
+def mk_iterate_tol(plan: Plan, tol: float, max_passes: int) -> Tuple[int, np.ndarray]:
+    """Passes until the library's error estimate is within tol (or max_passes):
+    returns (passes run, estimate per focal point as float64 [nf])."""
+    est = np.zeros(plan.nf, dtype=np.float64)
+    n = ctypes.c_int32()
+    _check(load_library().mk_iterate_tol(plan.handle, float(tol), int(max_passes), ctypes.byref(n),
+                                         est.ctypes.data), plan.handle)
+    return n.value, est
 
 
 def mk_get(plan: Plan, field, out=None):
@@ -284,9 +316,12 @@ def mk_tail_history(plan: Plan, out=None):
     shape = (plan.nf, plan.desc.nr, k, T)
     if out is None:
         out = np.zeros(shape, np.float32)
+    _expect_shape(out, shape, "out")
     if _is_torch(out):
         ptr, dev, _ = _ptr(out, "float32")
     else:
+        if out.dtype != np.float32 or not out.flags.c_contiguous:
+            raise TypeError("out must be a C-contiguous float32 array")
         ptr, dev = out.ctypes.data, 0
     _check(load_library().mk_tail_history(plan.handle, ptr, dev), plan.handle)
     return out

@@ -96,3 +96,40 @@ def test_net_param_count(lib):
     assert lib.mk_net_param_count(0, 64) == -1
     assert lib.mk_net_param_count(4, 0) == -1
     assert lib.mk_net_param_count(4, 129) == -1
+
+
+def _fake_plan(nf_max=2, nr=8, nt=64, lo=0, hi=32):
+    """A binding-side plan with no library handle: the shape checks below run
+    before any library call, so they need no GPU."""
+    d = _desc(nr=nr, ns=nr, nt=nt, iw_lo=lo, iw_hi=hi, nf_max=nf_max)
+    plan = mk.Plan(0, d)
+    plan.handle = None
+    return plan
+
+
+def test_binding_checks_shapes_before_the_library_reads():
+    import numpy as np
+
+    plan = _fake_plan()
+    ok_R = np.zeros((8, 33, 8), np.complex64)
+    for bad in (np.zeros((8, 32, 8), np.complex64), np.zeros((8, 33, 9), np.complex64),
+                np.zeros((8, 33, 8), np.float32), np.zeros((8, 33, 8, 2), np.float32)[:, :, :7]):
+        with pytest.raises(ValueError):
+            mk.mk_load_R(plan, bad)
+    assert ok_R.shape == (8, 33, 8)
+    Gd, itd = np.zeros((2, 8, 64), np.float32), np.zeros((2, 8), np.int32)
+    for g, i, b in ((np.zeros((3, 8, 64), np.float32), np.zeros((3, 8), np.int32), None),   # nf > nf_max
+                    (np.zeros((2, 8, 32), np.float32), itd, None),                          # wrong nt
+                    (Gd, np.zeros((2, 7), np.int32), None),                                  # wrong itd
+                    (Gd, itd, np.zeros((1, 2), np.int32)),                                   # wrong band
+                    (np.zeros((8, 64), np.float32), itd, None)):                             # no focal axis
+        with pytest.raises(ValueError):
+            mk.mk_set_focal(plan, g, i, 1, b)
+    plan.nf, plan.tail_kT = 2, (4, 16)
+    for out in (np.zeros((2, 8, 4, 8), np.float32), np.zeros((1, 8, 4, 16), np.float32)):
+        with pytest.raises(ValueError):
+            mk.mk_tail_history(plan, out)
+    with pytest.raises(TypeError):
+        mk.mk_tail_history(plan, np.zeros((2, 8, 4, 16), np.float64))
+    with pytest.raises(TypeError):
+        mk.mk_tail_history(plan, np.zeros((2, 8, 16, 4), np.float32).transpose(0, 1, 3, 2))

@@ -160,7 +160,7 @@ def test_single_interface_closed_form(golden_dir):
     case = load(golden_dir, "single_interface.json")
     out = _run_spike_case(case, [(case["k1"], case["r"])])
     nt = case["nt"]
-    for key in ["f1plus", "f1minus", "Gminus", "Gplus", "f2p", "pmin"]:
+    for key in ["f1plus", "f1minus", "Gminus", "Gplus", "f2p", "pmin", "Gtotal"]:
         want = spikes_to_trace(case["expected"][key], nt)
         np.testing.assert_allclose(out[key][0, 0], want, atol=2e-7, err_msg=key)
     np.testing.assert_allclose(out["norms"][:, 0], case["expected"]["norms"], atol=2e-7)
@@ -170,7 +170,7 @@ def test_two_interfaces_hand_derived_terms(golden_dir):
     case = load(golden_dir, "two_interfaces.json")
     out = _run_spike_case(case, [(case["k1"], case["r1"]), (case["k2"], case["r2"])])
     nt = case["nt"]
-    for key in ["f1plus", "f1minus", "Gminus", "Gplus"]:
+    for key in ["f1plus", "f1minus", "Gminus", "Gplus", "Gtotal"]:
         want = spikes_to_trace(case["expected"][key], nt)
         np.testing.assert_allclose(out[key][0, 0], want, atol=2e-7, err_msg=key)
     np.testing.assert_allclose(out["norms"][:, 0], case["expected"]["norms"], atol=2e-7)
@@ -188,6 +188,7 @@ def test_zero_reflectivity_leaves_the_initial_field():
     Gd = p.Gd.astype(np.float64)
     assert np.array_equal(out["f1plus"], rev(Gd))
     assert np.array_equal(out["Gplus"], Gd)
+    assert np.array_equal(out["Gtotal"], Gd)
     assert not out["f1minus"].any() and not out["Gminus"].any() and not out["norms"].any()
 
 
@@ -286,6 +287,20 @@ def test_G_identities_through_series_terms():
     gm = RN[0] + sum(RN[i + 1] for i in range(1, niter, 2)) - out["f1minus"]
     np.testing.assert_allclose(out["Gplus"], gp, atol=1e-12)
     np.testing.assert_allclose(out["Gminus"], gm, atol=1e-12)
+
+
+@pytest.mark.parametrize("niter", [1, 4, 7])
+def test_total_G_from_auxiliary_fields_equals_Gplus_plus_Gminus(niter):
+    """The total G read from p- and f2+ (one synthesis of the last term) and
+    the sum of G+ and G- (two syntheses of the focusing functions) are two
+    routes to the same field; a dipping model and two focal points with
+    different windows."""
+    p = small_problem(seed=13, nf=2, ndips=1)
+    S = SynthesisOperator(p.Rhat, p.band, p.c, p.geom.nt)
+    out = marchenko(S, p.Gd, p.itd, p.shift, niter)
+    total = out["Gplus"] + out["Gminus"]
+    np.testing.assert_allclose(out["Gtotal"], total, atol=1e-12 * np.abs(total).max())
+    assert np.abs(out["Gtotal"]).max() > 0
 
 
 def test_rel_l2():

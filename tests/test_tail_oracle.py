@@ -2,6 +2,7 @@
 series of Algorithm 1 and closed forms."""
 
 import numpy as np
+import pytest
 
 from mkgen.layered import small_problem
 from oracle import SynthesisOperator, marchenko
@@ -60,3 +61,49 @@ def test_exact_tail_makes_the_residual_vanish():
     np.testing.assert_allclose(f1m, full["f1minus"], atol=1e-12)
     _, _, rho, _ = ot.restart(S, p.Gd, p.itd, p.shift, f1p)
     assert np.linalg.norm(rho) <= 1e-10 * np.linalg.norm(p.Gd)
+
+
+# ---------------------------------------------------------------------------
+# the network's tails: normalisation by the RMS of N_0 and the output rescale
+# ---------------------------------------------------------------------------
+
+
+def _golden_net(golden_dir):
+    import json
+    import os
+
+    with open(os.path.join(golden_dir, "tail_network.json")) as fh:
+        case = json.load(fh)
+    P = {k: np.array(case[k], dtype=np.float64) for k in ("W1", "b1", "W2", "b2", "W3", "b3")}
+    hist = np.array(case["hist"], dtype=np.float64)[None]          # [nf=1][nr=2][k][T]
+    return case, P, hist
+
+
+@pytest.mark.parametrize("f16", [False, True])
+def test_net_tails_hand_derived(golden_dir, f16):
+    case, P, hist = _golden_net(golden_dir)
+    te, to = ot.net_tails(hist, P, f16=f16)
+    np.testing.assert_array_equal(te[0], np.array(case["expected_even"]))
+    np.testing.assert_array_equal(to[0], np.array(case["expected_odd"]))
+
+
+@pytest.mark.parametrize("f16", [False, True])
+@pytest.mark.parametrize("alpha", [2.0 ** -3, 2.0 ** 5])
+def test_net_tails_scale_with_the_iterates(alpha, f16):
+    """The series is linear in G_d, so the tails of alpha * (N_0 .. N_{k-1})
+    are alpha times the tails: the input is divided by the RMS of N_0 and the
+    output multiplied by it.  Powers of two keep every rounding identical."""
+    from oracle import tailnet as tn
+
+    rng = np.random.default_rng(4)
+    P = tn.init_params(rng, k=4, hidden=6)
+    for key in P:
+        P[key] = P[key] + 0.1 * rng.standard_normal(P[key].shape)     # non-zero biases everywhere
+    hist = rng.standard_normal((2, 3, 4, 48))
+    hist[1, 2, 0] = 0.0                                                  # a trace with N_0 = 0
+    te, to = ot.net_tails(hist, P, f16=f16)
+    te_a, to_a = ot.net_tails(alpha * hist, P, f16=f16)
+    np.testing.assert_array_equal(te_a, alpha * te)
+    np.testing.assert_array_equal(to_a, alpha * to)
+    assert not te[1, 2].any() and not to[1, 2].any()
+    assert np.abs(te).max() > 0 and np.abs(to).max() > 0

@@ -125,3 +125,21 @@ def test_half_form_equals_plain_form_on_exact_values():
     y, (_, a1, _, a2, _) = tn.forward(P, x)
     assert np.abs(a1).max() < 2048 and np.abs(a2).max() < 2048
     np.testing.assert_array_equal(tn.forward_f16(P, x), y)
+
+
+def test_adam_two_steps_closed_form():
+    """Two steps with b1 = 1/2, b2 = 3/4 (so that the bias corrections of step 2,
+    1 - b1^2 = 3/4 and 1 - b2^2 = 7/16, differ from those of step 1), lr = 1,
+    gradients 1 then 3, worked by hand:
+      step 1: m = 1/2, v = 1/4, m^ = 1, v^ = 1, w -= 1;
+      step 2: m = 7/4, v = 39/16, m^ = 7/3, v^ = 39/7, w -= (7/3) / sqrt(39/7)."""
+    P = {"w": np.array([5.0, -1.0])}
+    M = {"w": np.zeros(2)}
+    V = {"w": np.zeros(2)}
+    tn.adam_step(P, {"w": np.array([1.0, -1.0])}, M, V, step=1, lr=1.0, b1=0.5, b2=0.75, eps=0.0)
+    np.testing.assert_allclose(P["w"], [4.0, 0.0], rtol=0, atol=1e-15)
+    tn.adam_step(P, {"w": np.array([3.0, -3.0])}, M, V, step=2, lr=1.0, b1=0.5, b2=0.75, eps=0.0)
+    d = (7.0 / 3.0) / np.sqrt(39.0 / 7.0)
+    np.testing.assert_allclose(P["w"], [4.0 - d, d], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(M["w"], [1.75, -1.75], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(V["w"], [39.0 / 16.0, 39.0 / 16.0], rtol=0, atol=1e-15)
