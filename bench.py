@@ -47,7 +47,7 @@ PEAK_TFLOPS = {0: 157.3, 1: 2500.0, 2: 2500.0}     # dense MFMA: fp32, fp16, bf1
 # for the kernel source it was measured on (sha256 prefix of the file).
 TRAFFIC = {
     "k_contract_c64": {"source": "paper_2106_04649_amd/csrc/k_contract.hip",
-                       "sha": "576a68ac9b5a34b2", "bytes": 3006353126,
+                       "sha": "d5d072ef9c5e4c8f", "bytes": 3006352864,
                        "profile": "profiles/k_contract_c64_601x601_nt2048_nf1.md"},
 }
 
@@ -109,6 +109,14 @@ def cpu_baseline(p, passes: int) -> dict:
     }
 
 
+def oracle_reference_banded(pb, sample, niter):
+    """The FP64 oracle's fields for sampled focal points with their bands."""
+    from oracle import SynthesisOperator, marchenko
+
+    S = SynthesisOperator(pb.Rhat, pb.band, pb.c, pb.geom.nt)
+    return marchenko(S, pb.Gd[sample], pb.itd[sample], pb.shift, niter, fbands=pb.fbands[sample])
+
+
 def oracle_reference(pb, sample, niter):
     """The FP64 oracle's fields for the sampled focal points of the batch (the
     accuracy reference of the batched and combined paths)."""
@@ -126,17 +134,22 @@ def oracle_reference(pb, sample, niter):
 class Runner:
     """One plan on one workload; times whole solves.
 
-    With `tail` = (params, k, T, mode, extra) a solve is: k recorded passes,
-    mk_tail_apply (series-tail estimate + the two judging syntheses), then
-    `extra` more passes of the residual series, then the G assembly.
+    A solve is mk_set_focal, the series, and the G+/G- assembly of mk_get.
+    The series is `niter` passes of mk_iterate, or, with `tol` set, passes
+    until the library's own stopping rule (mk_iterate_tol: FP64 norms of the
+    series' last terms, no outside reference) judges every output within
+    `tol`.  With `tail` = (params, k, T, mode) the series starts with k
+    recorded passes and mk_tail_apply (series-tail estimate + the two judging
+    syntheses of the restart) before the remaining passes.
     """
 
-    def __init__(self, p, rprec=0, flags=0, tune=None, niter=32, tail=None):
+    def __init__(self, p, rprec=0, flags=0, tune=None, niter=32, tail=None, tol=None, max_passes=32):
         import torch
 
         from paper_2106_04649_amd import mk
 
         self.mk, self.torch, self.p, self.niter = mk, torch, p, niter
+        self.tol, self.max_passes = tol, max_passes
         self.stream = torch.cuda.current_stream()
         nr, nt = p.Rhat.shape[0], p.geom.nt
         self.plan = mk.mk_plan(nr, nr, nt, p.geom.dt, p.geom.dx, band=p.band, nf_max=p.nf, rprec=rprec,
@@ -153,8 +166,9 @@ class Runner:
         self.out_p = torch.empty(p.Gd.shape, dtype=torch.float32, device="cuda")
         self.out_m = torch.empty_like(self.out_p)
         self.tail = tail
+        self.passes, self.est = None, None
         if tail is not None:
-            params, k, T, mode, extra = tail
+            params, k, T, mode = tail
             mk.mk_tail_record(self.plan, k, T)
             if params is not None:
                 mk.mk_tail_load(self.plan, params)
@@ -162,16 +176,21 @@ class Runner:
     def step(self):
         mk = self.mk
         mk.mk_set_focal(self.plan, self.Gd, self.itd, self.p.shift, self.fb)
-        if self.tail is None:
-            mk.mk_iterate(self.plan, self.niter, want_norms=False)
-        else:
-            _, k, _, mode, extra = self.tail
+        if self.tail is not None:
+            _, k, _, mode = self.tail
             mk.mk_iterate(self.plan, k, want_norms=False)
             self.resid = mk.mk_tail_apply(self.plan, mode)
-            if extra:
-                mk.mk_iterate(self.plan, extra, want_norms=False)
+        if self.tol is not None:
+            self.passes, self.est = mk.mk_iterate_tol(self.plan, self.tol, self.max_passes)
+        else:
+            mk.mk_iterate(self.plan, self.niter, want_norms=False)
         mk.mk_get(self.plan, "Gplus", self.out_p)
         mk.mk_get(self.plan, "Gminus", self.out_m)
+
+    def syntheses(self):
+        """Syntheses of one solve before the G assembly (a tail's restart costs two)."""
+        n = self.passes if self.tol is not None else self.niter
+        return n + (self.tail[1] + 2 if self.tail is not None else 0)
 
     def time(self, steps, warmup):
         torch = self.torch
@@ -185,7 +204,7 @@ class Runner:
         return time.perf_counter() - t0
 
     def norms(self):
-        if self.tail is not None:
+        if self.tail is not None or self.tol is not None:
             self.step()
             return None
         self.mk.mk_set_focal(self.plan, self.Gd, self.itd, self.p.shift, self.fb)
@@ -240,84 +259,127 @@ def _errs(got, ref, n):
 
 
 def combined_path(pb, args, sample, ref, batched, tol=1e-3):
-    """FP16 R + batched + series tail, against plain FP32 batched.
+    """FP16 R + batched + series tail, against plain FP32 batched, at `tol`.
 
-    Each path's schedule (passes after the tail) is the shortest that keeps
-    every output within `tol` of the FP64 oracle on the sampled focal points;
-    the plain paths are timed at their own shortest pass counts reaching the
-    same accuracy.  Paths: the learned tail (network), the geometric tail, the
-    restart alone (no tail), each with two-plane and one-plane 16-bit X, then
-    plain FP16 R and plain FP32 R.
+    Every path stops by the library's own rule (mk_iterate_tol at `tol`):
+    the plain paths from the start of the series, the tail paths after k
+    recorded passes and the restart that judges the tail.  The pass counts
+    are the library's choice; the FP64 oracle is consulted only afterwards,
+    to report each path's error on the sampled focal points.  Paths: the
+    learned tail (network), the geometric tail and the restart alone (no
+    tail), each with two-plane and one-plane ("_1x") 16-bit X, then plain
+    FP16 R and plain FP32 R.
     """
     if not os.path.exists(TAIL_WEIGHTS):
         log(f"no trained tail network at {TAIL_WEIGHTS}: combined path skipped")
         return None
     w = np.load(TAIL_WEIGHTS)
     params, k, T = w["params"], int(w["k"]), int(w["T"])
-    out = {"tol": tol, "k": k, "T": T, "weights": os.path.relpath(TAIL_WEIGHTS, ROOT)}
+    out = {"tol": tol, "rule": "mk_iterate_tol (the library's FP64-norm estimate of the untaken terms)",
+           "k": k, "T": T, "weights": os.path.relpath(TAIL_WEIGHTS, ROOT), "sampled_focal_points": list(sample)}
     n = len(sample)
     from paper_2106_04649_amd import mk
 
-    r16 = Runner(pb, rprec=1, niter=0, tail=(params, k, T, 0, 0))
-    r16x = Runner(pb, rprec=1, niter=0, tail=(params, k, T, 0, 0), flags=mk.MK_FLAG_FAST_X)
-    p16 = Runner(pb, rprec=1, niter=32)
-    r32 = Runner(pb, rprec=0, niter=32)
-
-    def errors(r):
-        r.step()
-        return _errs(r.fields(sample), ref, n)
+    paths = {}
+    # "_1x": one 16-bit plane of X (MK_FLAG_FAST_X), half the matrix-core products
+    for flags, sfx in ((0, ""), (mk.MK_FLAG_FAST_X, "_1x")):
+        for mode, base in ((mk.TAIL_NET, "learned"), (mk.TAIL_GEOMETRIC, "geometric"), (mk.TAIL_NONE, "no_tail")):
+            paths[base + sfx] = dict(rprec=1, flags=flags, tail=(params, k, T, mode))
+    paths["plain_fp16"] = dict(rprec=1, flags=0, tail=None)
+    paths["plain_fp32"] = dict(rprec=0, flags=0, tail=None)
 
     sched, timing = {}, {}
-    # "_1x": one 16-bit plane of X (MK_FLAG_FAST_X), half the matrix-core products
-    for run, sfx in ((r16, ""), (r16x, "_1x")):
-        for mode, base in ((0, "learned"), (1, "geometric"), (2, "no_tail")):
-            name = base + sfx
-            sched[name] = None
-            tried = {}
-            for extra in (0, 1, 2, 3, 4, 6, 8, 12):
-                run.tail = (params, k, T, mode, extra)
-                e = errors(run)
-                tried[extra] = float(f"{max(e.values()):.3e}")
-                if max(e.values()) <= tol:
-                    sched[name] = {"extra": extra, "syntheses": k + 2 + extra, "err": e, "tried": tried}
-                    break
-            if sched[name] is not None:
-                timing[name] = run.time(args.steps, args.warmup) / args.steps
-    for name, r in (("plain_fp16", p16), ("plain_fp32", r32)):
-        sched[name] = None
-        for P in range(2, 33):
-            r.niter = P
-            e = errors(r)
-            if max(e.values()) <= tol:
-                sched[name] = {"passes": P, "err": e}
-                timing[name] = r.time(args.steps, args.warmup) / args.steps
-                break
-    for r in (r16, r16x, p16, r32):
+    for name, cfg in paths.items():
+        r = Runner(pb, rprec=cfg["rprec"], flags=cfg["flags"], tail=cfg["tail"], tol=tol, max_passes=32)
+        timing[name] = r.time(args.steps, args.warmup) / args.steps
+        e = _errs(r.fields(sample), ref, n)
+        sched[name] = {"syntheses": r.syntheses(), "passes_after_judge": r.passes,
+                       "estimate_max": float(f"{float(np.max(r.est)):.3e}"),
+                       "err": {k_: float(f"{v:.3e}") for k_, v in e.items()},
+                       "within_tol": bool(max(e.values()) <= tol)}
+        if cfg["tail"] is not None:
+            sched[name]["judge_resid_median"] = float(f"{float(np.median(r.resid)):.3e}")
         r.destroy()
+        log(f"combined {name}: {sched[name]['syntheses']} syntheses, {timing[name] * 1e3:.2f} ms, "
+            f"worst error {max(e.values()):.2e}")
     out["schedules"] = sched
+    out["all_within_tol"] = all(v["within_tol"] for v in sched.values())
     out["ms_per_step"] = {k_: round(v * 1e3, 3) for k_, v in timing.items()}
     t32 = batched["paths"]["fp32"]["ms_per_step"] / 1e3
     out["plain_fp32_32pass_ms_per_step"] = round(t32 * 1e3, 3)
-    if "plain_fp32" in timing:
-        base = timing["plain_fp32"]
-        out["speedup_vs_plain_fp32_same_tol"] = {k_: round(base / v, 3) for k_, v in timing.items()}
+    base = timing["plain_fp32"]
+    out["speedup_vs_plain_fp32_same_tol"] = {k_: round(base / v, 3) for k_, v in timing.items()}
     out["speedup_vs_plain_fp32_32pass"] = {k_: round(t32 / v, 3) for k_, v in timing.items()}
-    log("combined: schedules " + json.dumps({k_: (v or {}).get("syntheses", (v or {}).get("passes"))
-                                             for k_, v in sched.items()}) +
-        " speedup vs plain FP32 at the same accuracy " + json.dumps(out.get("speedup_vs_plain_fp32_same_tol")))
+    log("combined: syntheses " + json.dumps({k_: v["syntheses"] for k_, v in sched.items()}) +
+        " speedup vs plain FP32 at the same tolerance " + json.dumps(out["speedup_vs_plain_fp32_same_tol"]))
+    return out
+
+
+def mixed_leg(args) -> dict:
+    """The mixed workload: 512 focal points at 200-1200 m depth with per-focal
+    bands of 20-80 % of Nyquist, FP16 R with per-frequency scales, the passes
+    replayed as HIP graphs, 32 passes + G assembly per solve; against plain
+    FP32 R on the same 512 focal points and passes.  Errors of both against
+    the FP64 oracle on three sampled focal points (the narrowest band, the
+    widest, one in the middle); the FP16 contraction's roofline from its
+    live HIP-event average."""
+    from mkgen.layered import make_config
+    from paper_2106_04649_amd import mk
+
+    t = time.perf_counter()
+    pm = make_config("mixed", nf=512)
+    nr, nt, B = pm.Rhat.shape[0], pm.geom.nt, pm.Rhat.shape[1]
+    log(f"mixed: generated in {time.perf_counter() - t:.1f} s")
+    widths = pm.fbands[:, 1] - pm.fbands[:, 0] + 1
+    sample = sorted({int(np.argmin(widths)), int(np.argmax(widths)), pm.nf // 2})
+    ref = oracle_reference_banded(pm, sample, pm.niter)
+    out = {"workload": "601x601, nt=2048, 512 focal points at 200-1200 m, per-focal bands of 20-80 % of "
+                       "Nyquist, 32 passes + G assembly",
+           "nf": pm.nf, "mean_band_bins": float(widths.mean()), "sampled_focal_points": sample, "paths": {}}
+    for name, rprec, flags in (("fp16_graph", 1, mk.MK_FLAG_GRAPH), ("fp32", 0, 0)):
+        r = Runner(pm, rprec=rprec, flags=flags, niter=pm.niter)
+        wall = r.time(args.steps, args.warmup)
+        r.norms()
+        got = r.fields(sample)
+        r.destroy()
+        err = {k: max(rel_l2(got[k][j], ref[k][j]) for j in range(len(sample))) for k in got}
+        out["paths"][name] = {"ms_per_step": round(wall * 1e3 / args.steps, 3),
+                              "iters_per_s": round(pm.niter * args.steps / wall, 2),
+                              "focal_iters_per_s": round(pm.niter * args.steps * pm.nf / wall, 1),
+                              "max_rel_l2_vs_oracle": {k: float(f"{v:.3e}") for k, v in err.items()}}
+        log(f"mixed {name}: {out['paths'][name]['ms_per_step']} ms per solve, worst error "
+            f"{max(err.values()):.2e}")
+    out["fp16_graph_over_fp32"] = round(out["paths"]["fp32"]["ms_per_step"] /
+                                        out["paths"]["fp16_graph"]["ms_per_step"], 3)
+    if not args.no_profile:
+        avg_s, _, variant = profile_contract(pm, 1)
+        # algorithmic bytes and flops over the active (focal, bin) pairs only:
+        # R for every bin some focal point uses, X in (two 16-bit planes) and Y
+        # out for each active pair
+        active_bins = int(min(B, pm.fbands[:, 1].max() + 1))
+        pairs = int(widths.sum())
+        nbytes = 4 * nr * nr * active_bins + 8 * nr * pairs + 8 * nr * pairs
+        flops = 8.0 * nr * nr * pairs
+        gbs, tf = nbytes / avg_s / 1e9, flops / avg_s / 1e12
+        bound = "mfma" if flops / (PEAK_TFLOPS[1] * 1e12) > nbytes / (HBM_PEAK_GBS * 1e9) else "hbm"
+        out["contract"] = {"variant": variant, "avg_us": round(avg_s * 1e6, 1), "bytes": nbytes,
+                           "gbs": round(gbs, 1), "tflops": round(tf, 1), "bound": bound,
+                           "frac": round(gbs / HBM_PEAK_GBS if bound == "hbm" else tf / PEAK_TFLOPS[1], 4)}
+        log(f"mixed fp16 contraction: {avg_s * 1e6:.1f} us, {gbs:.0f} GB/s, {tf:.0f} TFLOP/s")
     return out
 
 
 def large_run(args) -> dict:
     """The 2001 x 2001, nt 2048 workload at full size: 2048 focal points of
     the 64 x 32 grid in batches, the mixed path (FP16 R, one 16-bit plane of
-    X, 4 recorded passes, geometric tail and restart, more passes) against
-    plain complex64 R on this GPU.  Each path's pass count is the smallest
-    reaching `tol` relative L2 (every field, every focal point) against 32
-    plain complex64 passes on 8 focal points spread over the grid; the whole
-    grid is then solved with those schedules, G+/G- included, inputs in HBM.
-    The learned tail uses the network trained on the medium family (same
-    spacing, sampling and earth-model family, a smaller aperture)."""
+    X, 4 recorded passes, geometric or learned tail and the restart, then
+    the passes the library's stopping rule asks for) against plain
+    complex64 R stopped by the same rule, G+/G- included, inputs in HBM.
+    Errors are reported afterwards on 8 focal points spread over the grid,
+    against 32 plain complex64 passes (R in complex128 does not fit the
+    host for the FP64 oracle at this size).  The learned tail uses the
+    network trained on the medium family (same spacing, sampling and
+    earth-model family, a smaller aperture)."""
     import torch
 
     from mkgen.torchgen import direct_arrivals_gpu, large_problem_gpu, large_setup
@@ -346,11 +408,11 @@ def large_run(args) -> dict:
         return {k: mk.mk_get(plan, k, torch.empty((nfb, n, nt), device="cuda")) for k in names}
 
     def err(got, ref):
-        worst = 0.0
+        worst = {}
         for k in names:
             d = torch.linalg.vector_norm((got[k] - ref[k]).reshape(got[k].shape[0], -1).double(), dim=1)
             r = torch.linalg.vector_norm(ref[k].reshape(ref[k].shape[0], -1).double(), dim=1)
-            worst = max(worst, float((d / torch.clamp(r, min=1e-300)).max().item()))
+            worst[k] = float((d / torch.clamp(r, min=1e-300)).max().item())
         return worst
 
     plain = plan_for(0, 0)
@@ -362,83 +424,66 @@ def large_run(args) -> dict:
     p.Rhat = None
     torch.cuda.empty_cache()
 
-    # ---- schedules on 8 focal points ----------------------------------------
+    outp = torch.empty((NB, n, nt), device="cuda")
+    outm = torch.empty_like(outp)
+    runs = [("plain", plain, None), ("mixed_geometric", mixed, mk.TAIL_GEOMETRIC)]
+    if tailw is not None:
+        runs.append(("mixed_learned", mixed, mk.TAIL_NET))
+
+    def solve(plan, Gd, itd, tail, nfb):
+        mk.mk_set_focal(plan, Gd, itd, p.shift)
+        syn = 0
+        if tail is not None:
+            mk.mk_iterate(plan, 4, want_norms=False)
+            mk.mk_tail_apply(plan, tail)
+            syn = 6
+        passes, _ = mk.mk_iterate_tol(plan, tol, 40)
+        mk.mk_get(plan, "Gplus", outp[:nfb])
+        mk.mk_get(plan, "Gminus", outm[:nfb])
+        return syn + passes
+
+    # ---- errors on 8 focal points, reported after the rule has chosen -------
     idx8 = np.linspace(0, NF - 1, 8).round().astype(int)
     G8, I8 = focal(idx8)
     mk.mk_set_focal(plain, G8, I8, p.shift)
     mk.mk_iterate(plain, 32, want_norms=False)
     ref = fields(plain, 8)
-    P = None
-    for cand in range(4, 33):
-        mk.mk_set_focal(plain, G8, I8, p.shift)
-        mk.mk_iterate(plain, cand, want_norms=False)
-        if err(fields(plain, 8), ref) <= tol:
-            P = cand
-            break
-    # tail modes: 1 geometric, 0 the network trained on the medium family
-    sched = {}
-    for mode, name in ((1, "geometric"), (0, "learned")):
-        if mode == 0 and tailw is None:
-            continue
-        for cand in (0, 1, 2, 3, 4, 6, 8, 10, 12, 16):
-            mk.mk_set_focal(mixed, G8, I8, p.shift)
-            mk.mk_iterate(mixed, 4, want_norms=False)
-            mk.mk_tail_apply(mixed, mode)
-            if cand:
-                mk.mk_iterate(mixed, cand, want_norms=False)
-            e = err(fields(mixed, 8), ref)
-            if e <= tol:
-                sched[name] = (mode, cand, e)
-                break
-    log(f"large: schedules plain {P} passes, mixed " +
-        ", ".join(f"{k} 4 + 2 + {v[1]}" for k, v in sched.items()))
+    sample_err, sample_syn = {}, {}
+    for name, plan, tail in runs:
+        sample_syn[name] = solve(plan, G8, I8, tail, 8)
+        sample_err[name] = err(fields(plan, 8), ref)
+    log("large: sampled syntheses " + json.dumps(sample_syn) + " worst errors " +
+        json.dumps({k: max(v.values()) for k, v in sample_err.items()}))
     del ref
     torch.cuda.empty_cache()
 
     # ---- the whole grid ------------------------------------------------------
-    outp = torch.empty((NB, n, nt), device="cuda")
-    outm = torch.empty_like(outp)
-
-    def solve(plan, Gd, itd, tail):
-        mk.mk_set_focal(plan, Gd, itd, p.shift)
-        if tail is not None:
-            mode, extra, _ = tail
-            mk.mk_iterate(plan, 4, want_norms=False)
-            mk.mk_tail_apply(plan, mode)
-            if extra:
-                mk.mk_iterate(plan, extra, want_norms=False)
-        else:
-            mk.mk_iterate(plan, P, want_norms=False)
-        nfb = Gd.shape[0]
-        mk.mk_get(plan, "Gplus", outp[:nfb])
-        mk.mk_get(plan, "Gminus", outm[:nfb])
-
-    runs = [("plain", plain, None)] + [("mixed_" + k, mixed, v) for k, v in sched.items()]
     times = {name: 0.0 for name, _, _ in runs}
-    if P is not None:
-        for b0 in range(0, NF, NB):
-            idx = np.arange(b0, min(NF, b0 + NB))
-            Gd, itd = focal(idx)
-            for name, plan, tail in runs:
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                solve(plan, Gd, itd, tail)
-                torch.cuda.synchronize()
-                times[name] += time.perf_counter() - t0
-            log(f"large: focal points {b0}..{idx[-1]} done")
+    syntheses = {name: [] for name, _, _ in runs}
+    for b0 in range(0, NF, NB):
+        idx = np.arange(b0, min(NF, b0 + NB))
+        Gd, itd = focal(idx)
+        for name, plan, tail in runs:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            syntheses[name].append(solve(plan, Gd, itd, tail, len(idx)))
+            torch.cuda.synchronize()
+            times[name] += time.perf_counter() - t0
+        log(f"large: focal points {b0}..{idx[-1]} done")
     mk.mk_destroy(plain)
     mk.mk_destroy(mixed)
     rec = {
         "config": "large: 2001 x 2001 shots/receivers at 5 m, nt 2048 at 2 ms, complex64 R 32.8 GB / "
                   "FP16 R 16.4 GB, 2048 focal points on a 64 x 32 grid (x 2000-8000 m, z 200-1200 m)",
-        "batch": NB, "tol": tol,
-        "schedule": {"plain_fp32_passes": P,
-                     **{f"mixed_{k}": {"syntheses": 4 + 2 + v[1], "err_vs_plain32": v[2]} for k, v in sched.items()}},
+        "batch": NB, "tol": tol, "rule": "mk_iterate_tol",
+        "syntheses_per_batch": syntheses,
+        "sampled": {"focal_points": idx8.tolist(), "syntheses": sample_syn,
+                    "err_vs_plain_c64_32pass": {k: {f: float(f"{e:.3e}") for f, e in v.items()}
+                                                for k, v in sample_err.items()}},
         "seconds": {k: round(v, 3) for k, v in times.items()},
+        "focal_per_s": {k: round(NF / v, 1) for k, v in times.items() if v > 0},
+        "speedup_vs_plain_same_tol": {k: round(times["plain"] / v, 3) for k, v in times.items() if v > 0},
     }
-    if P is not None:
-        rec["focal_per_s"] = {k: round(NF / v, 1) for k, v in times.items() if v > 0}
-        rec["speedup_vs_plain_same_tol"] = {k: round(times["plain"] / v, 3) for k, v in times.items() if v > 0}
     return rec
 
 
@@ -457,6 +502,7 @@ def main() -> int:
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-combined", action="store_true", help="skip the FP16 + learned-tail schedule search")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 512-focal banded FP16 workload")
     ap.add_argument("--graph", action="store_true", help="replay the passes as HIP graphs")
     ap.add_argument("--large", action="store_true",
                     help="instead of the headline: the 2001 x 2001 workload, mixed path against plain FP32")
@@ -531,7 +577,8 @@ def main() -> int:
         log(f"generating the batch (nf={args.batch_nf})")
         pb = make_config("medium", nf=args.batch_nf)
         batched = {"nf": pb.nf, "paths": {}}
-        sample = [0, pb.nf - 1]
+        # eight focal points spread over the line (both ends included)
+        sample = sorted({int(round(x)) for x in np.linspace(0, pb.nf - 1, 8)})
         ref = oracle_reference(pb, sample, args.niter)
         for name, rprec in (("fp32", 0), ("fp16", 1)):
             r = Runner(pb, rprec=rprec, flags=gflags, niter=args.niter)
@@ -582,6 +629,11 @@ def main() -> int:
         if combined is not None:
             batched["combined"] = combined
 
+    mixed = None
+    if not args.no_mixed:
+        log("mixed workload (512 focal points, bands, FP16 R, graphs)")
+        mixed = mixed_leg(args)
+
     rec = {
         "metric": "Marchenko iters/s + HBM TB/s; mixed+learned vs plain FP32 at rel.err 1e-3",
         "value": round(value, 2),
@@ -604,6 +656,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "norm_decay": float((norms[-1] / norms[0]).max()),
         "batched": batched,
+        "mixed": mixed,
     }
     rec.update(extra)
     print(json.dumps(rec), flush=True)

@@ -66,7 +66,11 @@ typedef enum {
     MK_GPLUS = 2,    /* G+  : f1+(-t) - S[f1-(-t)]   (one extra synthesis)     */
     MK_GMINUS = 3,   /* G-  : S[f1+] - f1-           (last lines of Alg. 1)    */
     MK_F2PLUS = 4,   /* f2+ : N_{-1} plus every pass's N_i (Alg. 1, second loop) */
-    MK_PMINUS = 5    /* p-  : sum of every pass's synthesis RN_i (Alg. 1)        */
+    MK_PMINUS = 5,   /* p-  : sum of every pass's synthesis RN_i (Alg. 1)        */
+    MK_GTOTAL = 6    /* G   : the total Green's function, which the Theory
+                        section obtains from f2+ and p- (p-(t) + S[N_last](t)
+                        + f2+(-t)); with Algorithm 1's signs that is G+ + G-,
+                        formed here as their sum                              */
 } mk_field;
 
 /* Plan flags. */
@@ -95,6 +99,14 @@ typedef struct {
     int32_t rprec;       /* mk_rprec                                            */
     uint32_t flags;      /* MK_FLAG_*                                           */
     void* stream;        /* hipStream_t to order work on; NULL = null stream    */
+    int64_t r_dev_bytes; /* cap on the device memory that holds R; <= 0 or at
+                            least R's size: R resident.  Below R's size, R
+                            stays in pinned host memory and crosses to the
+                            device in slabs of frequency bins on every
+                            synthesis, two slab buffers of at most half the
+                            cap each, the copy of one slab overlapping the
+                            contraction of the previous one (the pipelined
+                            batches of Algorithm 2, for R larger than HBM) */
 } mk_plan_desc;
 
 /*
@@ -106,11 +118,16 @@ typedef struct {
  * MK_R_BF16S keep 16-bit pairs with one FP32 scale per frequency (the
  * contraction accumulates in FP32; the norms and the final G subtraction
  * stay in FP64).
+ * With r_dev_bytes below the size of R in the plan's storage, the plan
+ * holds R in pinned host memory (hipHostMalloc) and two device slab buffers
+ * instead of a resident copy; results are the same bits as the resident
+ * plan's (the same kernels per bin), at PCIe speed.
  * Errors: MK_ERR_ARG (null pointers, nr != ns, nt not a power of two in
  * [16, 4096], band outside [0, nt/2], nf_max < 1, dt or dx not positive,
- * unknown rprec or flag), MK_ERR_UNSUPPORTED (ns > 2048 with MK_R_C64,
- * ns > 4096), MK_ERR_OOM, MK_ERR_HIP.  *out is NULL on
- * failure.
+ * unknown rprec or flag, r_dev_bytes positive but below two bins of R),
+ * MK_ERR_UNSUPPORTED (ns > 2048 with MK_R_C64, ns > 4096, MK_FLAG_GRAPH or
+ * MK_FLAG_AUTOTUNE with streamed R), MK_ERR_OOM, MK_ERR_HIP.  *out is NULL
+ * on failure.
  */
 mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out);
 
@@ -120,7 +137,9 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out);
  * R[r][w - iw_lo][s] for w in [iw_lo, iw_hi] (the layout of the
  * Introduction and Implementation sections: the space integral runs over
  * the fastest axis).  The plan repacks it frequency-major (and quantises it
- * for MK_R_F16S / MK_R_BF16S); the caller may free R on return.
+ * for MK_R_F16S / MK_R_BF16S); the caller may free R on return.  A plan
+ * with streamed R (r_dev_bytes) repacks one slab of bins at a time on the
+ * device and keeps the result in its pinned host copy.
  * Errors: MK_ERR_ARG (null, non-finite value), MK_ERR_HIP.
  */
 mk_status mk_load_R(mk_plan_t plan, const float* R, int on_device);
@@ -198,9 +217,10 @@ mk_status mk_iterate_tol(mk_plan_t plan, double tol, int32_t max_passes, int32_t
  * names them as the route to the total G): f2+ = f1+(t) - f1-(-t), which
  * holds N_{-1} and every N_i; p- = S[f2+ - N_last], formed from the G
  * assembly and one more synthesis of the last N (so it costs one pass's
- * contraction).  Both are defined for a plain series only.  The first request
- * of either allocates an nf_max x nr x nt buffer.  Synchronises when out is
- * a host pointer.
+ * contraction).  Both are defined for a plain series only.  MK_GTOTAL is
+ * the total G = G+ + G- (after the G assembly, one add per sample).  The
+ * first request of any of the three allocates an nf_max x nr x nt buffer.
+ * Synchronises when out is a host pointer.
  * Errors: MK_ERR_ARG (null out, unknown field), MK_ERR_STATE (no focal
  * set; MK_F2PLUS or MK_PMINUS after mk_tail_apply), MK_ERR_OOM, MK_ERR_HIP.
  */
@@ -338,20 +358,21 @@ mk_status mk_tail_history(mk_plan_t plan, float* out, int on_device);
 
 /*
  * mk_tail_apply -- after exactly k passes of a fresh series: add an estimate
- * of the rest of the series, T_even = sum_{i>=k even} N_i and
- * T_odd = sum_{i>=k odd} N_i, inside the mute window (f1- -= T_even(-t),
- * f1+ += T_odd, the rule of Algorithm 1 loop 2), then judge it with plain
- * synthesis: one fixed-point step f1- <- theta S f1+, f1+ <- G_d(-t) +
- * A^2 f1+ (A = theta Rev S; two syntheses, counted as two passes), whose
- * residual rho starts a new series carrying the remaining error; later
- * mk_iterate calls continue that series.  mode 0: the loaded network
+ * of the rest of the series, T_odd = sum_{i>=k odd} N_i, to f1+ inside the
+ * mute window (the rule of Algorithm 1 loop 2 for odd passes), then judge
+ * it with plain synthesis: one fixed-point step f1- <- theta S f1+,
+ * f1+ <- G_d(-t) + A^2 f1+ (A = theta Rev S; two syntheses, counted as two
+ * passes), whose residual rho starts a new series carrying the remaining
+ * error; later mk_iterate calls continue that series.  (The even-pass tail
+ * T_even would feed f1-, which the judging step rebuilds from f1+ alone, so
+ * it is not applied.)  mode 0: the loaded network
  * (inputs normalised by the RMS of N_0 per trace; with hidden width 16 it
  * runs as one kernel in its half-precision inference form -- input and
  * hidden activations stored as IEEE halves, FP32 accumulation -- and only
  * on the 256-sample tiles that meet the mute window; other widths run layer
  * by layer in FP32); 1: geometric
- * extrapolation of the last two iterates of each parity (needs an even
- * k >= 4); 2: no estimate (exactly two more passes of the plain series).
+ * extrapolation of the last two odd iterates (needs an even k >= 4);
+ * 2: no estimate (exactly two more passes of the plain series).
  * rel_resid: host double [nf] receiving ||rho|| / ||G_d|| per focal point
  * (the restart step's verdict on the estimate), or NULL.  Synchronises.
  * Errors: MK_ERR_ARG (mode), MK_ERR_STATE (not exactly k recorded passes
@@ -360,6 +381,32 @@ mk_status mk_tail_history(mk_plan_t plan, float* out, int on_device);
 mk_status mk_tail_apply(mk_plan_t plan, int32_t mode, double* rel_resid);
 
 /* mk_destroy -- free the plan and its device memory (NULL is a no-op). */
+/*
+ * Series state: checkpoint and resume of a running series (Algorithm 1's
+ * loop state: the accumulated f1+ and f1-, the spectrum of the last term as
+ * the next synthesis reads it, the pass counters, the focal set and the
+ * norms the stopping rule reads).  The next synthesis depends on the last
+ * term only through its stored in-band spectrum, so the blob holds that
+ * spectrum (in the plan's X storage) rather than the time-domain term.
+ *
+ * mk_state_bytes -- size in bytes of the blob for the current series.
+ * mk_get_state -- copy the state into blob (host memory of at least
+ *   mk_state_bytes bytes).  Synchronises.
+ * mk_set_state -- make blob the plan's current series.  The plan must have
+ *   R loaded and the same nr, nt, band, rprec and MK_FLAG_FAST_X as the
+ *   plan that saved it, nf_max >= the saved nf, and, when the saved series
+ *   was recording iterates, mk_tail_record with the same k and T.  The
+ *   series then continues exactly: mk_iterate after mk_set_state gives the
+ *   same bits as the uninterrupted plan (same R and contraction choice).
+ *   Synchronises.
+ * Errors: MK_ERR_ARG (NULL, short blob, a blob of another shape or storage,
+ * inconsistent counters), MK_ERR_STATE (no focal points set; R not loaded;
+ * recording mismatch), MK_ERR_OOM, MK_ERR_HIP.
+ */
+mk_status mk_state_bytes(mk_plan_t plan, size_t* bytes);
+mk_status mk_get_state(mk_plan_t plan, void* blob, size_t bytes);
+mk_status mk_set_state(mk_plan_t plan, const void* blob, size_t bytes);
+
 mk_status mk_destroy(mk_plan_t plan);
 
 /* mk_strerror -- static description of a status code. */

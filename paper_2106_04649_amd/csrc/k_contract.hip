@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_contract_q16(
 template <int J, int NF>
 void launch_one(const ContractArgs& c, const float2* X, float2* Yc, dim3 grid, dim3 block,
                 int64_t per_xcd, hipStream_t s) {
-    const int64_t nrows = (int64_t)c.B * c.nr;
+    const int64_t nrows = (int64_t)c.nb * c.nr;
     const int64_t xstride4 = (int64_t)c.B * (c.ns_pad / 2);
     const int64_t ystride = (int64_t)c.B * c.nr;
     if (c.prec == MK_R_C64) {
@@ -227,7 +227,7 @@ void launch_one(const ContractArgs& c, const float2* X, float2* Yc, dim3 grid, d
 
 template <int J>
 hipError_t launch_j(const ContractArgs& c, hipStream_t s) {
-    const int64_t nrows = (int64_t)c.B * c.nr;
+    const int64_t nrows = (int64_t)c.nb * c.nr;
     const int64_t waves = (nrows + kRowsPerWave - 1) / kRowsPerWave;
     const int64_t blocks = (waves + kWaves - 1) / kWaves;
     const int64_t per_xcd = (blocks + 7) / 8;

@@ -530,7 +530,7 @@ hipError_t launch_l(const ContractArgs& c, hipStream_t s) {
     constexpr int NFB = 8 * RA;
     const int ftiles = (c.ncols + NFB - 1) / NFB;
     const int rtiles = (c.nr + kLdsRcv - 1) / kLdsRcv;
-    const int64_t ntiles = (int64_t)ftiles * rtiles * c.B;
+    const int64_t ntiles = (int64_t)ftiles * rtiles * c.nb;
     const int64_t per_xcd = (ntiles + 7) / 8;
     hipLaunchKernelGGL((k_contract_lds<PREC, RA, SPLIT, TILED>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s,
                        c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B, c.ncols,
@@ -543,7 +543,7 @@ hipError_t launch_v(const ContractArgs& c, hipStream_t s) {
     constexpr int FT = 32 * WM, RT = 32 * WN;
     const int ftiles = (2 * c.ncols + FT - 1) / FT;
     const int rtiles = (c.nr + RT - 1) / RT;
-    const int64_t ntiles = (int64_t)ftiles * rtiles * c.B;
+    const int64_t ntiles = (int64_t)ftiles * rtiles * c.nb;
     const int64_t per_xcd = (ntiles + 7) / 8;
     hipLaunchKernelGGL((k_contract_mfma<PREC, WM, WN, SPLIT>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s,
                        c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B, c.ncols,

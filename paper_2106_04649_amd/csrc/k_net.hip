@@ -436,8 +436,7 @@ template <int KP>
 __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, const h8* __restrict__ wpk,
                                                   const float* __restrict__ hist,
                                                   const float* __restrict__ scale, const int32_t* __restrict__ itd,
-                                                  int shift, int k, int T, int nt, float* __restrict__ f1p,
-                                                  float* __restrict__ f1m) {
+                                                  int shift, int k, int T, int nt, float* __restrict__ f1p) {
     constexpr int XP = KP == 16 ? kHP : KP;    // halves per staged input sample
     constexpr int S1 = ksteps<KP>(), S2 = ksteps<kFH>();
     constexpr int U2 = kXN * XP > kA2N * kHP ? kXN * XP : kA2N * kHP;
@@ -493,24 +492,15 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
         }
     }
     float* fp = f1p + (size_t)tr * nt;
-    float* fm = f1m + (size_t)tr * nt;
     // |t| <= T/2 <= nt/2 for u < T: one wrap at most
     auto f1_ip = [&](int m) {
         const int u = t0 + 16 * (wv + 4 * m) + i16;
         const int t = u - hT;
         return u < T ? (t < 0 ? t + nt : t) : 0;
     };
-    auto f1_im = [&](int m) {
-        const int u = t0 + 16 * (wv + 4 * m) + i16;
-        const int t = u - hT;
-        return u < T ? (t > 0 ? nt - t : -t) : 0;
-    };
-    float pv[4], mv[4];
+    float pv[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        pv[m] = fp[f1_ip(m)];
-        mv[m] = fm[f1_im(m)];
-    }
+    for (int m = 0; m < 4; ++m) pv[m] = fp[f1_ip(m)];
     // window samples u = t + T/2 with |t| < L
     if (L <= 0 || t0 >= hT + L || t0 + kFT <= hT - L + 1) return;
     const float inv = se > 0.f ? 1.f / se : 0.f;
@@ -600,8 +590,10 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     }
     __syncthreads();
 
-    // layer 3 (rows 0 and 1 of a padded 16-row product) and the tail:
-    // f1+ += s y_odd, f1- -= s y_even(-t) inside the window
+    // layer 3 (rows 0 and 1 of a padded 16-row product) and the tail
+    // f1+ += s y_odd inside the window.  The even-pass tail (row 0) is not
+    // applied: the restart that judges the estimate rebuilds f1- from f1+
+    // alone (f1- := theta S f1+), so nothing would read it.
     h8 w3[S2];
 #pragma unroll
     for (int m = 0; m < S2; ++m) w3[m] = wpk[(S1 + S2 + m) * 64 + lane];
@@ -613,10 +605,7 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
         for (int q = 0; q < S2; ++q)
             y = __builtin_amdgcn_mfma_f32_16x16x32_f16(w3[q], acts_b<kFH, 16, kHP>(a2s, 16 * (wv + 4 * m) + i16, g, q),
                                                        y, 0, 0, 0);
-        if (g == 0 && upd[m]) {
-            fp[f1_ip(m)] = pv[m] + se * y[1];
-            fm[f1_im(m)] = mv[m] - se * y[0];
-        }
+        if (g == 0 && upd[m]) fp[f1_ip(m)] = pv[m] + se * y[1];
     }
 }
 
@@ -670,17 +659,17 @@ hipError_t net_tail_pack(const float* P, int k, int H, void* out, hipStream_t s)
 
 hipError_t net_tail_apply(const float* P, const void* wpack, const float* hist, const float* scale,
                           const int32_t* itd, int shift, int ntr, int k, int H, int T, int nt, float* f1p,
-                          float* f1m, hipStream_t s) {
+                          hipStream_t s) {
     if (!net_tail_fused(k, H)) return hipErrorInvalidValue;
     if (ntr <= 0 || T <= 0) return hipSuccess;
     const h8* w = static_cast<const h8*>(wpack);
     const dim3 grid(ntr, (T + kFT - 1) / kFT);
     if (k <= 4)
-        hipLaunchKernelGGL(k_net_tail<4>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p, f1m);
+        hipLaunchKernelGGL(k_net_tail<4>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p);
     else if (k <= 8)
-        hipLaunchKernelGGL(k_net_tail<8>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p, f1m);
+        hipLaunchKernelGGL(k_net_tail<8>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p);
     else
-        hipLaunchKernelGGL(k_net_tail<16>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p, f1m);
+        hipLaunchKernelGGL(k_net_tail<16>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p);
     return hipGetLastError();
 }
 

@@ -1,10 +1,12 @@
 // Series-tail application: the recorded first k iterates of each trace ->
-// an estimate of the remaining even-pass and odd-pass sums, added to f1- and
-// f1+ inside the mute window.  One wave per trace.
+// an estimate of the remaining odd-pass sum, added to f1+ inside the mute
+// window.  One wave per trace.  The even-pass sum would feed f1-, but the
+// restart that judges every tail rebuilds f1- from f1+ alone
+// (f1- := theta S f1+), so it is not applied.
 //
 // Window convention: recorded sample u of a trace holds time t = u - T/2
-// (periodic index t mod nt).  T_even feeds f1- -= T_even(-t) (even passes),
-// T_odd feeds f1+ += T_odd (odd passes), as in the series itself.
+// (periodic index t mod nt).  T_odd feeds f1+ += T_odd (odd passes), as in
+// the series itself.
 #include "mk_internal.h"
 
 namespace {
@@ -36,56 +38,52 @@ __global__ __launch_bounds__(256) void k_tail_prep(const float* __restrict__ his
     if (lane == 0) scale[tr] = inv > 0.f ? s : 0.f;
 }
 
-// mode 0: tails from the network output y[tr][2][T] (channel 0 even, 1 odd)
-// mode 1: geometric extrapolation of the last two iterates of each parity
+// mode 0: the odd tail from the network output y[tr][2][T] (channel 1)
+// mode 1: geometric extrapolation of the last two odd iterates
 __global__ __launch_bounds__(256) void k_tail_apply(const float* __restrict__ hist, const float* __restrict__ y,
                                                     const float* __restrict__ scale, const int32_t* __restrict__ itd,
                                                     int shift, int ntr, int k, int T, int nt, int mode,
-                                                    float* __restrict__ f1p, float* __restrict__ f1m) {
+                                                    float* __restrict__ f1p) {
     const int lane = threadIdx.x & 63;
     const int tr = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tr >= ntr) return;
     const float* h = hist + (size_t)tr * k * T;
     const int L = itd[tr] - shift;
     const int hT = T >> 1;
-    float ge = 0.f, go = 0.f, se = 0.f;
+    float g = 0.f;
     constexpr int U = 8;                       // samples per lane whose loads are in flight together
     if (mode == 1) {
-        // ratio of the norms of the last two iterates of each parity
-        float n[4] = {0.f, 0.f, 0.f, 0.f};
+        // ratio of the norms of the last two odd iterates (k even: channels k-3, k-1)
+        float n[2] = {0.f, 0.f};
         for (int u0 = 0; u0 < T; u0 += 64 * U) {
-            float v[U][4];
+            float v[U][2];
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int u = min(u0 + lane + 64 * j, T - 1);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) v[j][c] = h[(size_t)(k - 4 + c) * T + u];
+                v[j][0] = h[(size_t)(k - 3) * T + u];
+                v[j][1] = h[(size_t)(k - 1) * T + u];
             }
 #pragma unroll
             for (int j = 0; j < U; ++j)
                 if (u0 + lane + 64 * j < T) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) n[c] += v[j][c] * v[j][c];
+                    n[0] += v[j][0] * v[j][0];
+                    n[1] += v[j][1] * v[j][1];
                 }
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) n[c] = sqrtf(wave_sum_f(n[c]));
-        // k even: channels k-4, k-2 are even passes; k-3, k-1 odd passes
-        const float qe = n[0] > 0.f ? fminf(n[2] / n[0], 0.9f) : 0.f;
-        const float qo = n[1] > 0.f ? fminf(n[3] / n[1], 0.9f) : 0.f;
-        ge = qe / (1.f - qe);
-        go = qo / (1.f - qo);
+        n[0] = sqrtf(wave_sum_f(n[0]));
+        n[1] = sqrtf(wave_sum_f(n[1]));
+        const float qo = n[0] > 0.f ? fminf(n[1] / n[0], 0.9f) : 0.f;
+        g = qo / (1.f - qo);
     } else {
-        se = scale[tr];
+        g = scale[tr];
     }
     float* fp = f1p + (size_t)tr * nt;
-    float* fm = f1m + (size_t)tr * nt;
     // window samples t = u - T/2 with |t| < L (t = +-nt/2 excluded); every
     // read of a group is issued before the first update (addresses of samples
     // outside the window are clamped to the trace's first sample and unused)
     for (int u0 = 0; u0 < T; u0 += 64 * U) {
-        float te[U], to[U], pv[U], mv[U];
-        int ip[U], im[U];
+        float to[U], pv[U];
+        int ip[U];
         bool in[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) {
@@ -93,26 +91,13 @@ __global__ __launch_bounds__(256) void k_tail_apply(const float* __restrict__ hi
             const int t = u - hT;
             in[j] = (u < T) & (t < L) & (-t < L) & (t != nt / 2) & (-t != nt / 2);
             const int uc = min(u, T - 1);
-            if (mode == 1) {
-                te[j] = h[(size_t)(k - 2) * T + uc];
-                to[j] = h[(size_t)(k - 1) * T + uc];
-            } else {
-                te[j] = y[((size_t)tr * 2 + 0) * T + uc];
-                to[j] = y[((size_t)tr * 2 + 1) * T + uc];
-            }
+            to[j] = mode == 1 ? h[(size_t)(k - 1) * T + uc] : y[((size_t)tr * 2 + 1) * T + uc];
             ip[j] = in[j] ? ((t % nt) + nt) % nt : 0;
-            im[j] = in[j] ? ((-t % nt) + nt) % nt : 0;
             pv[j] = fp[ip[j]];
-            mv[j] = fm[im[j]];
         }
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            if (!in[j]) continue;
-            const float e = mode == 1 ? ge * te[j] : se * te[j];
-            const float o = mode == 1 ? go * to[j] : se * to[j];
-            fp[ip[j]] = pv[j] + o;               // odd passes feed f1+
-            fm[im[j]] = mv[j] - e;               // even passes feed f1- -= N(-t)
-        }
+        for (int j = 0; j < U; ++j)
+            if (in[j]) fp[ip[j]] = pv[j] + g * to[j];      // odd passes feed f1+
     }
 }
 
@@ -125,9 +110,9 @@ hipError_t launch_tail_prep(const float* hist, int ntr, int k, int T, float* x, 
 }
 
 hipError_t launch_tail_apply(const float* hist, const float* y, const float* scale, const int32_t* itd, int shift,
-                             int ntr, int k, int T, int nt, int mode, float* f1p, float* f1m, hipStream_t s) {
+                             int ntr, int k, int T, int nt, int mode, float* f1p, hipStream_t s) {
     if (ntr <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_tail_apply, dim3((ntr + 3) / 4), dim3(256), 0, s, hist, y, scale, itd, shift, ntr, k, T,
-                       nt, mode, f1p, f1m);
+                       nt, mode, f1p);
     return hipGetLastError();
 }

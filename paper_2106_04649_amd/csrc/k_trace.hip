@@ -1037,6 +1037,13 @@ __global__ __launch_bounds__(256) void k_f2p(const float* __restrict__ f1p, cons
     out[i] = f1p[i] - f1m[tr * nt + (k == 0 ? 0 : nt - k)];
 }
 
+// The total Green's function G = G+ + G-, one rounding per sample.
+__global__ __launch_bounds__(256) void k_gsum(const float* __restrict__ gp, const float* __restrict__ gm, int64_t n,
+                                              float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = gp[i] + gm[i];
+}
+
 // Double-focusing image (Theory section, imaging): the zero-time sample of
 // G- convolved in time with f1+ and integrated over the receivers.  First
 // stage, one wave per trace: sum_k G-[k] f1+[(-k) mod nt] in FP64 (a product
@@ -1177,6 +1184,12 @@ hipError_t launch_f2p(const float* f1p, const float* f1m, int64_t ntr, int nt, f
     if (ntr <= 0) return hipSuccess;
     const int64_t n = ntr * nt;
     hipLaunchKernelGGL(k_f2p, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f1p, f1m, ntr, nt, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gsum(const float* gp, const float* gm, int64_t n, float* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gsum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, gp, gm, n, out);
     return hipGetLastError();
 }
 

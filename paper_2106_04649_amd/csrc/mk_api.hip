@@ -66,6 +66,16 @@ void drop_graphs(mk_plan_t p) {
 void free_plan_memory(mk_plan_t p) {
     drop_graphs(p);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    if (p->copy_stream) {
+        (void)hipStreamSynchronize(p->copy_stream);
+        (void)hipStreamDestroy(p->copy_stream);
+    }
+    for (int b = 0; b < 2; ++b) {
+        if (p->rbuf[b]) (void)hipFree(p->rbuf[b]);
+        if (p->ev_copied[b]) (void)hipEventDestroy(p->ev_copied[b]);
+        if (p->ev_consumed[b]) (void)hipEventDestroy(p->ev_consumed[b]);
+    }
+    if (p->R_host) (void)hipHostFree(p->R_host);
     void* bufs[] = {p->R, p->rscale, p->X, p->Y, p->f1p, p->f1m, p->gp, p->gm, p->stage, p->itd,
                     p->fband, p->perm, p->iperm, p->ncols, p->npart, p->norm0, p->gdnorm, p->nlast, p->xscale,
                     p->norms, p->tw, p->flag, p->n0, p->hist, p->tail_w, p->tail_x, p->tail_work,
@@ -170,6 +180,7 @@ ContractArgs contract_args(mk_plan_t p, const void* X, int ncols, int ncols_mul)
     c.ns_pad = p->ns_pad;
     c.B = p->B;
     c.ncols = ncols;
+    c.nb = p->B;
     return c;
 }
 
@@ -295,6 +306,49 @@ TraceArgs trace_args(mk_plan_t p, int nfo) {
     return a;
 }
 
+// Streamed R: slab `slab` (bins [slab * slab_bins, ...)) into device buffer
+// `buf` on the copy stream, after the last contraction that read that buffer;
+// nothing to do when the buffer already holds it or is receiving it.
+mk_status slab_in(mk_plan_t p, int slab, int buf) {
+    if (p->buf_slab[buf] == slab) return MK_OK;
+    const int w0 = slab * p->slab_bins;
+    const int nb = std::min(p->slab_bins, p->B - w0);
+    HIP_TRY(p, hipStreamWaitEvent(p->copy_stream, p->ev_consumed[buf], 0));
+    HIP_TRY(p, hipMemcpyAsync(p->rbuf[buf], p->R_host + (size_t)w0 * p->bin_bytes, (size_t)nb * p->bin_bytes,
+                              hipMemcpyHostToDevice, p->copy_stream));
+    HIP_TRY(p, hipEventRecord(p->ev_copied[buf], p->copy_stream));
+    p->buf_slab[buf] = slab;
+    return MK_OK;
+}
+
+// One contraction over streamed R, slab by slab: each slab's launch covers
+// its bins (R, scales, X, Y and the active counts offset to its first bin,
+// X and Y keeping the strides of the whole band) and waits for its copy;
+// the next slab (after the last, the first one of the next contraction)
+// is copied into the other buffer meanwhile.  The per-bin arithmetic is that
+// of the resident plan.
+mk_status contract_streamed(mk_plan_t p, const ContractArgs& c, int variant, int xprec) {
+    const size_t xbin = (size_t)p->ns_pad * (xprec == XP_F32 ? sizeof(float2) : sizeof(uint32_t));
+    for (int j = 0; j < p->nslabs; ++j) {
+        const int buf = (int)(p->slab_use & 1);
+        const int w0 = j * p->slab_bins;
+        MK_TRY(slab_in(p, j, buf));
+        HIP_TRY(p, hipStreamWaitEvent(p->stream, p->ev_copied[buf], 0));
+        ContractArgs cj = c;
+        cj.R = p->rbuf[buf];
+        cj.rscale = c.rscale + w0;
+        cj.X = static_cast<const unsigned char*>(c.X) + (size_t)w0 * xbin;
+        cj.Y = c.Y + (size_t)w0 * c.nr;
+        cj.ncols_w = c.ncols_w ? c.ncols_w + w0 : nullptr;
+        cj.nb = std::min(p->slab_bins, p->B - w0);
+        HIP_TRY(p, launch_choice(cj, variant, p->stream));
+        HIP_TRY(p, hipEventRecord(p->ev_consumed[buf], p->stream));
+        ++p->slab_use;
+        MK_TRY(slab_in(p, (j + 1) % p->nslabs, buf ^ 1));
+    }
+    return MK_OK;
+}
+
 mk_status run_contract(mk_plan_t p, const ContractChoice& ch, const void* Xbuf, const float* xs,
                        int ncols, int ncols_mul, int kind) {
     int variant = ch.variant;
@@ -304,7 +358,8 @@ mk_status run_contract(mk_plan_t p, const ContractChoice& ch, const void* Xbuf, 
     c.xsplit = (ch.xprec == XP_F16X2 || ch.xprec == XP_BF16X2) ? 1 : 0;
     hipEvent_t ev = nullptr;
     HIP_TRY(p, prof_begin(p, &ev));
-    HIP_TRY(p, launch_choice(c, variant, p->stream));
+    if (p->r_stream) MK_TRY(contract_streamed(p, c, variant, ch.xprec));
+    else HIP_TRY(p, launch_choice(c, variant, p->stream));
     HIP_TRY(p, prof_end(p, ev, kind));
     return MK_OK;
 }
@@ -488,11 +543,18 @@ mk_status assemble_G(mk_plan_t p) {
 // After a tail or restart the fields are no longer partial sums of one
 // series, so both are refused there.
 mk_status aux_field(mk_plan_t p, int field) {
-    if (p->tail_applied)
+    if (p->tail_applied && field != MK_GTOTAL)
         return fail(p, MK_ERR_STATE, "mk_get: f2+ and p- are defined for a plain series (no tail applied)");
     if (!p->aux) {
         HIP_TRY(p, hipStreamSynchronize(p->stream));
         HIP_TRY(p, dalloc(&p->aux, (size_t)p->d.nf_max * p->d.nr * p->d.nt));
+    }
+    if (field == MK_GTOTAL) {
+        // p- + S[N_last] + f2+(-t) = G+ + G- (Algorithm 1's signs): the sum of
+        // the two assembled fields, without a third synthesis
+        if (!p->g_valid) MK_TRY(assemble_G(p));
+        HIP_TRY(p, launch_gsum(p->gp, p->gm, (int64_t)p->nf * p->d.nr * p->d.nt, p->aux, p->stream));
+        return MK_OK;
     }
     if (field == MK_F2PLUS) {
         HIP_TRY(p, launch_f2p(p->f1p, p->f1m, (int64_t)p->nf * p->d.nr, p->d.nt, p->aux, p->stream));
@@ -502,6 +564,61 @@ mk_status aux_field(mk_plan_t p, int field) {
     MK_TRY(run_contract(p, p->series_choice, p->X, p->xscale, p->nf, 1, 4));
     TraceArgs a = trace_args(p, p->nf);
     MK_TRY(run_trace(p, TM_POUT, a, 4));
+    return MK_OK;
+}
+
+// mk_load_R for streamed R: one slab of bins at a time, the caller's rows of
+// those bins (a 2D region of R[r][w][s]) go to a device staging buffer, the
+// resident path's repack / quantisation kernels write the slab's device
+// layout into slab buffer 0 (the per-frequency scales need only the slab's
+// own bins), and the slab goes down to its place in the pinned host copy.
+mk_status load_R_streamed(mk_plan_t p, const float* R, int on_device) {
+    const mk_plan_desc& d = p->d;
+    HIP_TRY(p, hipStreamSynchronize(p->copy_stream));      // no copy may still read the slab buffers
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    p->buf_slab[0] = p->buf_slab[1] = -1;
+    float* staging = nullptr;
+    HIP_TRY(p, dalloc(&staging, 2 * (size_t)d.nr * p->slab_bins * d.ns));
+    const size_t pitch = (size_t)p->B * d.ns * sizeof(float2);      // one receiver row of the caller's R
+    hipError_t e = hipMemsetAsync(p->flag, 0, sizeof(int), p->stream);
+    for (int j = 0; j < p->nslabs && e == hipSuccess; ++j) {
+        const int w0 = j * p->slab_bins;
+        const int nb = std::min(p->slab_bins, p->B - w0);
+        const size_t width = (size_t)nb * d.ns * sizeof(float2);
+        e = hipMemcpy2DAsync(staging, width, R + (size_t)w0 * d.ns * 2, pitch, width, d.nr,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->stream);
+        if (e != hipSuccess) break;
+        if (p->r_tiled) {
+            if (d.rprec != MK_R_C64) e = launch_rscale(staging, p->rscale + w0, d.nr, nb, d.ns, p->flag, p->stream);
+            if (e == hipSuccess)
+                e = launch_repack_tiled(d.rprec, staging, p->rbuf[0], p->rscale + w0, d.nr, nb, d.ns, p->ns_pad,
+                                        p->flag, p->stream);
+        } else if (d.rprec == MK_R_C64) {
+            e = launch_repack_c64(staging, reinterpret_cast<float2*>(p->rbuf[0]), d.nr, nb, d.ns, p->ns_pad,
+                                  p->flag, p->stream);
+        } else {
+            e = launch_quantize_R(d.rprec, staging, p->rbuf[0], p->rscale + w0, d.nr, nb, d.ns, p->ns_pad,
+                                  p->flag, p->stream);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p->R_host + (size_t)w0 * p->bin_bytes, p->rbuf[0], (size_t)nb * p->bin_bytes,
+                               hipMemcpyDeviceToHost, p->stream);
+    }
+    int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    (void)hipFree(staging);
+    if (e != hipSuccess) return hip_fail(p, e, "mk_load_R: streamed repack");
+    // the slab buffers were written by the compute stream: later copies into
+    // them wait for that work (done: the stream is synchronised)
+    for (int b = 0; b < 2; ++b) HIP_TRY(p, hipEventRecord(p->ev_consumed[b], p->stream));
+    if (h) {
+        p->R_loaded = false;
+        return fail(p, MK_ERR_ARG, "mk_load_R: R holds a non-finite value");
+    }
+    p->R_loaded = true;
+    p->focal_set = false;
+    p->g_valid = false;
     return MK_OK;
 }
 
@@ -543,15 +660,37 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
         return fail(nullptr, MK_ERR_UNSUPPORTED, "mk_plan: complex64 R supports ns <= 2048");
     if (d.flags & ~(MK_FLAG_GRAPH | MK_FLAG_PROFILE | MK_FLAG_AUTOTUNE | MK_FLAG_FAST_X | MK_FLAG_ROW_R))
         return fail(nullptr, MK_ERR_ARG, "mk_plan: unknown flag bits");
+    const int B = d.iw_hi - d.iw_lo + 1;
+    const int ns_pad = (d.ns + 31) & ~31;      // rows of whole 128-byte chunks in every precision
+    const bool r_tiled = d.nf_max > kGemvMaxCols && !(d.flags & MK_FLAG_ROW_R);
+    const size_t relem = d.rprec == MK_R_C64 ? sizeof(float2) : sizeof(uint32_t);
+    const size_t rbytes = r_tiled ? tiled_R_bytes(d.rprec, d.nr, B, ns_pad) : (size_t)B * d.nr * ns_pad * relem;
+    const size_t bin_bytes = rbytes / (size_t)B;
+    const bool r_stream = d.r_dev_bytes > 0 && (size_t)d.r_dev_bytes < rbytes;
+    int slab_bins = 0;
+    if (r_stream) {
+        slab_bins = (int)std::min<size_t>((size_t)d.r_dev_bytes / 2 / bin_bytes, (size_t)B);
+        if (slab_bins < 1)
+            return fail(nullptr, MK_ERR_ARG, "mk_plan: r_dev_bytes holds fewer than two bins of R (" +
+                                                 std::to_string(2 * bin_bytes) + " bytes)");
+        if (d.flags & (MK_FLAG_GRAPH | MK_FLAG_AUTOTUNE))
+            return fail(nullptr, MK_ERR_UNSUPPORTED,
+                        "mk_plan: streamed R (r_dev_bytes below the size of R) excludes MK_FLAG_GRAPH and "
+                        "MK_FLAG_AUTOTUNE");
+    }
 
     mk_plan_t p = new (std::nothrow) mk_plan_s();
     if (!p) return fail(nullptr, MK_ERR_OOM, "mk_plan: host allocation failed");
     p->d = d;
     if (!(p->d.div_factor > 0.0)) p->d.div_factor = 1e3;
-    p->B = d.iw_hi - d.iw_lo + 1;
+    p->B = B;
     p->M = d.nt / 2;
-    p->ns_pad = (d.ns + 31) & ~31;      // rows of whole 128-byte chunks in every precision
-    p->r_tiled = d.nf_max > kGemvMaxCols && !(d.flags & MK_FLAG_ROW_R);
+    p->ns_pad = ns_pad;
+    p->r_tiled = r_tiled;
+    p->r_stream = r_stream;
+    p->bin_bytes = bin_bytes;
+    p->slab_bins = slab_bins;
+    p->nslabs = r_stream ? (B + slab_bins - 1) / slab_bins : 0;
     p->stream = reinterpret_cast<hipStream_t>(d.stream);
     p->tune_mode = (d.flags & MK_FLAG_AUTOTUNE) ? -2 : -1;
 
@@ -570,10 +709,24 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     }
     const size_t nfm = (size_t)d.nf_max;
     const size_t trace = (size_t)d.nr * d.nt;
-    const size_t relem = d.rprec == MK_R_C64 ? sizeof(float2) : sizeof(uint32_t);
-    const size_t rbytes = p->r_tiled ? tiled_R_bytes(d.rprec, d.nr, p->B, p->ns_pad)
-                                     : (size_t)p->B * d.nr * p->ns_pad * relem;
-    if ((e = hipMalloc(&p->R, rbytes)) != hipSuccess) return bail(e, "R");
+    if (r_stream) {
+        if ((e = hipHostMalloc((void**)&p->R_host, rbytes, hipHostMallocDefault)) != hipSuccess)
+            return bail(e, "pinned host R");
+        for (int b = 0; b < 2; ++b) {
+            if ((e = hipMalloc(&p->rbuf[b], (size_t)slab_bins * bin_bytes)) != hipSuccess)
+                return bail(e, "R slab buffer");
+            if ((e = hipEventCreateWithFlags(&p->ev_copied[b], hipEventDisableTiming)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&p->ev_consumed[b], hipEventDisableTiming)) != hipSuccess)
+                return bail(e, "slab events");
+        }
+        // a second stream at the default priority carries the host-to-device copies
+        if ((e = hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking)) != hipSuccess)
+            return bail(e, "copy stream");
+        for (int b = 0; b < 2; ++b)
+            if ((e = hipEventRecord(p->ev_consumed[b], p->stream)) != hipSuccess) return bail(e, "slab events");
+    } else if ((e = hipMalloc(&p->R, rbytes)) != hipSuccess) {
+        return bail(e, "R");
+    }
     if ((e = dalloc(&p->rscale, (size_t)p->B)) != hipSuccess) return bail(e, "R scales");
     if ((e = dalloc(&p->X, 3 * nfm * p->B * p->ns_pad)) != hipSuccess) return bail(e, "X");
     if ((e = dalloc(&p->Y, 2 * nfm * p->B * d.nr)) != hipSuccess) return bail(e, "Y");
@@ -623,6 +776,7 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
 mk_status mk_load_R(mk_plan_t p, const float* R, int on_device) {
     if (!p) return fail(nullptr, MK_ERR_ARG, "mk_load_R: plan is NULL");
     if (!R) return fail(p, MK_ERR_ARG, "mk_load_R: R is NULL");
+    if (p->r_stream) return load_R_streamed(p, R, on_device);
     const mk_plan_desc& d = p->d;
     const size_t n = (size_t)d.nr * p->B * d.ns;      // complex elements
     const float* src = R;
@@ -846,6 +1000,87 @@ mk_status replay_passes(mk_plan_t p, int n, int parity0) {
     return MK_OK;
 }
 
+// ---- series state (checkpoint and resume) ----------------------------------
+// The blob is a header followed by the plan's series state in a fixed order;
+// every piece is a straight copy of what the plan holds, so a resumed series
+// continues with the same bits as an uninterrupted one.
+constexpr char kStateMagic[8] = {'M', 'K', 'S', 'T', 'A', 'T', 'E', '1'};
+
+struct StateHeader {
+    char magic[8];
+    int32_t nr, nt, iw_lo, iw_hi, ns_pad, rprec, flags;
+    int32_t nf, shift, passes, pass_base, tail_applied, has_fband;
+    int32_t variant, xprec, log_len, series_start, prev_series_start;
+    int32_t hist_k, hist_T, has_hist, reserved;
+};
+
+// One entry of the blob after the header: `bytes` bytes at device address
+// `dev` (or host address `host` when dev is null).
+struct StatePart {
+    void* dev;
+    void* host;
+    size_t bytes;
+};
+
+std::vector<StatePart> state_parts(mk_plan_t p, const StateHeader& h, std::vector<double>& host_norms) {
+    const size_t nf = (size_t)h.nf, nr = (size_t)p->d.nr, nt = (size_t)p->d.nt, B = (size_t)p->B;
+    const size_t trace = nf * nr * nt;
+    host_norms.resize(2 * nf);
+    std::vector<StatePart> v = {
+        {p->perm, nullptr, nf * sizeof(int32_t)},
+        {p->iperm, nullptr, nf * sizeof(int32_t)},
+        {p->fband, nullptr, 2 * nf * sizeof(int32_t)},
+        {p->ncols, nullptr, B * sizeof(int32_t)},
+        {p->itd, nullptr, nf * nr * sizeof(int32_t)},
+        {p->n0, nullptr, trace * sizeof(float)},
+        {p->f1p, nullptr, trace * sizeof(float)},
+        {p->f1m, nullptr, trace * sizeof(float)},
+        {p->X, nullptr, nf * B * (size_t)p->ns_pad * sizeof(float2)},   // the series' slab, any X storage
+        {p->xscale, nullptr, nf * sizeof(float)},
+        {p->norm0, nullptr, nf * sizeof(double)},
+        {p->gdnorm, nullptr, nf * sizeof(double)},
+        {p->nlast, nullptr, nf * sizeof(double)},
+        {p->norm_log, nullptr, (size_t)h.log_len * nf * sizeof(double)},
+        {nullptr, host_norms.data(), 2 * nf * sizeof(double)},          // norm0_host, gd_norm_host
+    };
+    if (h.has_hist) v.push_back({p->hist, nullptr, nf * nr * (size_t)h.hist_k * h.hist_T * sizeof(float)});
+    return v;
+}
+
+size_t state_size(mk_plan_t p, const StateHeader& h) {
+    std::vector<double> tmp;
+    size_t n = sizeof(StateHeader);
+    for (auto& part : state_parts(p, h, tmp)) n += part.bytes;
+    return n;
+}
+
+StateHeader state_header(mk_plan_t p) {
+    StateHeader h{};
+    std::memcpy(h.magic, kStateMagic, sizeof(h.magic));
+    h.nr = p->d.nr;
+    h.nt = p->d.nt;
+    h.iw_lo = p->d.iw_lo;
+    h.iw_hi = p->d.iw_hi;
+    h.ns_pad = p->ns_pad;
+    h.rprec = p->d.rprec;
+    h.flags = (int32_t)(p->d.flags & MK_FLAG_FAST_X);
+    h.nf = p->nf;
+    h.shift = p->shift;
+    h.passes = p->passes;
+    h.pass_base = p->pass_base;
+    h.tail_applied = p->tail_applied ? 1 : 0;
+    h.has_fband = p->has_fband ? 1 : 0;
+    h.variant = p->series_choice.variant;
+    h.xprec = p->series_choice.xprec;
+    h.log_len = p->log_len;
+    h.series_start = p->series_start;
+    h.prev_series_start = p->prev_series_start;
+    h.hist_k = p->hist_k;
+    h.hist_T = p->hist_T;
+    h.has_hist = p->hist ? 1 : 0;
+    return h;
+}
+
 bool tune_pending(mk_plan_t p) {
     if (p->tune_mode != -2) return false;
     for (auto& kv : p->tuned)
@@ -925,7 +1160,7 @@ mk_status mk_iterate_tol(mk_plan_t p, double tol, int32_t max_passes, int32_t* p
 mk_status mk_get(mk_plan_t p, int32_t field, float* out, int on_device) {
     if (!p) return fail(nullptr, MK_ERR_ARG, "mk_get: plan is NULL");
     if (!out) return fail(p, MK_ERR_ARG, "mk_get: out is NULL");
-    if (field < MK_F1PLUS || field > MK_PMINUS) return fail(p, MK_ERR_ARG, "mk_get: unknown field");
+    if (field < MK_F1PLUS || field > MK_GTOTAL) return fail(p, MK_ERR_ARG, "mk_get: unknown field");
     if (!p->focal_set) return fail(p, MK_ERR_STATE, "mk_get: no focal points set");
     const float* src = nullptr;
     switch (field) {
@@ -936,7 +1171,7 @@ mk_status mk_get(mk_plan_t p, int32_t field, float* out, int on_device) {
         default: break;
     }
     if ((field == MK_GPLUS || field == MK_GMINUS) && !p->g_valid) MK_TRY(assemble_G(p));
-    if (field == MK_F2PLUS || field == MK_PMINUS) {
+    if (field == MK_F2PLUS || field == MK_PMINUS || field == MK_GTOTAL) {
         MK_TRY(aux_field(p, field));
         src = p->aux;
     }
@@ -1116,7 +1351,7 @@ mk_status mk_tail_apply(mk_plan_t p, int32_t mode, double* rel_resid) {
     if (mode == 0 && net_tail_fused(k, p->tail_net_hidden)) {
         HIP_TRY(p, launch_tail_prep(p->hist, ntr, k, T, nullptr, p->tail_scale, p->stream));
         HIP_TRY(p, net_tail_apply(p->tail_w, p->tail_wpk, p->hist, p->tail_scale, p->itd, p->shift, ntr, k,
-                                  p->tail_net_hidden, T, nt, p->f1p, p->f1m, p->stream));
+                                  p->tail_net_hidden, T, nt, p->f1p, p->stream));
     } else if (mode == 0) {
         const int H = p->tail_net_hidden;
         const size_t act = (size_t)p->tail_chunk * H * T;
@@ -1127,10 +1362,10 @@ mk_status mk_tail_apply(mk_plan_t p, int32_t mode, double* rel_resid) {
             HIP_TRY(p, net_forward(p->tail_w, p->tail_x, n, k, H, T, p->tail_work, p->tail_work + act, p->tail_y,
                                    p->stream));
             HIP_TRY(p, launch_tail_apply(h, p->tail_y, p->tail_scale + c0, p->itd + c0, p->shift, n, k, T, nt, 0,
-                                         p->f1p + (size_t)c0 * nt, p->f1m + (size_t)c0 * nt, p->stream));
+                                         p->f1p + (size_t)c0 * nt, p->stream));
         }
     } else if (mode == 1) {
-        HIP_TRY(p, launch_tail_apply(p->hist, nullptr, nullptr, p->itd, p->shift, ntr, k, T, nt, 1, p->f1p, p->f1m,
+        HIP_TRY(p, launch_tail_apply(p->hist, nullptr, nullptr, p->itd, p->shift, ntr, k, T, nt, 1, p->f1p,
                                      p->stream));
     }
     // the judge: one fixed-point step f1+ <- G_d(-t) + A^2 f1+ (two syntheses),
@@ -1171,6 +1406,100 @@ mk_status mk_profile(mk_plan_t p, int32_t kind, double* total_ms, int64_t* launc
     if (total_ms) *total_ms = p->prof[kind].ms;
     if (launches) *launches = p->prof[kind].launches;
     if (reset) p->prof[kind] = ProfileSlot{};
+    return MK_OK;
+}
+
+mk_status mk_state_bytes(mk_plan_t p, size_t* bytes) {
+    if (!p || !bytes) return fail(p, MK_ERR_ARG, "mk_state_bytes: NULL argument");
+    if (!p->focal_set) return fail(p, MK_ERR_STATE, "mk_state_bytes: no focal points set");
+    *bytes = state_size(p, state_header(p));
+    return MK_OK;
+}
+
+mk_status mk_get_state(mk_plan_t p, void* blob, size_t bytes) {
+    if (!p || !blob) return fail(p, MK_ERR_ARG, "mk_get_state: NULL argument");
+    if (!p->focal_set) return fail(p, MK_ERR_STATE, "mk_get_state: no focal points set");
+    const StateHeader h = state_header(p);
+    if (bytes < state_size(p, h)) return fail(p, MK_ERR_ARG, "mk_get_state: blob smaller than mk_state_bytes");
+    std::vector<double> hn;
+    auto parts = state_parts(p, h, hn);
+    for (int j = 0; j < p->nf; ++j) {            // caller order, as the plan keeps them
+        hn[j] = p->norm0_host[j];
+        hn[p->nf + j] = p->gd_norm_host[j];
+    }
+    unsigned char* o = static_cast<unsigned char*>(blob);
+    std::memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    for (auto& part : parts) {
+        if (part.bytes == 0) continue;
+        if (part.dev)
+            HIP_TRY(p, hipMemcpyAsync(o, part.dev, part.bytes, hipMemcpyDeviceToHost, p->stream));
+        else
+            std::memcpy(o, part.host, part.bytes);
+        o += part.bytes;
+    }
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return MK_OK;
+}
+
+mk_status mk_set_state(mk_plan_t p, const void* blob, size_t bytes) {
+    if (!p || !blob) return fail(p, MK_ERR_ARG, "mk_set_state: NULL argument");
+    if (!p->R_loaded) return fail(p, MK_ERR_STATE, "mk_set_state: R has not been loaded");
+    StateHeader h;
+    if (bytes < sizeof(h)) return fail(p, MK_ERR_ARG, "mk_set_state: blob too small");
+    std::memcpy(&h, blob, sizeof(h));
+    if (std::memcmp(h.magic, kStateMagic, sizeof(h.magic)) != 0)
+        return fail(p, MK_ERR_ARG, "mk_set_state: not a state blob of this library");
+    if (h.nr != p->d.nr || h.nt != p->d.nt || h.iw_lo != p->d.iw_lo || h.iw_hi != p->d.iw_hi ||
+        h.ns_pad != p->ns_pad || h.rprec != p->d.rprec || h.flags != (int32_t)(p->d.flags & MK_FLAG_FAST_X))
+        return fail(p, MK_ERR_ARG, "mk_set_state: the blob was saved by a plan of another shape, band, "
+                                   "precision or X storage");
+    if (h.nf < 1 || h.nf > p->d.nf_max) return fail(p, MK_ERR_ARG, "mk_set_state: nf above this plan's nf_max");
+    if (h.variant < 0 || h.variant > contract_mfma_variants() || !variant_fits(p, h.variant) ||
+        xprec_of(p->d.rprec, h.variant, (p->d.flags & MK_FLAG_FAST_X) != 0) != h.xprec)
+        return fail(p, MK_ERR_ARG, "mk_set_state: the saved contraction choice cannot read this plan's R");
+    if (h.has_hist && (!p->hist || p->hist_k != h.hist_k || p->hist_T != h.hist_T))
+        return fail(p, MK_ERR_STATE, "mk_set_state: the saved series records iterates: call mk_tail_record "
+                                     "with the same k and T first");
+    if (h.log_len < 1 || h.series_start < 0 || h.series_start >= h.log_len || h.prev_series_start < 0 ||
+        h.prev_series_start > h.series_start || h.passes < h.pass_base || h.pass_base < 0)
+        return fail(p, MK_ERR_ARG, "mk_set_state: inconsistent counters in the blob");
+    if (bytes < state_size(p, h)) return fail(p, MK_ERR_ARG, "mk_set_state: blob truncated");
+    p->focal_set = false;
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    p->log_len = 0;                              // room for the saved norm log
+    MK_TRY(ensure_log_cap(p, h.log_len));
+    std::vector<double> hn;
+    auto parts = state_parts(p, h, hn);
+    const unsigned char* in = static_cast<const unsigned char*>(blob) + sizeof(h);
+    for (auto& part : parts) {
+        if (part.bytes == 0) continue;
+        if (part.dev)
+            HIP_TRY(p, hipMemcpyAsync(part.dev, in, part.bytes, hipMemcpyHostToDevice, p->stream));
+        else
+            std::memcpy(part.host, in, part.bytes);
+        in += part.bytes;
+    }
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    p->nf = h.nf;
+    p->shift = h.shift;
+    p->passes = h.passes;
+    p->pass_base = h.pass_base;
+    p->tail_applied = h.tail_applied != 0;
+    p->has_fband = h.has_fband != 0;
+    p->series_choice.variant = h.variant;
+    p->series_choice.xprec = h.xprec;
+    p->g_choice = choose(p, 2 * h.nf);
+    p->log_len = h.log_len;
+    p->series_start = h.series_start;
+    p->prev_series_start = h.prev_series_start;
+    p->norm0_host.assign(hn.begin(), hn.begin() + h.nf);
+    p->gd_norm_host.assign(hn.begin() + h.nf, hn.end());
+    std::vector<int32_t> perm(h.nf);
+    std::memcpy(perm.data(), static_cast<const unsigned char*>(blob) + sizeof(h), h.nf * sizeof(int32_t));
+    p->perm_host.assign(perm.begin(), perm.end());
+    p->g_valid = false;
+    p->focal_set = true;
     return MK_OK;
 }
 

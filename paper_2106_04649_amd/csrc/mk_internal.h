@@ -116,6 +116,18 @@ struct mk_plan_s {
     double* norm_log = nullptr;
     int log_cap = 0, log_len = 0, series_start = 0, prev_series_start = 0;
     double* fnorm = nullptr;   // [2 nf_max] ||f1+||, ||f1-|| for the stopping rule
+    // R streamed from pinned host memory (r_dev_bytes below the size of R):
+    // the whole of R in the device layout on the host, two device buffers of
+    // slab_bins bins each, a copy stream and the events that order the ring
+    bool r_stream = false;
+    unsigned char* R_host = nullptr;
+    void* rbuf[2] = {nullptr, nullptr};
+    size_t bin_bytes = 0;      // bytes of one bin of R in the device layout
+    int slab_bins = 0, nslabs = 0;
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_copied[2] = {nullptr, nullptr}, ev_consumed[2] = {nullptr, nullptr};
+    int buf_slab[2] = {-1, -1};  // slab each buffer holds (or is receiving)
+    int64_t slab_use = 0;        // slab contractions so far; use u reads buffer u % 2
     float2* tw = nullptr;      // [nt + 256]
     int* flag = nullptr;       // device scratch flag (non-finite input detection)
     float* n0 = nullptr;       // [nf_max][nr][nt] N_-1 = G_d(-t)
@@ -198,6 +210,8 @@ struct ContractArgs {
     int xsplit;            // 16-bit X held as hi and lo planes (two products)
     int tiled;             // R in the LDS-staged contraction's tiles
     int nr, ns, ns_pad, B, ncols;
+    int nb;                // bins this launch covers (R, rscale, X, Y, ncols_w start at its first bin;
+                           // X and Y keep the B-bin strides of the whole band)
 };
 
 // kernel launchers (return hipSuccess or the launch error)
@@ -207,6 +221,8 @@ hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out,
 hipError_t launch_sumsq(const float* x, int ntr, int nt, double* npart, hipStream_t s);
 // out = f1p(t) - f1m(-t) per trace (f2+)
 hipError_t launch_f2p(const float* f1p, const float* f1m, int64_t ntr, int nt, float* out, hipStream_t s);
+// out = gp + gm elementwise (the total G)
+hipError_t launch_gsum(const float* gp, const float* gm, int64_t n, float* out, hipStream_t s);
 // out[f] = scale * sum_r sum_k gm[f][r][k] f1p[f][r][(-k) mod nt] (FP64); part holds nf * nr doubles
 hipError_t launch_image(const float* gm, const float* f1p, int nf, int nr, int nt, double scale, double* part,
                         double* out, hipStream_t s);
@@ -236,8 +252,9 @@ bool contract_variant_reads_tiled(int variant);
 hipError_t launch_check_finite(const float* x, int64_t n, int* flag, hipStream_t s);
 // x may be NULL: then only the per-trace scales are written
 hipError_t launch_tail_prep(const float* hist, int ntr, int k, int T, float* x, float* scale, hipStream_t s);
+// the odd-pass tail into f1+ (the restart that follows rebuilds f1- from f1+)
 hipError_t launch_tail_apply(const float* hist, const float* y, const float* scale, const int32_t* itd, int shift,
-                             int ntr, int k, int T, int nt, int mode, float* f1p, float* f1m, hipStream_t s);
+                             int ntr, int k, int T, int nt, int mode, float* f1p, hipStream_t s);
 
 // series-tail network (k -> H -> H -> 2 channels, 5 taps, H hidden channels)
 constexpr int kNetHiddenMax = 128;      // widest hidden layer the ABI accepts
@@ -253,7 +270,7 @@ size_t net_tail_pack_bytes(int k);
 hipError_t net_tail_pack(const float* P, int k, int H, void* out, hipStream_t s);
 hipError_t net_tail_apply(const float* P, const void* wpack, const float* hist, const float* scale,
                           const int32_t* itd, int shift, int ntr, int k, int H, int T, int nt, float* f1p,
-                          float* f1m, hipStream_t s);
+                          hipStream_t s);
 hipError_t net_backward(const float* P, const float* x, const float* a1, const float* a2, const float* gy,
                         int N, int k, int H, int T, float* G, float* g1, float* g2, float* wt, hipStream_t s);
 hipError_t net_mse(const float* y, const float* tgt, const float* mask, int N, int T, float* gy,

@@ -23,10 +23,10 @@ LIB_PATH = os.path.join(HERE, "libmk.so")
 
 MK_OK, MK_ERR_ARG, MK_ERR_STATE, MK_ERR_OOM, MK_ERR_HIP, MK_ERR_UNSUPPORTED, MK_ERR_DIVERGED = range(7)
 MK_R_C64, MK_R_F16S, MK_R_BF16S = 0, 1, 2
-MK_F1PLUS, MK_F1MINUS, MK_GPLUS, MK_GMINUS, MK_F2PLUS, MK_PMINUS = 0, 1, 2, 3, 4, 5
+MK_F1PLUS, MK_F1MINUS, MK_GPLUS, MK_GMINUS, MK_F2PLUS, MK_PMINUS, MK_GTOTAL = 0, 1, 2, 3, 4, 5, 6
 MK_FLAG_GRAPH, MK_FLAG_PROFILE, MK_FLAG_AUTOTUNE, MK_FLAG_FAST_X, MK_FLAG_ROW_R = 0x1, 0x2, 0x4, 0x8, 0x10
 FIELDS = {"f1plus": MK_F1PLUS, "f1minus": MK_F1MINUS, "Gplus": MK_GPLUS, "Gminus": MK_GMINUS,
-          "f2plus": MK_F2PLUS, "pminus": MK_PMINUS}
+          "f2plus": MK_F2PLUS, "pminus": MK_PMINUS, "Gtotal": MK_GTOTAL}
 KERNEL_KINDS = {"contract": 0, "epilogue": 1, "norms": 2, "init": 3, "gassembly": 4, "image": 5}
 
 
@@ -44,6 +44,7 @@ class mk_plan_desc(ctypes.Structure):
         ("rprec", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
         ("stream", ctypes.c_void_p),
+        ("r_dev_bytes", ctypes.c_int64),
     ]
 
 
@@ -80,6 +81,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mk_profile": (i32, [P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                              ctypes.c_int]),
         "mk_destroy": (i32, [P]),
+        "mk_state_bytes": (i32, [P, ctypes.POINTER(ctypes.c_size_t)]),
+        "mk_get_state": (i32, [P, P, ctypes.c_size_t]),
+        "mk_set_state": (i32, [P, P, ctypes.c_size_t]),
         "mk_tail_record": (i32, [P, i32, i32]),
         "mk_tail_load": (i32, [P, P, i32]),
         "mk_tail_history": (i32, [P, P, ctypes.c_int]),
@@ -164,12 +168,14 @@ class Plan:
 
 def mk_plan(nr: int, ns: int, nt: int, dt: float, dx: float, band: Optional[Tuple[int, int]] = None,
             nf_max: int = 1, rprec: int = MK_R_C64, flags: int = 0, div_factor: float = 0.0,
-            stream: Optional[int] = None) -> Plan:
+            stream: Optional[int] = None, r_dev_bytes: int = 0) -> Plan:
+    """r_dev_bytes > 0 caps the device memory holding R (below R's size, R is
+    streamed from pinned host memory in slabs of frequency bins)."""
     lib = load_library()
     lo, hi = band if band is not None else (0, nt // 2)
     if stream is None:
         stream = _current_stream()
-    d = mk_plan_desc(nr, ns, nt, lo, hi, nf_max, dt, dx, div_factor, rprec, flags, stream)
+    d = mk_plan_desc(nr, ns, nt, lo, hi, nf_max, dt, dx, div_factor, rprec, flags, stream, int(r_dev_bytes))
     h = ctypes.c_void_p()
     _check(lib.mk_plan(ctypes.byref(d), ctypes.byref(h)), None)
     return Plan(h.value, d)
@@ -288,6 +294,24 @@ def mk_profile(plan: Plan, kind, reset: bool = False) -> Tuple[float, int]:
     _check(load_library().mk_profile(plan.handle, k, ctypes.byref(ms), ctypes.byref(n), int(reset)),
            plan.handle)
     return ms.value, n.value
+
+
+def mk_get_state(plan: Plan) -> bytes:
+    """The current series' state as an opaque blob (checkpoint)."""
+    lib = load_library()
+    n = ctypes.c_size_t()
+    _check(lib.mk_state_bytes(plan.handle, ctypes.byref(n)), plan.handle)
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib.mk_get_state(plan.handle, buf, n.value), plan.handle)
+    return buf.raw
+
+
+def mk_set_state(plan: Plan, blob: bytes) -> None:
+    """Resume the series saved by mk_get_state (same plan shape, R loaded)."""
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    _check(load_library().mk_set_state(plan.handle, buf, len(blob)), plan.handle)
+    # the blob's header: 8 magic bytes, then int32 nr, nt, iw_lo, iw_hi, ns_pad, rprec, flags, nf, ...
+    plan.nf = int.from_bytes(bytes(blob)[36:40], "little", signed=True)
 
 
 def mk_destroy(plan: Plan) -> None:

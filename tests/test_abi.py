@@ -44,7 +44,7 @@ def test_strerror(lib):
 
 def _desc(**kw):
     base = dict(nr=8, ns=8, nt=64, iw_lo=0, iw_hi=32, nf_max=1, dt=0.004, dx=10.0, div_factor=0.0,
-                rprec=0, flags=0, stream=None)
+                rprec=0, flags=0, stream=None, r_dev_bytes=0)
     base.update(kw)
     return mk.mk_plan_desc(*[base[f] for f, _ in mk.mk_plan_desc._fields_])
 
@@ -65,6 +65,10 @@ def _desc(**kw):
     (dict(div_factor=float("nan")), mk.MK_ERR_ARG),
     (dict(rprec=7), mk.MK_ERR_ARG),
     (dict(flags=0x100), mk.MK_ERR_ARG),
+    # streamed R: a cap below two bins of R (one bin is 8 x 32 complex64 = 2 KiB)
+    (dict(r_dev_bytes=4095), mk.MK_ERR_ARG),
+    (dict(r_dev_bytes=8192, flags=0x1), mk.MK_ERR_UNSUPPORTED),      # with graph replay
+    (dict(r_dev_bytes=8192, flags=0x4), mk.MK_ERR_UNSUPPORTED),      # with the autotuner
 ])
 def test_plan_rejects_bad_descriptions(lib, kw, status):
     d = _desc(**kw)
@@ -133,3 +137,11 @@ def test_binding_checks_shapes_before_the_library_reads():
         mk.mk_tail_history(plan, np.zeros((2, 8, 4, 16), np.float64))
     with pytest.raises(TypeError):
         mk.mk_tail_history(plan, np.zeros((2, 8, 16, 4), np.float32).transpose(0, 1, 3, 2))
+
+
+def test_state_calls_reject_null_arguments(lib):
+    n = ctypes.c_size_t()
+    assert lib.mk_state_bytes(None, ctypes.byref(n)) == mk.MK_ERR_ARG
+    buf = ctypes.create_string_buffer(64)
+    assert lib.mk_get_state(None, buf, 64) == mk.MK_ERR_ARG
+    assert lib.mk_set_state(None, buf, 64) == mk.MK_ERR_ARG
