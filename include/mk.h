@@ -322,6 +322,19 @@ mk_status mk_net_backward(const float* params, const float* x, const float* work
 mk_status mk_net_loss(const float* y, const float* target, const float* mask, int32_t N, int32_t T,
                       float count, float* gy, double* loss, double* part, int32_t nparts, void* stream);
 
+/* mk_net_loss_noalloc -- mk_net_loss without the caller's scratch buffer,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc).  It allocates nothing: the nparts FP64 partial sums go to a
+ * fixed array inside the library (1024 doubles per GPU, held until the
+ * process ends).  Same arguments, results and stream ordering as
+ * mk_net_loss with the same nparts (the same kernels, so the same bits).
+ * Calls that overlap on one GPU (two streams, or two threads) share that
+ * array and race; order them on one stream.  Errors: MK_ERR_ARG (NULL, bad
+ * sizes, nparts outside [1, 1024]), MK_ERR_HIP. */
+mk_status mk_net_loss_noalloc(const float* y, const float* target, const float* mask, int32_t N, int32_t T,
+                              float count, float* gy, double* loss, int32_t nparts, void* stream);
+
 /* One Adam step (Kingma and Ba) with bias correction on FP32 master weights
  * w with moments m, v; writes the BF16-rounded weights to wq. */
 mk_status mk_net_adam(float* w, float* wq, const float* g, float* m, float* v, int32_t n, int32_t step,

@@ -1,6 +1,15 @@
 // C ABI of the series-tail network kernels (training and inference on
 // caller-owned device buffers).
+#include <mutex>
+
 #include "mk_internal.h"
+
+// Partial sums of mk_net_loss_noalloc: one double per block of the loss
+// kernel.  Every GPU the library runs on holds its own copy until the process
+// ends; the host side reaches it only through the per-device address below
+// (the array's own name is not a device address in host code).
+constexpr int kLossScratchParts = 1024;
+static __device__ __align__(256) double scratch[kLossScratchParts];
 
 namespace {
 thread_local std::string g_net_error;
@@ -17,6 +26,29 @@ mk_status net_hip(hipError_t e, const char* where) {
 
 bool net_dims_ok(int N, int k, int T) { return N >= 1 && k >= 1 && k <= 16 && T >= 1 && T <= 4096; }
 bool hidden_ok(int H) { return H >= 1 && H <= kNetHiddenMax; }
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+mk_status scratch_on_current_device(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return net_hip(e, "mk_net_loss_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return net_fail(MK_ERR_UNSUPPORTED, "mk_net_loss_noalloc: device index");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return net_hip(e, "mk_net_loss_noalloc: hipGetSymbolAddress");
+        if (!ptr) return net_fail(MK_ERR_HIP, "mk_net_loss_noalloc: no address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return MK_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -57,6 +89,22 @@ mk_status mk_net_loss(const float* y, const float* target, const float* mask, in
     if (!net_dims_ok(N, 1, T) || !(count > 0.f)) return net_fail(MK_ERR_ARG, "mk_net_loss: bad N, T or count");
     return net_hip(net_mse(y, target, mask, N, T, gy, part, nparts, loss, count, (hipStream_t)stream),
                    "mk_net_loss");
+}
+
+mk_status mk_net_loss_noalloc(const float* y, const float* target, const float* mask, int32_t N, int32_t T,
+                              float count, float* gy, double* loss, int32_t nparts, void* stream) {
+    if (!y || !target || !mask || !gy || !loss) return net_fail(MK_ERR_ARG, "mk_net_loss_noalloc: NULL pointer");
+    if (nparts < 1 || nparts > kLossScratchParts)
+        return net_fail(MK_ERR_ARG, "mk_net_loss_noalloc: nparts must be in [1, " +
+                                        std::to_string(kLossScratchParts) + "]");
+    if (!net_dims_ok(N, 1, T) || !(count > 0.f))
+        return net_fail(MK_ERR_ARG, "mk_net_loss_noalloc: bad N, T or count");
+    double* part = nullptr;
+    const mk_status st = scratch_on_current_device(&part);
+    if (st != MK_OK) return st;
+    // every block of the loss kernel writes its own partial: nothing to clear
+    return net_hip(net_mse(y, target, mask, N, T, gy, part, nparts, loss, count, (hipStream_t)stream),
+                   "mk_net_loss_noalloc");
 }
 
 mk_status mk_net_adam(float* w, float* wq, const float* g, float* m, float* v, int32_t n, int32_t step, float lr,

@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mk_net_forward": (i32, [P, P, i32, i32, i32, i32, P, P, P]),
         "mk_net_backward": (i32, [P, P, P, P, i32, i32, i32, i32, P, P, P]),
         "mk_net_loss": (i32, [P, P, P, i32, i32, ctypes.c_float, P, P, P, i32, P]),
+        "mk_net_loss_noalloc": (i32, [P, P, P, i32, i32, ctypes.c_float, P, P, i32, P]),
         "mk_net_adam": (i32, [P, P, P, P, P, i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, P]),
         "mk_net_round": (i32, [P, P, i32, P]),
@@ -406,6 +407,15 @@ def mk_net_loss(y, target, mask, count, gy, loss, part, stream=None) -> None:
     s = _current_stream() if stream is None else stream
     _net_check(load_library().mk_net_loss(_dev(y), _dev(target), _dev(mask), N, T, float(count), _dev(gy),
                                           _dev(loss, "float64"), _dev(part, "float64"), part.numel(), s))
+
+
+def mk_net_loss_noalloc(y, target, mask, count, gy, loss, nparts=256, stream=None) -> None:
+    """mk_net_loss with the partial sums in the library's fixed scratch array
+    (no buffer from the caller, nothing allocated; nparts <= 1024)."""
+    N, _, T = y.shape
+    s = _current_stream() if stream is None else stream
+    _net_check(load_library().mk_net_loss_noalloc(_dev(y), _dev(target), _dev(mask), N, T, float(count),
+                                                  _dev(gy), _dev(loss, "float64"), int(nparts), s))
 
 
 def mk_net_adam(w, wq, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None) -> None:
