@@ -422,8 +422,9 @@ mk_status mk_set_state(mk_plan_t plan, const void* blob, size_t bytes);
 
 mk_status mk_destroy(mk_plan_t plan);
 
-/* mk_strerror -- static description of a status code. */
-const char* mk_strerror(mk_status status);
+/* mk_strerror -- static description of a status code (an mk_status value;
+ * any other value gives "unknown status"). */
+const char* mk_strerror(int32_t status);
 
 /* mk_last_error -- message of the plan's last failure ("" if none); with a
  * NULL plan, the message of the last failed mk_plan on this thread. */

@@ -1,9 +1,12 @@
 """Build libmk.so (the HIP kernels and the C ABI) in-tree for gfx950.
 
-    python -m paper_2106_04649_amd.build
+    python -m paper_2106_04649_amd.build            # libmk.so
+    python -m paper_2106_04649_amd.build --asan     # _build/asan/libmk_asan.so
 
 Each source compiles on its own (in parallel) and the objects are linked
-into ``paper_2106_04649_amd/libmk.so``.  The build always recompiles.
+into ``paper_2106_04649_amd/libmk.so``.  The build always recompiles.  The
+sanitizer build instruments the host code with AddressSanitizer and
+UndefinedBehaviorSanitizer, for the host-side checks in tests/.
 """
 
 from __future__ import annotations
@@ -70,9 +73,43 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(verbose: bool = False) -> str:
+    """The library with AddressSanitizer and UndefinedBehaviorSanitizer on its
+    host code (device code unchanged in kind, built at -O1 with debug info):
+    ``_build/asan/libmk_asan.so``, for host-side checks without a GPU.  The
+    sanitizer flags apply to the host compilation only."""
+    out = os.path.join(BUILD, "asan")
+    os.makedirs(out, exist_ok=True)
+    host = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+    flags = [f if f != "-O3" else "-O1" for f in common_flags()] + ["-g"] + host
+
+    def one(src: str) -> str:
+        obj = os.path.join(out, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc(), *flags, "-c", os.path.join(CSRC, src), "-o", obj]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"compile of {src} failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+        return obj
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(one, SOURCES))
+    lib = os.path.join(out, "libmk_asan.so")
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", lib]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    if verbose:
+        print(f"built {lib}")
+    return lib
+
+
 if __name__ == "__main__":
     try:
-        build(verbose=True)
+        if "--asan" in sys.argv[1:]:
+            build_sanitized(verbose=True)
+        else:
+            build(verbose=True)
     except RuntimeError as exc:
         print(exc, file=sys.stderr)
         sys.exit(1)

@@ -108,6 +108,18 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
 #pragma unroll
         for (int b = 0; b < WN; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
+    // output scales of this lane's focal columns, loaded before the K loop so
+    // that the stores at the end wait for nothing (a load inside the
+    // conditional store loop is waited for one at a time)
+    float osc[WM][2];
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int f = min(((n0 + 16 * a + 4 * g) >> 1) + h, nfc - 1);
+            osc[a][h] = PREC == MK_R_C64 ? 1.f : rscale[w] * xscale[f];
+        }
+
     int cfl[WM];
     bool xok[WM];
     bool rok[WN];
@@ -203,7 +215,6 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
     }
 
     // D rows n0 + 16a + 4g + v (v = 0..3) are (Re, Im) of focal f0 and f0 + 1
-    const float rs = PREC == MK_R_C64 ? 1.f : rscale[w];
 #pragma unroll
     for (int a = 0; a < WM; ++a) {
         const int f0 = (n0 + 16 * a + 4 * g) >> 1;
@@ -215,7 +226,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
             for (int h = 0; h < 2; ++h) {
                 const int f = f0 + h;
                 if (f >= nact) continue;
-                const float sc = PREC == MK_R_C64 ? 1.f : rs * xscale[f];
+                const float sc = osc[a][h];
                 Y[((int64_t)f * B + w) * nr + r] = make_float2(acc[a][b][2 * h] * sc, acc[a][b][2 * h + 1] * sc);
             }
         }
@@ -377,6 +388,15 @@ __global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
+    // output scales of this lane's focal columns (fbase + 8a + 2g + h),
+    // loaded before the chunk loop: the stores at the end wait for nothing
+    float osc[RA][2];
+#pragma unroll
+    for (int a = 0; a < RA; ++a)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            osc[a][h] = C64 ? 1.f : rscale[w] * xscale[min(fbase + 8 * a + 2 * g + h, nfc - 1)];
+
     // one K step: lane (i16, g) reads LDS row 16 a + i16 of each plane (focal
     // 8 a + i16 / 2 in form i16 % 2) at byte offset off; B from bv.  All A
     // fragments are read first and the products run plane by plane (or K
@@ -505,7 +525,6 @@ __global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
     if (r0 >= nr) return;
 
     // D rows 16a + 4g + v (v = 0..3) are (Re, Im) of focal fbase + 8a + 2g and the next one
-    const float rs = C64 ? 1.f : rscale[w];
 #pragma unroll
     for (int a = 0; a < RA; ++a) {
         const int f0 = fbase + 8 * a + 2 * g;
@@ -517,7 +536,7 @@ __global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
             for (int h = 0; h < 2; ++h) {
                 const int f = f0 + h;
                 if (f >= nact) continue;
-                const float sc = C64 ? 1.f : rs * xscale[f];
+                const float sc = osc[a][h];
                 Y[((int64_t)f * B + w) * nr + r] = make_float2(acc[a][b][2 * h] * sc, acc[a][b][2 * h + 1] * sc);
             }
         }

@@ -626,8 +626,9 @@ mk_status load_R_streamed(mk_plan_t p, const float* R, int on_device) {
 
 extern "C" {
 
-const char* mk_strerror(mk_status status) {
-    const int i = (int)status;
+const char* mk_strerror(int32_t status) {
+    // an int, not the enum: a caller may pass a value no enumerator names
+    const int i = status;
     if (i < 0 || i >= (int)(sizeof(kStatusText) / sizeof(kStatusText[0]))) return "unknown status";
     return kStatusText[i];
 }
