@@ -445,9 +445,11 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     const int tr = blockIdx.x;
     const int t0 = blockIdx.y * kFT;
     const int hT = T >> 1;
-    // the loads of the block go out before the window test that needs itd,
-    // so that they are in flight together (a skipped tile wastes them)
+    // a tile that shares no sample with the mute window |t| < L leaves before
+    // it loads anything (one round trip for itd first; the other blocks on
+    // the CU cover it)
     const int L = itd[tr] - shift;
+    if (L <= 0 || t0 >= hT + L || t0 + kFT <= hT - L + 1) return;
     const float se = scale[tr];
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int i16 = lane & 15, g = lane >> 4;
@@ -501,8 +503,6 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     float pv[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) pv[m] = fp[f1_ip(m)];
-    // window samples u = t + T/2 with |t| < L
-    if (L <= 0 || t0 >= hT + L || t0 + kFT <= hT - L + 1) return;
     const float inv = se > 0.f ? 1.f / se : 0.f;
     // output samples s = u - t0 of this tile the tail is used at: [lo3, hi3]
     // (not empty: the window test passed); layer 2 is needed on [lo3, hi3 + 64]

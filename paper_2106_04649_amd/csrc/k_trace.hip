@@ -1013,14 +1013,30 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
 }
 
 // Sum of squares of each trace (FP64), one wave per trace: the norm of G_d.
-__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ x, int ntr, int nt,
-                                               double* __restrict__ npart) {
+// FP64 sum of squares of every trace: npart[j] for trace j of x0 (j < n0)
+// and for trace j - n0 of x1 (j >= n0), so two fields reduce in one launch.
+// One wave per trace, 16-byte loads, eight of a lane's loads in flight
+// together (addresses clamped, out-of-range values dropped after the load).
+__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ x0, const float* __restrict__ x1, int n0,
+                                               int ntr, int nt, double* __restrict__ npart) {
     const int lane = threadIdx.x & 63;
     const int trace = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (trace >= ntr) return;
-    const float* p = x + (size_t)trace * nt;
+    const float4* p = reinterpret_cast<const float4*>(trace < n0 ? x0 + (size_t)trace * nt
+                                                                 : x1 + (size_t)(trace - n0) * nt);
+    const int n4 = nt >> 2;
     double acc = 0.0;
-    for (int t = lane; t < nt; t += 64) acc += (double)p[t] * p[t];
+    for (int i0 = 0; i0 < n4; i0 += 64 * 8) {
+        float4 v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = p[min(i0 + lane + 64 * j, n4 - 1)];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const double w = i0 + lane + 64 * j < n4 ? 1.0 : 0.0;
+            acc += w * ((double)v[j].x * v[j].x + (double)v[j].y * v[j].y + (double)v[j].z * v[j].z +
+                        (double)v[j].w * v[j].w);
+        }
+    }
     acc = wave_sum_d(acc);
     if (lane == 0) npart[trace] = acc;
 }
@@ -1176,7 +1192,13 @@ hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out,
 
 hipError_t launch_sumsq(const float* x, int ntr, int nt, double* npart, hipStream_t s) {
     if (ntr <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sumsq, dim3((ntr + 3) / 4), dim3(256), 0, s, x, ntr, nt, npart);
+    hipLaunchKernelGGL(k_sumsq, dim3((ntr + 3) / 4), dim3(256), 0, s, x, x, ntr, ntr, nt, npart);
+    return hipGetLastError();
+}
+
+hipError_t launch_sumsq2(const float* x0, const float* x1, int ntr, int nt, double* npart, hipStream_t s) {
+    if (ntr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sumsq, dim3((2 * ntr + 3) / 4), dim3(256), 0, s, x0, x1, ntr, 2 * ntr, nt, npart);
     return hipGetLastError();
 }
 

@@ -467,8 +467,7 @@ RestEstimate estimate_rest(const double* a, int n, double q_prior) {
 // every estimate is within tol, -1 when some q is not known yet).
 mk_status judge_series(mk_plan_t p, double tol, std::vector<double>& est, int* more) {
     const int nf = p->nf, nr = p->d.nr, nt = p->d.nt;
-    HIP_TRY(p, launch_sumsq(p->f1p, nf * nr, nt, p->npart, p->stream));
-    HIP_TRY(p, launch_sumsq(p->f1m, nf * nr, nt, p->npart + (size_t)nf * nr, p->stream));
+    HIP_TRY(p, launch_sumsq2(p->f1p, p->f1m, nf * nr, nt, p->npart, p->stream));
     HIP_TRY(p, launch_norm_reduce(p->npart, nr, 2 * nf, p->fnorm, nullptr, p->stream));
     std::vector<double> fn(2 * (size_t)nf), log((size_t)p->log_len * nf);
     HIP_TRY(p, hipMemcpyAsync(fn.data(), p->fnorm, fn.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));

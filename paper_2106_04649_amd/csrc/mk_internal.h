@@ -219,6 +219,8 @@ hipError_t launch_trace(int mode, int nt, const TraceArgs& a, hipStream_t s);
 hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out, double* out2,
                               hipStream_t s);
 hipError_t launch_sumsq(const float* x, int ntr, int nt, double* npart, hipStream_t s);
+// the sums of squares of two fields of ntr traces each in one launch: npart [2 ntr]
+hipError_t launch_sumsq2(const float* x0, const float* x1, int ntr, int nt, double* npart, hipStream_t s);
 // out = f1p(t) - f1m(-t) per trace (f2+)
 hipError_t launch_f2p(const float* f1p, const float* f1m, int64_t ntr, int nt, float* out, hipStream_t s);
 // out = gp + gm elementwise (the total G)
