@@ -336,7 +336,11 @@ def mixed_leg(args) -> dict:
     out = {"workload": "601x601, nt=2048, 512 focal points at 200-1200 m, per-focal bands of 20-80 % of "
                        "Nyquist, 32 passes + G assembly",
            "nf": pm.nf, "mean_band_bins": float(widths.mean()), "sampled_focal_points": sample, "paths": {}}
-    for name, rprec, flags in (("fp16_graph", 1, mk.MK_FLAG_GRAPH), ("fp32", 0, 0)):
+    # fp16_graph: the banded plan's default, the contraction as a persistent
+    # kernel walking the active tiles; fp16_graph_grid: one block per tile
+    # (MK_FLAG_GRID), the form the walk replaces
+    for name, rprec, flags in (("fp16_graph", 1, mk.MK_FLAG_GRAPH),
+                               ("fp16_graph_grid", 1, mk.MK_FLAG_GRAPH | mk.MK_FLAG_GRID), ("fp32", 0, 0)):
         r = Runner(pm, rprec=rprec, flags=flags, niter=pm.niter)
         wall = r.time(args.steps, args.warmup)
         r.norms()
@@ -349,8 +353,8 @@ def mixed_leg(args) -> dict:
                               "max_rel_l2_vs_oracle": {k: float(f"{v:.3e}") for k, v in err.items()}}
         log(f"mixed {name}: {out['paths'][name]['ms_per_step']} ms per solve, worst error "
             f"{max(err.values()):.2e}")
-    out["fp16_graph_over_fp32"] = round(out["paths"]["fp32"]["ms_per_step"] /
-                                        out["paths"]["fp16_graph"]["ms_per_step"], 3)
+    for name in ("fp16_graph", "fp16_graph_grid"):
+        out[f"{name}_over_fp32"] = round(out["paths"]["fp32"]["ms_per_step"] / out["paths"][name]["ms_per_step"], 3)
     if not args.no_profile:
         avg_s, _, variant = profile_contract(pm, 1)
         # algorithmic bytes and flops over the active (focal, bin) pairs only:

@@ -80,6 +80,17 @@ typedef enum {
 #define MK_FLAG_FAST_X   0x8u  /* 16-bit R on matrix cores: one 16-bit plane of X
                                   instead of the default hi + lo planes (half the
                                   products, about 2x the rounding error)        */
+#define MK_FLAG_WALK     0x20u /* run the LDS-staged contraction (variants 6..8)
+                                  as a persistent kernel that walks a list of
+                                  its active tiles, spread evenly over the
+                                  XCDs, also without per-focal bands (with
+                                  bands the plan walks by default); not with
+                                  MK_FLAG_AUTOTUNE, MK_FLAG_GRID or streamed R */
+#define MK_FLAG_GRID     0x40u /* launch one block per tile of the LDS-staged
+                                  contraction even with per-focal bands (out-of-
+                                  band tiles then exit at once): the form the
+                                  walk replaces, kept for comparison; not with
+                                  MK_FLAG_WALK                                 */
 #define MK_FLAG_ROW_R    0x10u /* keep R frequency-major and row-major even when
                                   nf_max > 4 (by default such plans store R in
                                   the tiles of the LDS-staged matrix-core
@@ -126,8 +137,8 @@ typedef struct {
  * [16, 4096], band outside [0, nt/2], nf_max < 1, dt or dx not positive,
  * unknown rprec or flag, r_dev_bytes positive but below two bins of R),
  * MK_ERR_UNSUPPORTED (ns > 2048 with MK_R_C64, ns > 4096, MK_FLAG_GRAPH or
- * MK_FLAG_AUTOTUNE with streamed R), MK_ERR_OOM, MK_ERR_HIP.  *out is NULL
- * on failure.
+ * MK_FLAG_AUTOTUNE with streamed R, MK_FLAG_WALK with MK_FLAG_AUTOTUNE or
+ * streamed R), MK_ERR_OOM, MK_ERR_HIP.  *out is NULL on failure.
  */
 mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out);
 

@@ -273,7 +273,7 @@ template <int... J, typename F>
 __device__ __forceinline__ void for_each_index(std::integer_sequence<int, J...>, F&& f) {
     (f(std::integral_constant<int, J>{}), ...);
 }
-constexpr int kLdsRcv = 256;        // receivers per block
+constexpr int kLdsRcv = kLdsTileReceivers;   // receivers per block
 
 // both embedding forms of a 16-byte X vector: form 0 (Re, -Im), form 1 (Im, Re)
 template <bool C64>
@@ -287,14 +287,23 @@ __device__ __forceinline__ void x_forms(v4u x, v4u& f0, v4u& f1) {
     }
 }
 
-// RA = 8 needs more than half the register file (one wave per SIMD);
-// smaller tiles run two waves per SIMD.
+// LDS bytes of one block of the LDS-staged tiles
+template <int PREC, int RA, bool SPLIT>
+constexpr int lds_tile_bytes() {
+    constexpr int ROWS = 8 * RA * (SPLIT ? 2 : 1);
+    return (RA >= 8 ? 4 : 3) * 2 * ROWS * (kChunkBytes + 16);
+}
+
+// One tile of the LDS-staged contraction: tile index t = (w * rtiles + rt)
+// * ftiles + ft, on the block's LDS.  Every thread of the block calls it
+// with the same t; it returns early (block-uniformly) when the tile's focal
+// columns are past the bin's active count.
 template <int PREC, int RA, bool SPLIT, bool TILED>
-__global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
+__device__ __forceinline__ void contract_lds_tile(
     const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
     const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
-    int ncols_mul, int nr, int ns_pad, int B, int nfc, int ftiles, int rtiles, int64_t ntiles,
-    int64_t per_xcd) {
+    int ncols_mul, int nr, int ns_pad, int B, int nfc, int ftiles, int rtiles, int64_t t,
+    unsigned char* __restrict__ lds) {
     constexpr bool C64 = PREC == MK_R_C64;
     constexpr int PLANES = SPLIT ? 2 : 1;
     constexpr int NFB = 8 * RA;                   // focal columns per block
@@ -310,13 +319,9 @@ __global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
     // RA = 8 (one wave per SIMD) puts a barrier after every other chunk, which
     // takes four LDS buffers; the others close every chunk with one (three)
     constexpr bool PAIRED = RA >= 8;
-    __shared__ __attribute__((aligned(16))) unsigned char lds[(PAIRED ? 4 : 3) * BUFB];
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int64_t bid = blockIdx.x;
-    const int64_t t = (bid & 7) * per_xcd + (bid >> 3);
-    if (t >= ntiles) return;
     const int ft = (int)(t % ftiles);
     const int64_t t2 = t / ftiles;
     const int rt = (int)(t2 % rtiles);
@@ -543,12 +548,62 @@ __global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
     }
 }
 
+// RA = 8 needs more than half the register file (one wave per SIMD);
+// smaller tiles run two waves per SIMD.  Grid form: one block per tile,
+// tiles dealt to the 8 XCDs in contiguous runs (focal tiles fastest, so the
+// focal tiles that share an R tile meet in one L2).
+template <int PREC, int RA, bool SPLIT, bool TILED>
+__global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
+    const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
+    const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
+    int ncols_mul, int nr, int ns_pad, int B, int nfc, int ftiles, int rtiles, int64_t ntiles,
+    int64_t per_xcd) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[lds_tile_bytes<PREC, RA, SPLIT>()];
+    const int64_t bid = blockIdx.x;
+    const int64_t t = (bid & 7) * per_xcd + (bid >> 3);
+    if (t >= ntiles) return;
+    contract_lds_tile<PREC, RA, SPLIT, TILED>(Rv, rscale, Xv, xscale, Y, ncols_w, ncols_mul, nr, ns_pad, B, nfc,
+                                              ftiles, rtiles, t, lds);
+}
+
+// Persistent form: a fixed grid (every block resident at once) walks a list
+// of the active tiles -- those whose focal columns some focal point's band
+// reaches at their bin -- so bins past most bands cost no block launch.  The
+// list (ascending tile indices) is cut into 8 contiguous runs, one per XCD;
+// the blocks of an XCD stride through its run.  Every block leaves the loop
+// when its run is exhausted.
+template <int PREC, int RA, bool SPLIT, bool TILED>
+__global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds_walk(
+    const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
+    const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
+    int ncols_mul, int nr, int ns_pad, int B, int nfc, int ftiles, int rtiles,
+    const int* __restrict__ items) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[lds_tile_bytes<PREC, RA, SPLIT>()];
+    const int nitems = items[0];                  // the list: [count, tiles...]
+    const int x = (int)(blockIdx.x & 7);
+    const int per_xcd = (nitems + 7) >> 3;
+    const int lo = x * per_xcd, hi = min(lo + per_xcd, nitems);
+    const int step = (int)(gridDim.x >> 3);
+    for (int i = lo + (int)(blockIdx.x >> 3); i < hi; i += step) {
+        contract_lds_tile<PREC, RA, SPLIT, TILED>(Rv, rscale, Xv, xscale, Y, ncols_w, ncols_mul, nr, ns_pad, B,
+                                                  nfc, ftiles, rtiles, items[1 + i], lds);
+        __syncthreads();                          // the next tile restages the LDS buffers
+    }
+}
+
 template <int PREC, int RA, bool SPLIT, bool TILED>
 hipError_t launch_l(const ContractArgs& c, hipStream_t s) {
     if ((c.ns_pad * (PREC == MK_R_C64 ? 8 : 4)) % kChunkBytes != 0) return hipErrorInvalidValue;
     constexpr int NFB = 8 * RA;
     const int ftiles = (c.ncols + NFB - 1) / NFB;
     const int rtiles = (c.nr + kLdsRcv - 1) / kLdsRcv;
+    if (c.items) {          // persistent form over the list of active tiles
+        const int grid = 8 * std::max(1, c.walk_blocks_per_xcd / (RA >= 8 ? 2 : 1));
+        hipLaunchKernelGGL((k_contract_lds_walk<PREC, RA, SPLIT, TILED>), dim3((unsigned)grid), dim3(256), 0, s,
+                           c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B, c.ncols,
+                           ftiles, rtiles, c.items);
+        return hipGetLastError();
+    }
     const int64_t ntiles = (int64_t)ftiles * rtiles * c.nb;
     const int64_t per_xcd = (ntiles + 7) / 8;
     hipLaunchKernelGGL((k_contract_lds<PREC, RA, SPLIT, TILED>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s,
@@ -599,6 +654,11 @@ hipError_t launch_p(const ContractArgs& c, int variant, hipStream_t s) {
 bool contract_variant_reads_tiled(int variant) { return variant >= 6 && variant <= 8; }
 
 int contract_mfma_variants() { return 8; }
+
+// focal columns per tile of LDS-staged variant v (6, 7, 8), 0 for the others
+int contract_variant_focal_tile(int variant) {
+    return variant == 6 ? 64 : variant == 7 ? 32 : variant == 8 ? 16 : 0;
+}
 
 hipError_t launch_contract_mfma(const ContractArgs& c, int variant, hipStream_t s) {
     if (c.ncols <= 0) return hipSuccess;

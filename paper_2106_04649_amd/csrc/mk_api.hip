@@ -79,7 +79,8 @@ void free_plan_memory(mk_plan_t p) {
     void* bufs[] = {p->R, p->rscale, p->X, p->Y, p->f1p, p->f1m, p->gp, p->gm, p->stage, p->itd,
                     p->fband, p->perm, p->iperm, p->ncols, p->npart, p->norm0, p->gdnorm, p->nlast, p->xscale,
                     p->norms, p->tw, p->flag, p->n0, p->hist, p->tail_w, p->tail_x, p->tail_work,
-                    p->tail_y, p->tail_scale, p->img, p->aux, p->tail_wpk, p->norm_log, p->fnorm};
+                    p->tail_y, p->tail_scale, p->img, p->aux, p->tail_wpk, p->norm_log, p->fnorm,
+                    p->walk_items[0], p->walk_items[1]};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (auto& pe : p->pending) {
@@ -356,6 +357,11 @@ mk_status run_contract(mk_plan_t p, const ContractChoice& ch, const void* Xbuf, 
     ContractArgs c = contract_args(p, Xbuf, ncols, ncols_mul);
     c.xscale = xs;
     c.xsplit = (ch.xprec == XP_F16X2 || ch.xprec == XP_BF16X2) ? 1 : 0;
+    const int wk = ncols_mul == 2 ? 1 : 0;      // the series' list, or the G assembly's
+    if (p->walk_variant[wk] == variant && ncols == (wk + 1) * p->nf) {
+        c.items = p->walk_items[wk];
+        c.walk_blocks_per_xcd = p->walk_blocks_per_xcd;
+    }
     hipEvent_t ev = nullptr;
     HIP_TRY(p, prof_begin(p, &ev));
     if (p->r_stream) MK_TRY(contract_streamed(p, c, variant, ch.xprec));
@@ -566,6 +572,50 @@ mk_status aux_field(mk_plan_t p, int field) {
     return MK_OK;
 }
 
+// The lists of active tiles for the series' and the G
+// assembly's contraction choices (when they are LDS-staged tiles): tile
+// (w, rt, ft) is active when focal tile ft starts below the bin's active
+// column count (all nf, or the band prefix ncols_host[w]).  Ascending tile
+// indices, (w rtiles + rt) ftiles + ft, the order of the grid form.
+mk_status build_walk(mk_plan_t p) {
+    p->walk_variant[0] = p->walk_variant[1] = -1;
+    // always with MK_FLAG_WALK; by default whenever per-focal bands are set,
+    // where it also balances the XCDs (the grid form deals contiguous runs of
+    // bins to them, and the low bins hold most of the active tiles)
+    const bool walk = (p->d.flags & MK_FLAG_WALK) ||
+                      (p->has_fband && !p->r_stream && !(p->d.flags & MK_FLAG_GRID));
+    if (!walk) return MK_OK;
+    const ContractChoice* ch[2] = {&p->series_choice, &p->g_choice};
+    const int rtiles = (p->d.nr + kLdsTileReceivers - 1) / kLdsTileReceivers;
+    for (int k = 0; k < 2; ++k) {
+        const int nfb = contract_variant_focal_tile(ch[k]->variant);
+        if (nfb == 0) continue;                   // not an LDS-staged choice
+        if (!p->walk_items[k]) {
+            // sized once for the largest list (every tile of the narrowest
+            // LDS-staged tiles, 16 focal columns), so captured graphs keep a
+            // valid address across focal sets
+            const size_t cap = 1 + (size_t)p->B * rtiles * (((size_t)(k + 1) * p->d.nf_max + 15) / 16);
+            HIP_TRY(p, hipStreamSynchronize(p->stream));
+            HIP_TRY(p, dalloc(&p->walk_items[k], cap));
+        }
+        const int mul = k + 1, ncols = mul * p->nf;
+        const int ftiles = (ncols + nfb - 1) / nfb;
+        std::vector<int32_t> items(1, 0);
+        for (int w = 0; w < p->B; ++w) {
+            const int nact = p->has_fband ? std::min(p->ncols_host[w] * mul, ncols) : ncols;
+            const int fa = (nact + nfb - 1) / nfb;
+            for (int rt = 0; rt < rtiles; ++rt)
+                for (int ft = 0; ft < fa; ++ft) items.push_back((w * rtiles + rt) * ftiles + ft);
+        }
+        items[0] = (int32_t)(items.size() - 1);
+        HIP_TRY(p, hipMemcpyAsync(p->walk_items[k], items.data(), items.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, p->stream));
+        HIP_TRY(p, hipStreamSynchronize(p->stream));      // the host list goes out of scope
+        p->walk_variant[k] = ch[k]->variant;
+    }
+    return MK_OK;
+}
+
 // mk_load_R for streamed R: one slab of bins at a time, the caller's rows of
 // those bins (a 2D region of R[r][w][s]) go to a device staging buffer, the
 // resident path's repack / quantisation kernels write the slab's device
@@ -658,8 +708,13 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
         return fail(nullptr, MK_ERR_ARG, "mk_plan: unknown rprec");
     if (d.rprec == MK_R_C64 && d.ns > 2048)
         return fail(nullptr, MK_ERR_UNSUPPORTED, "mk_plan: complex64 R supports ns <= 2048");
-    if (d.flags & ~(MK_FLAG_GRAPH | MK_FLAG_PROFILE | MK_FLAG_AUTOTUNE | MK_FLAG_FAST_X | MK_FLAG_ROW_R))
+    if (d.flags & ~(MK_FLAG_GRAPH | MK_FLAG_PROFILE | MK_FLAG_AUTOTUNE | MK_FLAG_FAST_X | MK_FLAG_ROW_R |
+                    MK_FLAG_WALK | MK_FLAG_GRID))
         return fail(nullptr, MK_ERR_ARG, "mk_plan: unknown flag bits");
+    if ((d.flags & MK_FLAG_WALK) && (d.flags & MK_FLAG_GRID))
+        return fail(nullptr, MK_ERR_ARG, "mk_plan: MK_FLAG_WALK and MK_FLAG_GRID exclude each other");
+    if ((d.flags & MK_FLAG_WALK) && (d.flags & MK_FLAG_AUTOTUNE))
+        return fail(nullptr, MK_ERR_UNSUPPORTED, "mk_plan: MK_FLAG_WALK excludes MK_FLAG_AUTOTUNE");
     const int B = d.iw_hi - d.iw_lo + 1;
     const int ns_pad = (d.ns + 31) & ~31;      // rows of whole 128-byte chunks in every precision
     const bool r_tiled = d.nf_max > kGemvMaxCols && !(d.flags & MK_FLAG_ROW_R);
@@ -673,10 +728,10 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
         if (slab_bins < 1)
             return fail(nullptr, MK_ERR_ARG, "mk_plan: r_dev_bytes holds fewer than two bins of R (" +
                                                  std::to_string(2 * bin_bytes) + " bytes)");
-        if (d.flags & (MK_FLAG_GRAPH | MK_FLAG_AUTOTUNE))
+        if (d.flags & (MK_FLAG_GRAPH | MK_FLAG_AUTOTUNE | MK_FLAG_WALK))
             return fail(nullptr, MK_ERR_UNSUPPORTED,
-                        "mk_plan: streamed R (r_dev_bytes below the size of R) excludes MK_FLAG_GRAPH and "
-                        "MK_FLAG_AUTOTUNE");
+                        "mk_plan: streamed R (r_dev_bytes below the size of R) excludes MK_FLAG_GRAPH, "
+                        "MK_FLAG_AUTOTUNE and MK_FLAG_WALK");
     }
 
     mk_plan_t p = new (std::nothrow) mk_plan_s();
@@ -750,6 +805,12 @@ mk_status mk_plan(const mk_plan_desc* desc, mk_plan_t* out) {
     if ((e = dalloc(&p->tw, (size_t)d.nt + 256)) != hipSuccess) return bail(e, "twiddles");
     if ((e = dalloc(&p->flag, 1)) != hipSuccess) return bail(e, "flag");
     if ((e = dalloc(&p->n0, nfm * trace)) != hipSuccess) return bail(e, "N_-1");
+    {
+        int cus = 0;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device)) != hipSuccess)
+            return bail(e, "CU count");
+        p->walk_blocks_per_xcd = 2 * std::max(1, cus / 8);     // two blocks of four waves per CU
+    }
     // the padding columns of X (s >= ns) must read as zero
     if ((e = hipMemsetAsync(p->X, 0, 3 * nfm * p->B * p->ns_pad * sizeof(float2), p->stream)) !=
         hipSuccess)
@@ -897,6 +958,7 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
         HIP_TRY(p, hipMemcpyAsync(p->ncols, nc.data(), nc.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                   p->stream));
         HIP_TRY(p, hipStreamSynchronize(p->stream));    // host vectors go out of scope
+        p->ncols_host = nc;
     }
     p->has_fband = band != nullptr;
     p->perm_host = perm;
@@ -908,6 +970,7 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
     p->g_valid = false;
     p->series_choice = choose(p, nf);
     p->g_choice = choose(p, 2 * nf);
+    MK_TRY(build_walk(p));
     // ||N_-1|| = ||G_d|| per focal point (also the scale of the first 16-bit X)
     HIP_TRY(p, launch_sumsq(p->gp, (int)ntr, d.nt, p->npart, p->stream));
     HIP_TRY(p, launch_norm_reduce(p->npart, d.nr, nf, p->norm0, p->nlast, p->stream));
@@ -1490,6 +1553,13 @@ mk_status mk_set_state(mk_plan_t p, const void* blob, size_t bytes) {
     p->series_choice.variant = h.variant;
     p->series_choice.xprec = h.xprec;
     p->g_choice = choose(p, 2 * h.nf);
+    if (p->has_fband) {
+        p->ncols_host.assign(p->B, 0);
+        HIP_TRY(p, hipMemcpyAsync(p->ncols_host.data(), p->ncols, p->B * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  p->stream));
+        HIP_TRY(p, hipStreamSynchronize(p->stream));
+    }
+    MK_TRY(build_walk(p));
     p->log_len = h.log_len;
     p->series_start = h.series_start;
     p->prev_series_start = h.prev_series_start;

@@ -116,6 +116,14 @@ struct mk_plan_s {
     double* norm_log = nullptr;
     int log_cap = 0, log_len = 0, series_start = 0, prev_series_start = 0;
     double* fnorm = nullptr;   // [2 nf_max] ||f1+||, ||f1-|| for the stopping rule
+    // MK_FLAG_WALK: lists of active tiles for the persistent LDS-staged
+    // contraction, [0] the series (nf columns), [1] the G assembly (2 nf)
+    // ([count, tiles...] on the device; buffers sized once for the largest
+    // list, so that captured graphs keep valid pointers)
+    int* walk_items[2] = {nullptr, nullptr};
+    int walk_variant[2] = {-1, -1};
+    int walk_blocks_per_xcd = 0;
+    std::vector<int32_t> ncols_host;   // active focal count per bin (sorted order) when bands are set
     // R streamed from pinned host memory (r_dev_bytes below the size of R):
     // the whole of R in the device layout on the host, two device buffers of
     // slab_bins bins each, a copy stream and the events that order the ring
@@ -212,6 +220,12 @@ struct ContractArgs {
     int nr, ns, ns_pad, B, ncols;
     int nb;                // bins this launch covers (R, rscale, X, Y, ncols_w start at its first bin;
                            // X and Y keep the B-bin strides of the whole band)
+    // LDS-staged variants only: when items is set, the persistent form walks
+    // the tile list items = [count, tile indices (ascending)...] with
+    // walk_blocks_per_xcd blocks of two waves per SIMD on each of the 8 XCDs
+    // (half as many for the one-wave 128-row tiles)
+    const int* items = nullptr;
+    int walk_blocks_per_xcd = 0;
 };
 
 // kernel launchers (return hipSuccess or the launch error)
@@ -245,12 +259,15 @@ hipError_t launch_rscale(const float* Rin, float* rscale, int nr, int B, int ns,
 // tiles follow in (w, rg, c) order, so one wave load of 64 x 16 bytes is 1 KB
 // of contiguous memory.  Receivers past nr and shots past ns are zero.
 constexpr int kTileRows = 16;
+constexpr int kLdsTileReceivers = 256;     // receivers per block of the LDS-staged contraction
 constexpr int kTileChunkBytes = 128;
 // R into the tiles of the LDS-staged contraction (any precision)
 hipError_t launch_repack_tiled(int prec, const float* Rin, void* Rout, const float* rscale, int nr, int B,
                                int ns, int ns_pad, int* flag, hipStream_t s);
 size_t tiled_R_bytes(int prec, int nr, int B, int ns_pad);
 bool contract_variant_reads_tiled(int variant);
+// focal columns per tile of LDS-staged contraction variant v (6, 7, 8); 0 for the others
+int contract_variant_focal_tile(int variant);
 hipError_t launch_check_finite(const float* x, int64_t n, int* flag, hipStream_t s);
 // x may be NULL: then only the per-trace scales are written
 hipError_t launch_tail_prep(const float* hist, int ntr, int k, int T, float* x, float* scale, hipStream_t s);

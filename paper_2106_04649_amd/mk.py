@@ -24,7 +24,8 @@ LIB_PATH = os.path.join(HERE, "libmk.so")
 MK_OK, MK_ERR_ARG, MK_ERR_STATE, MK_ERR_OOM, MK_ERR_HIP, MK_ERR_UNSUPPORTED, MK_ERR_DIVERGED = range(7)
 MK_R_C64, MK_R_F16S, MK_R_BF16S = 0, 1, 2
 MK_F1PLUS, MK_F1MINUS, MK_GPLUS, MK_GMINUS, MK_F2PLUS, MK_PMINUS, MK_GTOTAL = 0, 1, 2, 3, 4, 5, 6
-MK_FLAG_GRAPH, MK_FLAG_PROFILE, MK_FLAG_AUTOTUNE, MK_FLAG_FAST_X, MK_FLAG_ROW_R = 0x1, 0x2, 0x4, 0x8, 0x10
+MK_FLAG_GRAPH, MK_FLAG_PROFILE, MK_FLAG_AUTOTUNE, MK_FLAG_FAST_X, MK_FLAG_ROW_R, MK_FLAG_WALK, MK_FLAG_GRID = \
+    0x1, 0x2, 0x4, 0x8, 0x10, 0x20, 0x40
 FIELDS = {"f1plus": MK_F1PLUS, "f1minus": MK_F1MINUS, "Gplus": MK_GPLUS, "Gminus": MK_GMINUS,
           "f2plus": MK_F2PLUS, "pminus": MK_PMINUS, "Gtotal": MK_GTOTAL}
 KERNEL_KINDS = {"contract": 0, "epilogue": 1, "norms": 2, "init": 3, "gassembly": 4, "image": 5}

@@ -284,6 +284,8 @@ def main(argv=None):
     ap.add_argument("--report", default=None)
     ap.add_argument("--eval-only", default=None, metavar="NPZ",
                     help="skip training: evaluate the network saved in NPZ on the held-out models")
+    ap.add_argument("--no-eval", action="store_true",
+                    help="train and save only (evaluate later with --eval-only)")
     args = ap.parse_args(argv)
 
     import torch
@@ -306,6 +308,7 @@ def main(argv=None):
         report = {"workload": args.workload, "rprec": args.rprec, "network": os.path.basename(args.eval_only),
                   "holdout_models": len(hold_seeds), "k": int(saved["k"]), "T": int(saved["T"]),
                   "hidden": mk.net_hidden(params.size, int(saved["k"])),
+                  **{key: int(saved[key]) for key in ("train_models", "steps") if key in saved.files},
                   "summary": summarise(rows)}
         if args.report:
             with open(args.report, "w") as fh:
@@ -324,6 +327,10 @@ def main(argv=None):
     log(f"saved {args.out}")
     del X, Y, M
     torch.cuda.empty_cache()
+    if args.no_eval:
+        print(json.dumps({"workload": args.workload, "train_models": args.train, "k": args.k, "T": args.T,
+                          "hidden": args.hidden, "steps": args.steps, "curve": curve}), flush=True)
+        return 0
     rows = evaluate(params, hold_seeds, args.k, args.T, gen, args.rprec)
     summary = summarise(rows)
     report = {"workload": args.workload, "rprec": args.rprec,

@@ -69,6 +69,10 @@ def _desc(**kw):
     (dict(r_dev_bytes=4095), mk.MK_ERR_ARG),
     (dict(r_dev_bytes=8192, flags=0x1), mk.MK_ERR_UNSUPPORTED),      # with graph replay
     (dict(r_dev_bytes=8192, flags=0x4), mk.MK_ERR_UNSUPPORTED),      # with the autotuner
+    (dict(r_dev_bytes=8192, flags=0x20), mk.MK_ERR_UNSUPPORTED),     # with the tile walk
+    (dict(flags=0x24), mk.MK_ERR_UNSUPPORTED),                       # tile walk with the autotuner
+    (dict(flags=0x60), mk.MK_ERR_ARG),                               # tile walk and grid form
+    (dict(flags=0x80), mk.MK_ERR_ARG),                               # unknown bit
 ])
 def test_plan_rejects_bad_descriptions(lib, kw, status):
     d = _desc(**kw)

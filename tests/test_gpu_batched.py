@@ -109,3 +109,51 @@ def test_medium_focal_line_batched():
         assert_parity(gv, r, tol=1e-3, label=f"medium64-fp16-v{v}{'t' if tiled else ''}")
     g32 = run_gpu(p, niter=2, tune=8)
     assert_parity(g32, r, label="medium64-fp32-v8t")
+
+
+@pytest.mark.parametrize("rprec,variant,bands", [(0, 7, True), (1, 6, True), (1, 7, False), (2, 8, True),
+                                                 (1, 7, True)])
+def test_tile_walk_equals_grid_launch(rprec, variant, bands):
+    """The persistent kernel walks the list of active tiles (MK_FLAG_WALK, and
+    by default with bands); each tile is the grid form's computation
+    (MK_FLAG_GRID), so every output is the same bits, and the oracle agrees."""
+    mk = require_gpu()
+    p = small_problem(seed=44, n=60, nt=128, nf=40, niter=5)
+    fb = None
+    if bands:
+        rng = np.random.default_rng(8)
+        fb = np.stack([np.zeros(p.nf, np.int32), rng.integers(8, 65, p.nf).astype(np.int32)], axis=1)
+    say(f"tile walk rprec {rprec} variant {variant} bands {bands}")
+    grid = run_gpu(p, fbands=fb, rprec=rprec, tune=variant, flags=mk.MK_FLAG_GRID)
+    walk = run_gpu(p, fbands=fb, rprec=rprec, tune=variant, flags=mk.MK_FLAG_WALK)
+    for k in ("f1plus", "f1minus", "Gplus", "Gminus", "norms"):
+        assert np.array_equal(walk[k], grid[k]), k
+    if bands:      # the default form of a banded plan is the walk
+        dflt = run_gpu(p, fbands=fb, rprec=rprec, tune=variant)
+        for k in ("f1plus", "f1minus", "Gplus", "Gminus", "norms"):
+            assert np.array_equal(dflt[k], walk[k]), k
+    assert_parity(walk, run_oracle(p, fbands=fb), tol=TOL[rprec], label=f"walk{rprec}-v{variant}")
+
+
+def test_tile_walk_under_graph_replay_with_new_bands():
+    """Graph replays keep the tile list's address and read its length from
+    device memory: a new focal set with other bands replays the same graph
+    and must match the eager passes bit for bit."""
+    mk = require_gpu()
+    p = small_problem(seed=45, n=48, nt=128, nf=24, niter=4)
+    nr, nt = p.Rhat.shape[0], p.geom.nt
+    outs = {}
+    for flags in (mk.MK_FLAG_WALK, mk.MK_FLAG_WALK | mk.MK_FLAG_GRAPH):
+        plan = mk.mk_plan(nr, nr, nt, p.geom.dt, p.geom.dx, band=p.band, nf_max=p.nf, rprec=1, flags=flags)
+        mk.mk_load_R(plan, p.Rhat)
+        res = []
+        for trial in range(3):
+            rng_t = np.random.default_rng(100 + trial)
+            fb = np.stack([np.zeros(p.nf, np.int32), rng_t.integers(6, 65, p.nf).astype(np.int32)], axis=1)
+            mk.mk_set_focal(plan, p.Gd, p.itd, p.shift, fb)
+            n = mk.mk_iterate(plan, 4)
+            res.append((n, mk.mk_get(plan, "Gminus", np.zeros(p.Gd.shape, np.float32))))
+        mk.mk_destroy(plan)
+        outs[flags] = res
+    for (n0, g0), (n1, g1) in zip(outs[mk.MK_FLAG_WALK], outs[mk.MK_FLAG_WALK | mk.MK_FLAG_GRAPH]):
+        assert np.array_equal(n0, n1) and np.array_equal(g0, g1)
