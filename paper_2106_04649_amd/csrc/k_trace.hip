@@ -1017,28 +1017,63 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
 // and for trace j - n0 of x1 (j >= n0), so two fields reduce in one launch.
 // One wave per trace, 16-byte loads, eight of a lane's loads in flight
 // together (addresses clamped, out-of-range values dropped after the load).
+// WIN 1: only the samples inside the trace's mute window |t| < L,
+// L = min(itd - shift, nt / 2) (sample k is inside when k < L or k > nt - L),
+// read alone: the f1 samples a pass can change.  WIN 2: the whole trace into
+// npart and the samples outside the window into npart2.  Trace i of x1 is
+// trace i - n0 of the window table.
+template <int WIN>
 __global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ x0, const float* __restrict__ x1, int n0,
-                                               int ntr, int nt, double* __restrict__ npart) {
+                                               int ntr, int nt, const int32_t* __restrict__ itd, int shift,
+                                               double* __restrict__ npart, double* __restrict__ npart2) {
     const int lane = threadIdx.x & 63;
     const int trace = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (trace >= ntr) return;
     const float4* p = reinterpret_cast<const float4*>(trace < n0 ? x0 + (size_t)trace * nt
                                                                  : x1 + (size_t)(trace - n0) * nt);
     const int n4 = nt >> 2;
-    double acc = 0.0;
-    for (int i0 = 0; i0 < n4; i0 += 64 * 8) {
+    const int L = min(itd[trace < n0 ? trace : trace - n0] - shift, nt >> 1);
+    auto inwin = [&](int k) { return k < L || k > nt - L; };
+    // WIN 1 visits the float4 runs [0, a1) and [b2, n4), which hold the window
+    int a1 = n4, b2 = n4, cnt = n4;
+    if constexpr (WIN == 1) {
+        a1 = (max(L, 0) + 3) >> 2;
+        b2 = min((nt - max(L, 0) + 1) >> 2, n4);
+        cnt = b2 <= a1 ? n4 : a1 + (n4 - b2);
+        if (L <= 0) cnt = 0;
+    }
+    double acc = 0.0, acco = 0.0;
+    for (int i0 = 0; i0 < cnt; i0 += 64 * 8) {
         float4 v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = p[min(i0 + lane + 64 * j, n4 - 1)];
+        int q[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const double w = i0 + lane + 64 * j < n4 ? 1.0 : 0.0;
-            acc += w * ((double)v[j].x * v[j].x + (double)v[j].y * v[j].y + (double)v[j].z * v[j].z +
-                        (double)v[j].w * v[j].w);
+            const int u = min(i0 + lane + 64 * j, cnt - 1);
+            q[j] = (WIN == 1 && b2 > a1 && u >= a1) ? b2 + (u - a1) : u;
+            v[j] = p[q[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const bool live = i0 + lane + 64 * j < cnt;
+            const float e[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double sq = (double)e[c] * e[c];
+                if constexpr (WIN == 1) {
+                    acc += (live && inwin(4 * q[j] + c)) ? sq : 0.0;
+                } else {
+                    acc += live ? sq : 0.0;
+                    acco += (live && !inwin(4 * q[j] + c)) ? sq : 0.0;
+                }
+            }
         }
     }
     acc = wave_sum_d(acc);
-    if (lane == 0) npart[trace] = acc;
+    if constexpr (WIN == 2) acco = wave_sum_d(acco);
+    if (lane == 0) {
+        npart[trace] = acc;
+        if constexpr (WIN == 2) npart2[trace] = acco;
+    }
 }
 
 // f2+ = N_-1 + sum of every pass's N_i (Algorithm 1, second loop): the odd
@@ -1190,15 +1225,19 @@ hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out,
     return hipGetLastError();
 }
 
-hipError_t launch_sumsq(const float* x, int ntr, int nt, double* npart, hipStream_t s) {
+hipError_t launch_sumsq_out(const float* x, int ntr, int nt, const int32_t* itd, int shift, double* npart,
+                            double* npart_out, hipStream_t s) {
     if (ntr <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sumsq, dim3((ntr + 3) / 4), dim3(256), 0, s, x, x, ntr, ntr, nt, npart);
+    hipLaunchKernelGGL(k_sumsq<2>, dim3((ntr + 3) / 4), dim3(256), 0, s, x, x, ntr, ntr, nt, itd, shift, npart,
+                       npart_out);
     return hipGetLastError();
 }
 
-hipError_t launch_sumsq2(const float* x0, const float* x1, int ntr, int nt, double* npart, hipStream_t s) {
+hipError_t launch_sumsq2_win(const float* x0, const float* x1, int ntr, int nt, const int32_t* itd, int shift,
+                             double* npart, hipStream_t s) {
     if (ntr <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sumsq, dim3((2 * ntr + 3) / 4), dim3(256), 0, s, x0, x1, ntr, 2 * ntr, nt, npart);
+    hipLaunchKernelGGL(k_sumsq<1>, dim3((2 * ntr + 3) / 4), dim3(256), 0, s, x0, x1, ntr, 2 * ntr, nt, itd, shift,
+                       npart, nullptr);
     return hipGetLastError();
 }
 

@@ -76,6 +76,7 @@ void free_plan_memory(mk_plan_t p) {
         if (p->ev_consumed[b]) (void)hipEventDestroy(p->ev_consumed[b]);
     }
     if (p->R_host) (void)hipHostFree(p->R_host);
+    if (p->hpin) (void)hipHostFree(p->hpin);
     void* bufs[] = {p->R, p->rscale, p->X, p->Y, p->f1p, p->f1m, p->gp, p->gm, p->stage, p->itd,
                     p->fband, p->perm, p->iperm, p->ncols, p->npart, p->norm0, p->gdnorm, p->nlast, p->xscale,
                     p->norms, p->tw, p->flag, p->n0, p->hist, p->tail_w, p->tail_x, p->tail_work,
@@ -425,6 +426,24 @@ mk_status ensure_log_cap(mk_plan_t p, int rows) {
     return MK_OK;
 }
 
+// Small device-to-host reads go through a pinned buffer: into pageable
+// memory the runtime completes every copy on its own before the call
+// returns, into pinned memory several copies queue behind one
+// synchronisation.  Returns the buffer, grown to hold `doubles` values.
+mk_status pinned(mk_plan_t p, size_t doubles, double** out) {
+    if (doubles > p->hpin_cap) {
+        HIP_TRY(p, hipStreamSynchronize(p->stream));
+        if (p->hpin) HIP_TRY(p, hipHostFree(p->hpin));
+        p->hpin = nullptr;
+        p->hpin_cap = 0;
+        const size_t cap = std::max<size_t>(doubles, 4096);
+        HIP_TRY(p, hipHostMalloc(reinterpret_cast<void**>(&p->hpin), cap * sizeof(double), hipHostMallocDefault));
+        p->hpin_cap = cap;
+    }
+    *out = p->hpin;
+    return MK_OK;
+}
+
 // Append `rows` rows of nf norms from device memory to the log.
 mk_status log_rows(mk_plan_t p, const double* src, int rows) {
     if (rows <= 0) return MK_OK;
@@ -440,6 +459,19 @@ mk_status log_series_start(mk_plan_t p, const double* start) {
     p->prev_series_start = p->series_start;
     p->series_start = p->log_len;
     return log_rows(p, start, 1);
+}
+
+// Outside its mute window f1+ keeps N_-1 and f1- stays zero (every pass,
+// tail and restart writes inside the window only), so the judge reads the
+// windows alone and adds these sums of squares of N_-1 outside them.
+// `src`: N_-1 or G_d (the window is symmetric in t), plan order.  Leaves
+// ||src|| per focal point in p->norm0 and p->nlast (whole traces).
+mk_status outside_window_norms(mk_plan_t p, const float* src, int nf, int32_t shift) {
+    const int nr = p->d.nr, ntr = nf * nr;
+    HIP_TRY(p, launch_sumsq_out(src, ntr, p->d.nt, p->itd, shift, p->npart, p->npart + ntr, p->stream));
+    HIP_TRY(p, launch_norm_reduce(p->npart, nr, nf, p->norm0, p->nlast, p->stream));
+    HIP_TRY(p, launch_norm_reduce(p->npart + ntr, nr, nf, p->fnorm, nullptr, p->stream));
+    return MK_OK;
 }
 
 // The stopping rule.  a[0..n) are the norms of one focal point's terms in the
@@ -471,15 +503,32 @@ RestEstimate estimate_rest(const double* a, int n, double q_prior) {
 // The rule for every focal point: est[j] = rest / min(||f1+||, ||f1-||) in the
 // plan's sorted order, and the passes still needed, predicted from q (0 when
 // every estimate is within tol, -1 when some q is not known yet).
-mk_status judge_series(mk_plan_t p, double tol, std::vector<double>& est, int* more) {
+mk_status judge_series(mk_plan_t p, double tol, std::vector<double>& est, int* more, int check_from) {
     const int nf = p->nf, nr = p->d.nr, nt = p->d.nt;
-    HIP_TRY(p, launch_sumsq2(p->f1p, p->f1m, nf * nr, nt, p->npart, p->stream));
+    HIP_TRY(p, launch_sumsq2_win(p->f1p, p->f1m, nf * nr, nt, p->itd, p->shift, p->npart, p->stream));
     HIP_TRY(p, launch_norm_reduce(p->npart, nr, 2 * nf, p->fnorm, nullptr, p->stream));
-    std::vector<double> fn(2 * (size_t)nf), log((size_t)p->log_len * nf);
-    HIP_TRY(p, hipMemcpyAsync(fn.data(), p->fnorm, fn.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(p, hipMemcpyAsync(log.data(), p->norm_log, log.size() * sizeof(double), hipMemcpyDeviceToHost,
-                              p->stream));
+    double* h = nullptr;
+    MK_TRY(pinned(p, 2 * (size_t)nf + (size_t)p->log_len * nf, &h));
+    const double* fn = h;
+    const double* log = h + 2 * nf;
+    HIP_TRY(p, hipMemcpyAsync(h, p->fnorm, 2 * (size_t)nf * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    if (p->log_len > 0)
+        HIP_TRY(p, hipMemcpyAsync(h + 2 * nf, p->norm_log, (size_t)p->log_len * nf * sizeof(double),
+                                  hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
+    // the divergence check of the passes since row check_from (mk_iterate's,
+    // on the same rows of the log)
+    for (int e = std::max(check_from, 0); check_from >= 0 && e < p->log_len; ++e)
+        for (int j = 0; j < nf; ++j) {
+            const double v = log[(size_t)e * nf + j];
+            const int f = p->perm_host[j];
+            if (!std::isfinite(v) || v > p->d.div_factor * p->norm0_host[f]) {
+                char buf[160];
+                std::snprintf(buf, sizeof(buf), "mk_iterate_tol: ||N|| = %g at pass %d, focal %d (||N_-1|| = %g)", v,
+                              p->passes - (p->log_len - e), f, p->norm0_host[f]);
+                return fail(p, MK_ERR_DIVERGED, buf);
+            }
+        }
     est.assign(nf, 0.0);
     *more = 0;
     const int n = p->log_len - p->series_start;
@@ -494,7 +543,8 @@ mk_status judge_series(mk_plan_t p, double tol, std::vector<double>& est, int* m
         a.clear();
         for (int e = p->series_start; e < p->log_len; ++e) a.push_back(log[(size_t)e * nf + j]);
         const RestEstimate r = estimate_rest(a.data(), n, q_prior);
-        const double den = std::min(fn[j], fn[nf + j]);
+        const double fp = std::sqrt(fn[j] * fn[j] + p->f1p_out2_host[j]);     // ||f1+||, ||f1-||
+        const double den = std::min(fp, fn[nf + j]);
         if (r.rest == 0.0) {
             est[j] = 0.0;
             continue;
@@ -929,7 +979,14 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
         MK_TRY(copy_in(p, p->stage, Gd, ntr * d.nt, 0, "mk_set_focal: Gd"));
         gsrc = p->stage;
     }
-    HIP_TRY(p, launch_gather(gsrc, p->gp, p->perm, nf, (int64_t)d.nr * d.nt, p->stream));
+    // in the caller's order INIT reads G_d where it is (this call waits for
+    // INIT before it returns)
+    bool identity = true;
+    for (int j = 0; j < nf; ++j) identity = identity && perm[j] == j;
+    if (!identity) {
+        HIP_TRY(p, launch_gather(gsrc, p->gp, p->perm, nf, (int64_t)d.nr * d.nt, p->stream));
+        gsrc = p->gp;
+    }
     const int32_t* isrc = itd;
     if (!on_device) {
         int32_t* itd_stage = p->itd + (size_t)d.nf_max * d.nr;
@@ -972,19 +1029,22 @@ mk_status mk_set_focal(mk_plan_t p, int32_t nf, const float* Gd, const int32_t* 
     p->g_choice = choose(p, 2 * nf);
     MK_TRY(build_walk(p));
     // ||N_-1|| = ||G_d|| per focal point (also the scale of the first 16-bit X)
-    HIP_TRY(p, launch_sumsq(p->gp, (int)ntr, d.nt, p->npart, p->stream));
-    HIP_TRY(p, launch_norm_reduce(p->npart, d.nr, nf, p->norm0, p->nlast, p->stream));
+    MK_TRY(outside_window_norms(p, gsrc, nf, shift));
     HIP_TRY(p, hipMemcpyAsync(p->gdnorm, p->norm0, nf * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
     TraceArgs a = trace_args(p, nf);
-    a.src = p->gp;
+    a.src = gsrc;
     a.xprec = p->series_choice.xprec;
     a.xs_in = p->norm0;
     a.xs_out = p->xscale;
     a.skip_outband = (p->series_choice.variant != 0 && p->has_fband) ? 1 : 0;
     MK_TRY(run_trace(p, TM_INIT, a, 3));
-    std::vector<double> n0(nf);
-    HIP_TRY(p, hipMemcpyAsync(n0.data(), p->norm0, nf * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    double* n0 = nullptr;
+    MK_TRY(pinned(p, 2 * (size_t)nf, &n0));
+    HIP_TRY(p, hipMemcpyAsync(n0, p->norm0, nf * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(n0 + nf, p->fnorm, nf * sizeof(double), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
+    p->f1p_out2_host.resize(nf);
+    for (int j = 0; j < nf; ++j) p->f1p_out2_host[j] = n0[nf + j] * n0[nf + j];
     for (int j = 0; j < nf; ++j)
         if (!std::isfinite(n0[j])) return fail(p, MK_ERR_ARG, "mk_set_focal: Gd holds a non-finite value");
     p->norm0_host.assign(nf, 0.0);
@@ -1174,8 +1234,9 @@ mk_status mk_iterate(mk_plan_t p, int32_t niter, double* norms) {
     p->passes += niter;
     MK_TRY(log_rows(p, p->norms, niter));
     if (norms) {
-        std::vector<double> h((size_t)niter * p->nf);
-        HIP_TRY(p, hipMemcpyAsync(h.data(), p->norms, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+        double* h = nullptr;
+        MK_TRY(pinned(p, (size_t)niter * p->nf, &h));
+        HIP_TRY(p, hipMemcpyAsync(h, p->norms, (size_t)niter * p->nf * sizeof(double), hipMemcpyDeviceToHost,
                                   p->stream));
         HIP_TRY(p, hipStreamSynchronize(p->stream));
         for (int i = 0; i < niter; ++i)
@@ -1201,16 +1262,18 @@ mk_status mk_iterate_tol(mk_plan_t p, double tol, int32_t max_passes, int32_t* p
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(p, MK_ERR_ARG, "mk_iterate_tol: tol must be positive");
     if (max_passes < 0) return fail(p, MK_ERR_ARG, "mk_iterate_tol: max_passes must be >= 0");
     if (!p->focal_set) return fail(p, MK_ERR_STATE, "mk_iterate_tol: no focal points set");
-    std::vector<double> e, nbuf;
-    int run = 0;
+    std::vector<double> e;
+    int run = 0, check_from = -1;
     for (;;) {
         int more = 0;
-        MK_TRY(judge_series(p, tol, e, &more));
+        // the judge also reads the new passes' norms: it applies mk_iterate's
+        // divergence check to them, so the passes return without a read
+        MK_TRY(judge_series(p, tol, e, &more, check_from));
         if (more == 0 || run >= max_passes) break;
         // an unknown contraction factor needs two terms of this series first
         const int m = std::min(more < 0 ? 2 : more, max_passes - run);
-        nbuf.resize((size_t)m * p->nf);
-        mk_status st = mk_iterate(p, m, nbuf.data());
+        check_from = p->log_len;
+        mk_status st = mk_iterate(p, m, nullptr);
         run += m;
         if (passes_run) *passes_run = run;
         if (st != MK_OK) return st;
@@ -1444,8 +1507,9 @@ mk_status mk_tail_apply(mk_plan_t p, int32_t mode, double* rel_resid) {
     MK_TRY(run_contract(p, p->series_choice, p->X, p->xscale, p->nf, 1, 0));
     MK_TRY(run_trace(p, TM_RST2, a, 1));
     HIP_TRY(p, launch_norm_reduce(p->npart, nr, p->nf, p->norm0, p->nlast, p->stream));
-    std::vector<double> rn(p->nf);
-    HIP_TRY(p, hipMemcpyAsync(rn.data(), p->norm0, p->nf * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    double* rn = nullptr;
+    MK_TRY(pinned(p, p->nf, &rn));
+    HIP_TRY(p, hipMemcpyAsync(rn, p->norm0, p->nf * sizeof(double), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
     for (int j = 0; j < p->nf; ++j) {
         const int f = p->perm_host[j];
@@ -1560,6 +1624,18 @@ mk_status mk_set_state(mk_plan_t p, const void* blob, size_t bytes) {
         HIP_TRY(p, hipStreamSynchronize(p->stream));
     }
     MK_TRY(build_walk(p));
+    {
+        // the outside-window sums of N_-1; norm0 and nlast keep their saved values
+        const int ntr = h.nf * p->d.nr;
+        HIP_TRY(p, launch_sumsq_out(p->n0, ntr, p->d.nt, p->itd, h.shift, p->npart, p->npart + ntr, p->stream));
+        HIP_TRY(p, launch_norm_reduce(p->npart + ntr, p->d.nr, h.nf, p->fnorm, nullptr, p->stream));
+        double* o = nullptr;
+        MK_TRY(pinned(p, h.nf, &o));
+        HIP_TRY(p, hipMemcpyAsync(o, p->fnorm, h.nf * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(p, hipStreamSynchronize(p->stream));
+        p->f1p_out2_host.resize(h.nf);
+        for (int j = 0; j < h.nf; ++j) p->f1p_out2_host[j] = o[j] * o[j];
+    }
     p->log_len = h.log_len;
     p->series_start = h.series_start;
     p->prev_series_start = h.prev_series_start;

@@ -116,6 +116,8 @@ struct mk_plan_s {
     double* norm_log = nullptr;
     int log_cap = 0, log_len = 0, series_start = 0, prev_series_start = 0;
     double* fnorm = nullptr;   // [2 nf_max] ||f1+||, ||f1-|| for the stopping rule
+    double* hpin = nullptr;    // pinned host buffer for small device-to-host reads
+    size_t hpin_cap = 0;       // its capacity in doubles
     // MK_FLAG_WALK: lists of active tiles for the persistent LDS-staged
     // contraction, [0] the series (nf columns), [1] the G assembly (2 nf)
     // ([count, tiles...] on the device; buffers sized once for the largest
@@ -166,6 +168,9 @@ struct mk_plan_s {
     bool focal_set = false;
     bool g_valid = false;
     std::vector<double> norm0_host;
+    // sum of squares of N_-1 outside the mute window per focal point (plan
+    // order): f1+ keeps those samples of N_-1, f1- is zero there
+    std::vector<double> f1p_out2_host;
     std::vector<int> perm_host;
     ContractChoice series_choice, g_choice;
 
@@ -232,9 +237,13 @@ struct ContractArgs {
 hipError_t launch_trace(int mode, int nt, const TraceArgs& a, hipStream_t s);
 hipError_t launch_norm_reduce(const double* npart, int nr, int nfo, double* out, double* out2,
                               hipStream_t s);
-hipError_t launch_sumsq(const float* x, int ntr, int nt, double* npart, hipStream_t s);
-// the sums of squares of two fields of ntr traces each in one launch: npart [2 ntr]
-hipError_t launch_sumsq2(const float* x0, const float* x1, int ntr, int nt, double* npart, hipStream_t s);
+// the sums of squares of two fields of ntr traces each, over the samples
+// inside each trace's mute window only (itd [ntr]), in one launch: npart [2 ntr]
+hipError_t launch_sumsq2_win(const float* x0, const float* x1, int ntr, int nt, const int32_t* itd, int shift,
+                             double* npart, hipStream_t s);
+// whole traces into npart, the samples outside the mute window into npart_out
+hipError_t launch_sumsq_out(const float* x, int ntr, int nt, const int32_t* itd, int shift, double* npart,
+                            double* npart_out, hipStream_t s);
 // out = f1p(t) - f1m(-t) per trace (f2+)
 hipError_t launch_f2p(const float* f1p, const float* f1m, int64_t ntr, int nt, float* out, hipStream_t s);
 // out = gp + gm elementwise (the total G)

@@ -213,4 +213,9 @@ def test_divergence_is_reported():
     with pytest.raises(mk.MKError) as ei:
         mk.mk_iterate(plan, 40)
     assert ei.value.status == mk.MK_ERR_DIVERGED
+    # the stopping rule's passes: the judge applies the same check
+    mk.mk_set_focal(plan, p.Gd, p.itd, p.shift)
+    with pytest.raises(mk.MKError) as ei:
+        mk.mk_iterate_tol(plan, 1e-9, 40)
+    assert ei.value.status == mk.MK_ERR_DIVERGED
     mk.mk_destroy(plan)

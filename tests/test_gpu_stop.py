@@ -116,3 +116,31 @@ def test_budget_and_arguments(problem):
     with pytest.raises(mk.MKError):
         mk.mk_iterate_tol(plan, 1e-3, -1)
     mk.mk_destroy(plan)
+
+
+@pytest.mark.parametrize("tail", [None, "geometric"])
+def test_fields_outside_the_mute_window_keep_their_start(problem, tail):
+    """The rule reads only the mute windows of f1+ and f1- and adds the
+    sums of squares of N_-1 outside them: that holds if nothing writes
+    there.  Outside every trace's window f1+ must still be N_-1 = G_d(-t)
+    and f1- zero, to the bit, after passes, a tail and its restart."""
+    mk = require_gpu()
+    p = problem
+    plan = _plan(mk, p)
+    mk.mk_tail_record(plan, 4, 64)
+    mk.mk_set_focal(plan, p.Gd, p.itd, p.shift)
+    mk.mk_iterate(plan, 4, want_norms=False)
+    if tail is not None:
+        mk.mk_tail_apply(plan, mk.TAIL_GEOMETRIC)
+    mk.mk_iterate_tol(plan, 1e-5, 20)
+    got = _fields(mk, plan, p)
+    mk.mk_destroy(plan)
+    nt = p.geom.nt
+    k = np.arange(nt)
+    L = np.minimum(p.itd.astype(np.int64) - p.shift, nt // 2)[..., None]
+    outside = ~((k < L) | (k > nt - L))
+    n_start = p.Gd[..., (-k) % nt]
+    say(f"outside-window samples: {int(outside.sum())} of {outside.size}, tail {tail}")
+    assert outside.any()
+    assert np.array_equal(got["f1plus"][outside], n_start[outside])
+    assert not got["f1minus"][outside].any()
