@@ -93,6 +93,21 @@ def test_autotuner_choice_passes_parity(tmp_path, monkeypatch):
         assert np.array_equal(g[k], g2[k])
 
 
+@pytest.mark.parametrize("rprec", [0, 1])
+def test_autotuner_with_bands(tmp_path, monkeypatch, rprec):
+    """Bands make the LDS-staged contraction walk its active tiles by default;
+    with the autotuner timing the variants on first use, whichever variant
+    it picks (walking or not) must keep parity."""
+    mk = require_gpu()
+    say(f"autotune with bands, rprec {rprec}")
+    monkeypatch.setenv("MK_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    p = small_problem(seed=52, n=48, nt=128, nf=20, niter=5)
+    rng = np.random.default_rng(9)
+    fb = np.stack([np.zeros(p.nf, np.int32), rng.integers(10, 65, p.nf).astype(np.int32)], axis=1)
+    g = run_gpu(p, fbands=fb, rprec=rprec, flags=mk.MK_FLAG_AUTOTUNE)
+    assert_parity(g, run_oracle(p, fbands=fb), tol=TOL[rprec], label=f"autotune-bands{rprec}")
+
+
 def test_medium_focal_line_batched():
     """601 x 601, nt 2048, 64 focal points: FP32 and FP16 batched, first 2 passes."""
     say("medium nf=64 batched")
