@@ -441,6 +441,19 @@ const char* mk_strerror(int32_t status);
  * NULL plan, the message of the last failed mk_plan on this thread. */
 const char* mk_last_error(mk_plan_t plan);
 
+/* mk_device_checks -- the device-side bounds checks of the checked build
+ * (the same library compiled with -DMK_DEVICE_CHECKS: every kernel compares
+ * the end of each range of a buffer it reads or writes with the end of the
+ * allocation behind the pointer it was given).  Waits for the device, then
+ * writes to *violations a bit mask of the kernel files whose checks failed
+ * since the last call (bit 0: per-trace kernels, 1: streaming contraction,
+ * 2: matrix-core contraction, 3: network, 4: series tail) and clears them.
+ * MK_ERR_UNSUPPORTED from a library built without the checks; MK_ERR_ARG if
+ * violations is NULL; MK_ERR_HIP if the device reports an error.  It reads
+ * no plan; it is for debugging runs, as the host sanitizer build is for the
+ * host code. */
+mk_status mk_device_checks(uint32_t* violations);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,6 +2,7 @@
 
     python -m paper_2106_04649_amd.build            # libmk.so
     python -m paper_2106_04649_amd.build --asan     # _build/asan/libmk_asan.so
+    python -m paper_2106_04649_amd.build --device-checks   # libmk_checked.so
 
 Each source compiles on its own (in parallel) and the objects are linked
 into ``paper_2106_04649_amd/libmk.so``.  The build always recompiles.  The
@@ -104,10 +105,46 @@ def build_sanitized(verbose: bool = False) -> str:
     return lib
 
 
+CHECKED_LIB = os.path.join(HERE, "libmk_checked.so")
+
+
+def build_checked(verbose: bool = False) -> str:
+    """The library with its device-side bounds checks compiled in
+    (-DMK_DEVICE_CHECKS, otherwise the normal flags): every kernel compares
+    the end of each range it addresses with the allocation behind the
+    pointer and records failures for mk_device_checks().  In-tree as
+    ``libmk_checked.so`` beside ``libmk.so``."""
+    out = os.path.join(BUILD, "checked")
+    os.makedirs(out, exist_ok=True)
+    flags = common_flags() + ["-DMK_DEVICE_CHECKS"]
+
+    def one(src: str) -> str:
+        obj = os.path.join(out, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc(), *flags, "-c", os.path.join(CSRC, src), "-o", obj]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"compile of {src} failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+        return obj
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(one, SOURCES))
+    tmp = CHECKED_LIB + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, CHECKED_LIB)
+    if verbose:
+        print(f"built {CHECKED_LIB}")
+    return CHECKED_LIB
+
+
 if __name__ == "__main__":
     try:
         if "--asan" in sys.argv[1:]:
             build_sanitized(verbose=True)
+        elif "--device-checks" in sys.argv[1:]:
+            build_checked(verbose=True)
         else:
             build(verbose=True)
     except RuntimeError as exc:

@@ -55,12 +55,16 @@ __device__ __forceinline__ float2 unpack16(uint32_t u) {
 template <int J, int NF>
 __global__ __launch_bounds__(kWaves * 64) void k_contract_c64(
     const v4f* __restrict__ R, const v4f* __restrict__ X, float2* __restrict__ Y,
-    int nr, int n4, int nload4, int64_t nrows, int64_t xstride4, int64_t ystride, int64_t per_xcd) {
+    int nr, int n4, int nload4, int64_t nrows, int64_t xstride4, int64_t ystride, int64_t per_xcd, Ext3 ext) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = xcd_block(per_xcd) * kWaves + (threadIdx.x >> 6);
     const int64_t q0 = wave * kRowsPerWave;
     if (q0 >= nrows) return;
     const int64_t q1 = q0 + kRowsPerWave < nrows ? q0 + kRowsPerWave : nrows;
+    // checked build: this run's rows of R, its X slabs and its Y entries
+    MK_DCHECK(((q1 - 1) * n4 + nload4) * 16 <= ext.r);
+    MK_DCHECK(((NF - 1) * xstride4 + (q1 - 1) / nr * n4 + nload4) * 16 <= ext.x);
+    MK_DCHECK(((NF - 1) * ystride + q1) * 8 <= ext.y);
 
     int w = (int)(q0 / nr);
     v4f xr[NF][J];
@@ -127,12 +131,16 @@ template <int J, int NF, int PREC>
 __global__ __launch_bounds__(kWaves * 64) void k_contract_q16(
     const v4u* __restrict__ R, const v4f* __restrict__ X, const float* __restrict__ rscale,
     float2* __restrict__ Y, int nr, int n16, int nload16, int n4, int64_t nrows, int64_t xstride4,
-    int64_t ystride, int64_t per_xcd) {
+    int64_t ystride, int64_t per_xcd, Ext3 ext) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = xcd_block(per_xcd) * kWaves + (threadIdx.x >> 6);
     const int64_t q0 = wave * kRowsPerWave;
     if (q0 >= nrows) return;
     const int64_t q1 = q0 + kRowsPerWave < nrows ? q0 + kRowsPerWave : nrows;
+    // checked build: this run's rows of R, its X slabs and its Y entries
+    MK_DCHECK(((q1 - 1) * n16 + nload16) * 16 <= ext.r);
+    MK_DCHECK(((NF - 1) * xstride4 + (q1 - 1) / nr * n4 + 2 * nload16) * 16 <= ext.x);
+    MK_DCHECK(((NF - 1) * ystride + q1) * 8 <= ext.y);
 
     int w = (int)(q0 / nr);
     v4f xr[NF][J][2];
@@ -208,20 +216,24 @@ void launch_one(const ContractArgs& c, const float2* X, float2* Yc, dim3 grid, d
     const int64_t nrows = (int64_t)c.nb * c.nr;
     const int64_t xstride4 = (int64_t)c.B * (c.ns_pad / 2);
     const int64_t ystride = (int64_t)c.B * c.nr;
+    // this column group's X and Y start past the launch's pointers
+    const Ext3 ext{c.ext_r,
+                   c.ext_x - (int64_t)(reinterpret_cast<const char*>(X) - static_cast<const char*>(c.X)),
+                   c.ext_y - (int64_t)(reinterpret_cast<const char*>(Yc) - reinterpret_cast<const char*>(c.Y))};
     if (c.prec == MK_R_C64) {
         hipLaunchKernelGGL((k_contract_c64<J, NF>), grid, block, 0, s,
                            reinterpret_cast<const v4f*>(c.R), reinterpret_cast<const v4f*>(X), Yc, c.nr,
-                           c.ns_pad / 2, (c.ns + 1) / 2, nrows, xstride4, ystride, per_xcd);
+                           c.ns_pad / 2, (c.ns + 1) / 2, nrows, xstride4, ystride, per_xcd, ext);
     } else if (c.prec == MK_R_F16S) {
         hipLaunchKernelGGL((k_contract_q16<J, NF, MK_R_F16S>), grid, block, 0, s,
                            reinterpret_cast<const v4u*>(c.R), reinterpret_cast<const v4f*>(X), c.rscale,
                            Yc, c.nr, c.ns_pad / 4, (c.ns + 3) / 4, c.ns_pad / 2, nrows, xstride4, ystride,
-                           per_xcd);
+                           per_xcd, ext);
     } else {
         hipLaunchKernelGGL((k_contract_q16<J, NF, MK_R_BF16S>), grid, block, 0, s,
                            reinterpret_cast<const v4u*>(c.R), reinterpret_cast<const v4f*>(X), c.rscale,
                            Yc, c.nr, c.ns_pad / 4, (c.ns + 3) / 4, c.ns_pad / 2, nrows, xstride4, ystride,
-                           per_xcd);
+                           per_xcd, ext);
     }
 }
 
@@ -281,6 +293,9 @@ __global__ void k_check_finite(const float* __restrict__ x, int64_t n, int* __re
 }
 
 }  // namespace
+
+MK_CHECK_TAKE(check_take_contract)
+
 
 hipError_t launch_contract_gemv(const ContractArgs& c, hipStream_t s) {
     // 16-byte chunks per row: 2 complex (complex64) or 4 complex (16-bit)

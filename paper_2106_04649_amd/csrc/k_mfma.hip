@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
     const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
     const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
     int ncols_mul, int nr, int ns_pad, int B, int nfc, int ftiles, int rtiles, int64_t ntiles,
-    int64_t per_xcd) {
+    int64_t per_xcd, Ext3 ext) {
     constexpr int FT = 32 * WM;      // focal-real rows per block
     constexpr int RT = 32 * WN;      // receivers per block
     const int lane = threadIdx.x & 63;
@@ -97,6 +97,15 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
     const int w = (int)(t2 / rtiles);
     const int nact = ncols_w ? min(ncols_w[w] * ncols_mul, nfc) : nfc;
     if (ft * (FT / 2) >= nact) return;
+    {
+        // checked build: the rows of R and X this tile reads and the Y it writes
+        constexpr int64_t EB = PREC == MK_R_C64 ? 8 : 4;
+        const int64_t fmax = min(ft * (FT / 2) + FT / 2, nact) - 1;
+        const int64_t rmax = min(rt * RT + RT, nr) - 1;
+        MK_DCHECK(((int64_t)w * nr + rmax + 1) * ns_pad * EB <= ext.r);
+        MK_DCHECK(((SPLIT ? (int64_t)nfc * B * ns_pad : 0) + (fmax * B + w + 1) * ns_pad) * EB <= ext.x);
+        MK_DCHECK(((fmax * B + w) * nr + nr) * 8 <= ext.y);
+    }
 
     const int i16 = lane & 15, g = lane >> 4;
     const int n0 = ft * FT + wm * 16 * WM;
@@ -303,7 +312,7 @@ __device__ __forceinline__ void contract_lds_tile(
     const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
     const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
     int ncols_mul, int nr, int ns_pad, int B, int nfc, int ftiles, int rtiles, int64_t t,
-    unsigned char* __restrict__ lds) {
+    unsigned char* __restrict__ lds, const Ext3& ext) {
     constexpr bool C64 = PREC == MK_R_C64;
     constexpr int PLANES = SPLIT ? 2 : 1;
     constexpr int NFB = 8 * RA;                   // focal columns per block
@@ -335,6 +344,14 @@ __device__ __forceinline__ void contract_lds_tile(
     const int rowbytes = ns_pad * EB;
     const int nch = rowbytes / CB;                // rows are whole chunks (checked at launch)
     const int64_t lo_bytes = (int64_t)nfc * B * rowbytes;
+    {
+        // checked build: the bin's R, the tile's rows of X (both planes) and its Y
+        const int64_t fmax = min(fbase + NFB, nact) - 1;
+        const int64_t rbin = TILED ? (int64_t)((nr + kTileRows - 1) / kTileRows) * nch * 2048 : (int64_t)nr * rowbytes;
+        MK_DCHECK((int64_t)(w + 1) * rbin <= ext.r);
+        MK_DCHECK((PLANES - 1) * lo_bytes + (fmax * B + w + 1) * rowbytes <= ext.x);
+        MK_DCHECK(((fmax * B + w) * nr + nr) * 8 <= ext.y);
+    }
 
     // ---- X staging: chunk c -> registers -> LDS buffer (both forms) --------
     auto stage_load = [&](int c, v4u (&xr)[NV]) {
@@ -557,13 +574,13 @@ __global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
     const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
     const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
     int ncols_mul, int nr, int ns_pad, int B, int nfc, int ftiles, int rtiles, int64_t ntiles,
-    int64_t per_xcd) {
+    int64_t per_xcd, Ext3 ext) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[lds_tile_bytes<PREC, RA, SPLIT>()];
     const int64_t bid = blockIdx.x;
     const int64_t t = (bid & 7) * per_xcd + (bid >> 3);
     if (t >= ntiles) return;
     contract_lds_tile<PREC, RA, SPLIT, TILED>(Rv, rscale, Xv, xscale, Y, ncols_w, ncols_mul, nr, ns_pad, B, nfc,
-                                              ftiles, rtiles, t, lds);
+                                              ftiles, rtiles, t, lds, ext);
 }
 
 // Persistent form: a fixed grid (every block resident at once) walks a list
@@ -577,7 +594,7 @@ __global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds_walk(
     const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
     const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
     int ncols_mul, int nr, int ns_pad, int B, int nfc, int ftiles, int rtiles,
-    const int* __restrict__ items) {
+    const int* __restrict__ items, Ext3 ext) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[lds_tile_bytes<PREC, RA, SPLIT>()];
     const int nitems = items[0];                  // the list: [count, tiles...]
     const int x = (int)(blockIdx.x & 7);
@@ -586,7 +603,7 @@ __global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds_walk(
     const int step = (int)(gridDim.x >> 3);
     for (int i = lo + (int)(blockIdx.x >> 3); i < hi; i += step) {
         contract_lds_tile<PREC, RA, SPLIT, TILED>(Rv, rscale, Xv, xscale, Y, ncols_w, ncols_mul, nr, ns_pad, B,
-                                                  nfc, ftiles, rtiles, items[1 + i], lds);
+                                                  nfc, ftiles, rtiles, items[1 + i], lds, ext);
         __syncthreads();                          // the next tile restages the LDS buffers
     }
 }
@@ -601,14 +618,14 @@ hipError_t launch_l(const ContractArgs& c, hipStream_t s) {
         const int grid = 8 * std::max(1, c.walk_blocks_per_xcd / (RA >= 8 ? 2 : 1));
         hipLaunchKernelGGL((k_contract_lds_walk<PREC, RA, SPLIT, TILED>), dim3((unsigned)grid), dim3(256), 0, s,
                            c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B, c.ncols,
-                           ftiles, rtiles, c.items);
+                           ftiles, rtiles, c.items, Ext3{c.ext_r, c.ext_x, c.ext_y});
         return hipGetLastError();
     }
     const int64_t ntiles = (int64_t)ftiles * rtiles * c.nb;
     const int64_t per_xcd = (ntiles + 7) / 8;
     hipLaunchKernelGGL((k_contract_lds<PREC, RA, SPLIT, TILED>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s,
                        c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B, c.ncols,
-                       ftiles, rtiles, ntiles, per_xcd);
+                       ftiles, rtiles, ntiles, per_xcd, Ext3{c.ext_r, c.ext_x, c.ext_y});
     return hipGetLastError();
 }
 
@@ -621,7 +638,7 @@ hipError_t launch_v(const ContractArgs& c, hipStream_t s) {
     const int64_t per_xcd = (ntiles + 7) / 8;
     hipLaunchKernelGGL((k_contract_mfma<PREC, WM, WN, SPLIT>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s,
                        c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B, c.ncols,
-                       ftiles, rtiles, ntiles, per_xcd);
+                       ftiles, rtiles, ntiles, per_xcd, Ext3{c.ext_r, c.ext_x, c.ext_y});
     return hipGetLastError();
 }
 
@@ -649,6 +666,9 @@ hipError_t launch_p(const ContractArgs& c, int variant, hipStream_t s) {
 }
 
 }  // namespace
+
+MK_CHECK_TAKE(check_take_mfma)
+
 
 // contraction variant v (0 = GEMV, 1 + i = matrix-core shape i) reads tiled R
 bool contract_variant_reads_tiled(int variant) { return variant >= 6 && variant <= 8; }

@@ -436,7 +436,8 @@ template <int KP>
 __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, const h8* __restrict__ wpk,
                                                   const float* __restrict__ hist,
                                                   const float* __restrict__ scale, const int32_t* __restrict__ itd,
-                                                  int shift, int k, int T, int nt, float* __restrict__ f1p) {
+                                                  int shift, int k, int T, int nt, float* __restrict__ f1p,
+                                                  Ext3 ext) {
     constexpr int XP = KP == 16 ? kHP : KP;    // halves per staged input sample
     constexpr int S1 = ksteps<KP>(), S2 = ksteps<kFH>();
     constexpr int U2 = kXN * XP > kA2N * kHP ? kXN * XP : kA2N * kHP;
@@ -450,6 +451,8 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
     // the CU cover it)
     const int L = itd[tr] - shift;
     if (L <= 0 || t0 >= hT + L || t0 + kFT <= hT - L + 1) return;
+    // checked build: this trace's recorded iterates and its f1+
+    MK_DCHECK((int64_t)(tr + 1) * k * T * 4 <= ext.r && (int64_t)(tr + 1) * nt * 4 <= ext.y);
     const float se = scale[tr];
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int i16 = lane & 15, g = lane >> 4;
@@ -611,6 +614,8 @@ __global__ __launch_bounds__(256) void k_net_tail(const float* __restrict__ P, c
 
 }  // namespace
 
+MK_CHECK_TAKE(check_take_net)
+
 // Parameter layout (one FP32 vector): W1 [H][k][5], b1 [H], W2 [H][H][5],
 // b2 [H], W3 [2][H][5], b3 [2].
 int net_param_count(int k, int H) {
@@ -664,12 +669,14 @@ hipError_t net_tail_apply(const float* P, const void* wpack, const float* hist, 
     if (ntr <= 0 || T <= 0) return hipSuccess;
     const h8* w = static_cast<const h8*>(wpack);
     const dim3 grid(ntr, (T + kFT - 1) / kFT);
+    const Ext3 ext{device_extent(hist), kExtentUnknown, device_extent(f1p)};
     if (k <= 4)
-        hipLaunchKernelGGL(k_net_tail<4>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p);
+        hipLaunchKernelGGL(k_net_tail<4>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p, ext);
     else if (k <= 8)
-        hipLaunchKernelGGL(k_net_tail<8>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p);
+        hipLaunchKernelGGL(k_net_tail<8>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p, ext);
     else
-        hipLaunchKernelGGL(k_net_tail<16>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p);
+        hipLaunchKernelGGL(k_net_tail<16>, grid, dim3(256), 0, s, P, w, hist, scale, itd, shift, k, T, nt, f1p,
+                           ext);
     return hipGetLastError();
 }
 

@@ -21,10 +21,13 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 // over the window (0 for a silent trace, which the network then skips); with
 // x NULL only s_tr is written (the fused network scales as it stages).
 __global__ __launch_bounds__(256) void k_tail_prep(const float* __restrict__ hist, int ntr, int k, int T,
-                                                   float* __restrict__ x, float* __restrict__ scale) {
+                                                   float* __restrict__ x, float* __restrict__ scale, Ext3 ext) {
     const int lane = threadIdx.x & 63;
     const int tr = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tr >= ntr) return;
+    // checked build: this trace's recorded iterates, and its scaled copy
+    MK_DCHECK((int64_t)(tr + 1) * k * T * 4 <= ext.r);
+    if (x) MK_DCHECK((int64_t)(tr + 1) * k * T * 4 <= ext.x);
     const float* h = hist + (size_t)tr * k * T;
     float ss = 0.f;
     for (int u = lane; u < T; u += 64) ss += h[u] * h[u];
@@ -43,10 +46,14 @@ __global__ __launch_bounds__(256) void k_tail_prep(const float* __restrict__ his
 __global__ __launch_bounds__(256) void k_tail_apply(const float* __restrict__ hist, const float* __restrict__ y,
                                                     const float* __restrict__ scale, const int32_t* __restrict__ itd,
                                                     int shift, int ntr, int k, int T, int nt, int mode,
-                                                    float* __restrict__ f1p) {
+                                                    float* __restrict__ f1p, Ext3 ext) {
     const int lane = threadIdx.x & 63;
     const int tr = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tr >= ntr) return;
+    // checked build: this trace's recorded iterates, network output and f1+
+    MK_DCHECK((int64_t)(tr + 1) * k * T * 4 <= ext.r);
+    if (mode == 0) MK_DCHECK((int64_t)(tr + 1) * 2 * T * 4 <= ext.x);
+    MK_DCHECK((int64_t)(tr + 1) * nt * 4 <= ext.y);
     const float* h = hist + (size_t)tr * k * T;
     const int L = itd[tr] - shift;
     const int hT = T >> 1;
@@ -103,9 +110,13 @@ __global__ __launch_bounds__(256) void k_tail_apply(const float* __restrict__ hi
 
 }  // namespace
 
+MK_CHECK_TAKE(check_take_tail)
+
+
 hipError_t launch_tail_prep(const float* hist, int ntr, int k, int T, float* x, float* scale, hipStream_t s) {
     if (ntr <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tail_prep, dim3((ntr + 3) / 4), dim3(256), 0, s, hist, ntr, k, T, x, scale);
+    hipLaunchKernelGGL(k_tail_prep, dim3((ntr + 3) / 4), dim3(256), 0, s, hist, ntr, k, T, x, scale,
+                       Ext3{device_extent(hist), device_extent(x), kExtentUnknown});
     return hipGetLastError();
 }
 
@@ -113,6 +124,6 @@ hipError_t launch_tail_apply(const float* hist, const float* y, const float* sca
                              int ntr, int k, int T, int nt, int mode, float* f1p, hipStream_t s) {
     if (ntr <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_tail_apply, dim3((ntr + 3) / 4), dim3(256), 0, s, hist, y, scale, itd, shift, ntr, k, T,
-                       nt, mode, f1p);
+                       nt, mode, f1p, Ext3{device_extent(hist), device_extent(y), device_extent(f1p)});
     return hipGetLastError();
 }

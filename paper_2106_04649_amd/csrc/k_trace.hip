@@ -512,6 +512,36 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
     }
     const size_t tbase = ((size_t)f * a.nr + r) * NT;
     const float s = a.scale;
+    {
+        // checked build: every range this trace addresses ends inside its buffer
+        const int64_t tend = (int64_t)(tbase + NT) * 4;           // per-trace fields, float
+        if constexpr (YIN) MK_DCHECK((int64_t)(fo + 1) * a.B * a.nr * 8 <= a.ext[TE_Y]);
+        if constexpr (MODE == TM_INIT) {
+            MK_DCHECK(tend <= a.ext[TE_SRC] && tend <= a.ext[TE_F1P] && tend <= a.ext[TE_F1M]);
+            if (a.n0) MK_DCHECK(tend <= a.ext[TE_N0]);
+        } else if constexpr (MODE == TM_ITER) {
+            MK_DCHECK(tend <= a.ext[a.parity == 0 ? TE_F1M : TE_F1P]);
+            if (a.hist && a.rec_slot >= 0)
+                MK_DCHECK((((int64_t)f * a.nr + r) * a.hist_k + a.rec_slot + 1) * a.hist_T * 4 <= a.ext[TE_HIST]);
+        } else if constexpr (MODE == TM_GFWD || MODE == TM_GOUT) {
+            MK_DCHECK(tend <= a.ext[TE_F1P] && tend <= a.ext[TE_F1M]);
+            if constexpr (MODE == TM_GOUT) MK_DCHECK(tend <= a.ext[TE_GP] && tend <= a.ext[TE_GM]);
+        } else if constexpr (MODE == TM_FWDF) {
+            MK_DCHECK(tend <= a.ext[TE_F1P]);
+        } else if constexpr (MODE == TM_RST1) {
+            MK_DCHECK(tend <= a.ext[TE_F1M]);
+        } else if constexpr (MODE == TM_RST2) {
+            MK_DCHECK(tend <= a.ext[TE_N0] && tend <= a.ext[TE_F1P]);
+        } else if constexpr (MODE == TM_POUT) {
+            MK_DCHECK(tend <= a.ext[TE_F1P] && tend <= a.ext[TE_F1M] && tend <= a.ext[TE_GP] &&
+                      tend <= a.ext[TE_GM] && tend <= a.ext[TE_AUX]);
+        }
+        if constexpr (MODE != TM_GOUT && MODE != TM_POUT) {       // X out: [planes][nfo][B][ns_pad]
+            const bool x16 = a.xprec != XP_F32, split = a.xprec == XP_F16X2 || a.xprec == XP_BF16X2;
+            MK_DCHECK(a.nr <= a.ns_pad && (int64_t)((split ? a.nfo : 0) + fo + 1) * a.B * a.ns_pad * (x16 ? 4 : 8) <=
+                                              a.ext[TE_X]);
+        }
+    }
     // window of the mute, |t| < L (loaded first: the f1 addresses depend on it)
     [[maybe_unused]] int L = 0;
     if constexpr (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2)
@@ -1201,6 +1231,9 @@ hipError_t launch_trace_nt(int mode, const TraceArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+MK_CHECK_TAKE(check_take_trace)
+
 
 hipError_t launch_trace(int mode, int nt, const TraceArgs& a, hipStream_t s) {
     if (a.nfo * a.nr <= 0) return hipSuccess;

@@ -13,6 +13,33 @@
 
 #include "mk_internal.h"
 
+// Bytes from `ptr` to the end of the device allocation behind it, for the
+// checked build's kernel-side bounds checks (0 for a null pointer; unknown,
+// which passes every check, in the normal build or when the runtime does not
+// know the pointer).
+int64_t device_extent(const void* ptr) {
+#ifdef MK_DEVICE_CHECKS
+    if (!ptr) return 0;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(ptr)) != hipSuccess) {
+        (void)hipGetLastError();
+        return kExtentUnknown;
+    }
+    const int64_t ext = (int64_t)size - (int64_t)(static_cast<const char*>(ptr) - static_cast<const char*>(base));
+    // a test hook: report extents this many bytes short, so that the checks
+    // fire on accesses that are in bounds
+    static const int64_t shrink = [] {
+        const char* v = std::getenv("MK_CHECK_SHRINK");
+        return v ? std::atoll(v) : 0LL;
+    }();
+    return ext - shrink;
+#else
+    (void)ptr;
+    return kExtentUnknown;
+#endif
+}
+
 namespace {
 
 thread_local std::string g_plan_error;
@@ -166,6 +193,12 @@ int heuristic_variant(mk_plan_t p, int ncols) {
 // whether contraction variant v can read the plan's layout of R
 bool variant_fits(mk_plan_t p, int v) { return contract_variant_reads_tiled(v) || !p->r_tiled; }
 
+void set_contract_extents(ContractArgs& c) {
+    c.ext_r = device_extent(c.R);
+    c.ext_x = device_extent(c.X);
+    c.ext_y = device_extent(c.Y);
+}
+
 ContractArgs contract_args(mk_plan_t p, const void* X, int ncols, int ncols_mul) {
     ContractArgs c{};
     c.R = p->R;
@@ -183,6 +216,7 @@ ContractArgs contract_args(mk_plan_t p, const void* X, int ncols, int ncols_mul)
     c.B = p->B;
     c.ncols = ncols;
     c.nb = p->B;
+    set_contract_extents(c);
     return c;
 }
 
@@ -343,6 +377,7 @@ mk_status contract_streamed(mk_plan_t p, const ContractArgs& c, int variant, int
         cj.Y = c.Y + (size_t)w0 * c.nr;
         cj.ncols_w = c.ncols_w ? c.ncols_w + w0 : nullptr;
         cj.nb = std::min(p->slab_bins, p->B - w0);
+        set_contract_extents(cj);
         HIP_TRY(p, launch_choice(cj, variant, p->stream));
         HIP_TRY(p, hipEventRecord(p->ev_consumed[buf], p->stream));
         ++p->slab_use;
@@ -371,7 +406,10 @@ mk_status run_contract(mk_plan_t p, const ContractChoice& ch, const void* Xbuf, 
     return MK_OK;
 }
 
-mk_status run_trace(mk_plan_t p, int mode, const TraceArgs& a, int kind) {
+mk_status run_trace(mk_plan_t p, int mode, const TraceArgs& a0, int kind) {
+    TraceArgs a = a0;
+    const void* bufs[TE_COUNT] = {a.Y, a.X, a.src, a.f1p, a.f1m, a.gp, a.gm, a.aux, a.n0, a.hist};
+    for (int i = 0; i < TE_COUNT; ++i) a.ext[i] = device_extent(bufs[i]);
     hipEvent_t ev = nullptr;
     HIP_TRY(p, prof_begin(p, &ev));
     HIP_TRY(p, launch_trace(mode, p->d.nt, a, p->stream));
@@ -1647,6 +1685,26 @@ mk_status mk_set_state(mk_plan_t p, const void* blob, size_t bytes) {
     p->g_valid = false;
     p->focal_set = true;
     return MK_OK;
+}
+
+mk_status mk_device_checks(uint32_t* violations) {
+    if (!violations) return fail(nullptr, MK_ERR_ARG, "mk_device_checks: violations is NULL");
+    *violations = 0;
+#ifndef MK_DEVICE_CHECKS
+    return fail(nullptr, MK_ERR_UNSUPPORTED, "mk_device_checks: this library was built without device checks");
+#else
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(nullptr, MK_ERR_HIP, std::string("mk_device_checks: ") + hipGetErrorString(e));
+    hipError_t (*take[])(unsigned*) = {check_take_trace, check_take_contract, check_take_mfma, check_take_net,
+                                       check_take_tail};
+    for (int i = 0; i < 5; ++i) {
+        unsigned v = 0;
+        if ((e = take[i](&v)) != hipSuccess)
+            return fail(nullptr, MK_ERR_HIP, std::string("mk_device_checks: ") + hipGetErrorString(e));
+        if (v) *violations |= 1u << i;
+    }
+    return MK_OK;
+#endif
 }
 
 mk_status mk_destroy(mk_plan_t p) {

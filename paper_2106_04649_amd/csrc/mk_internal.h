@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "mk.h"
+#include "mk_check.h"
 
 // Per-trace kernel modes (one wave per trace of nt samples).
 enum TraceMode : int {
@@ -25,6 +26,9 @@ enum TraceMode : int {
 // Storage of the contraction input X.  The X2 forms keep a 16-bit "hi" plane
 // and a 16-bit "lo" plane (x ~ hi + lo) for two matrix-core products.
 enum XPrec : int { XP_F32 = 0, XP_F16 = 1, XP_BF16 = 2, XP_F16X2 = 3, XP_BF16X2 = 4 };
+
+// Buffers of the per-trace kernel whose extents the checked build tests.
+enum TraceExt : int { TE_Y, TE_X, TE_SRC, TE_F1P, TE_F1M, TE_GP, TE_GM, TE_AUX, TE_N0, TE_HIST, TE_COUNT };
 
 // Arguments of the per-trace kernel.  Layouts (all row-major):
 //   Y   [nfo][B][nr]        complex, contraction output (unscaled sum over s)
@@ -63,6 +67,8 @@ struct TraceArgs {
     int shift;
     int parity;    // pass index & 1 (TM_ITER)
     float scale;   // c / (nt / 2): Riemann weight and inverse-FFT normalisation
+    // bytes from each pointer to the end of its allocation (checked build)
+    int64_t ext[TE_COUNT];
 };
 
 struct ProfileSlot {
@@ -231,7 +237,27 @@ struct ContractArgs {
     // (half as many for the one-wave 128-row tiles)
     const int* items = nullptr;
     int walk_blocks_per_xcd = 0;
+    // bytes from R, X and Y to the end of their allocations (checked build)
+    int64_t ext_r = kExtentUnknown, ext_x = kExtentUnknown, ext_y = kExtentUnknown;
 };
+
+// extents (bytes from the pointer to the end of its allocation) of a
+// contraction launch's R, X and Y, for the checked build
+struct Ext3 {
+    int64_t r, x, y;
+};
+
+// bytes from ptr to the end of the device allocation behind it (checked
+// build; 0 for NULL; kExtentUnknown in the normal build)
+int64_t device_extent(const void* ptr);
+
+// the checked build's bounds-check words, one per translation unit (read
+// and cleared; always 0 in the normal build)
+hipError_t check_take_trace(unsigned* out);
+hipError_t check_take_contract(unsigned* out);
+hipError_t check_take_mfma(unsigned* out);
+hipError_t check_take_net(unsigned* out);
+hipError_t check_take_tail(unsigned* out);
 
 // kernel launchers (return hipSuccess or the launch error)
 hipError_t launch_trace(int mode, int nt, const TraceArgs& a, hipStream_t s);

@@ -19,7 +19,10 @@ from typing import Optional, Tuple
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmk.so")
+# MK_LIBRARY selects another build of the same library, such as
+# libmk_checked.so (device-side bounds checks); it must exist as well
+LIB_PATH = os.environ.get("MK_LIBRARY") or os.path.join(HERE, "libmk.so")
+CHECKED_LIB_PATH = os.path.join(HERE, "libmk_checked.so")
 
 MK_OK, MK_ERR_ARG, MK_ERR_STATE, MK_ERR_OOM, MK_ERR_HIP, MK_ERR_UNSUPPORTED, MK_ERR_DIVERGED = range(7)
 MK_R_C64, MK_R_F16S, MK_R_BF16S = 0, 1, 2
@@ -100,6 +103,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mk_net_round": (i32, [P, P, i32, P]),
         "mk_strerror": (ctypes.c_char_p, [i32]),
         "mk_last_error": (ctypes.c_char_p, [P]),
+        "mk_device_checks": (i32, [ctypes.POINTER(ctypes.c_uint32)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -314,6 +318,15 @@ def mk_set_state(plan: Plan, blob: bytes) -> None:
     _check(load_library().mk_set_state(plan.handle, buf, len(blob)), plan.handle)
     # the blob's header: 8 magic bytes, then int32 nr, nt, iw_lo, iw_hi, ns_pad, rprec, flags, nf, ...
     plan.nf = int.from_bytes(bytes(blob)[36:40], "little", signed=True)
+
+
+def mk_device_checks() -> int:
+    """Bit mask of the kernel files whose device-side bounds checks failed
+    since the last call (0: none), from the checked build; raises MKError
+    (MK_ERR_UNSUPPORTED) on the normal build."""
+    v = ctypes.c_uint32(0)
+    _check(load_library().mk_device_checks(ctypes.byref(v)), None)
+    return int(v.value)
 
 
 def mk_destroy(plan: Plan) -> None:

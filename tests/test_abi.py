@@ -36,6 +36,20 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, name), name
 
 
+def test_device_checks_need_the_checked_build(lib):
+    v = ctypes.c_uint32(7)
+    assert lib.mk_device_checks(None) == mk.MK_ERR_ARG
+    assert lib.mk_device_checks(ctypes.byref(v)) == mk.MK_ERR_UNSUPPORTED and v.value == 0
+
+
+def test_checked_build_exports_every_declared_symbol():
+    if not os.path.exists(mk.CHECKED_LIB_PATH):
+        pytest.skip("libmk_checked.so is not built (python -m paper_2106_04649_amd.build --device-checks)")
+    checked = ctypes.CDLL(mk.CHECKED_LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(checked, name), name
+
+
 def test_strerror(lib):
     for s in range(7):
         assert lib.mk_strerror(s).decode()
