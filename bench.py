@@ -338,9 +338,11 @@ def mixed_leg(args) -> dict:
            "nf": pm.nf, "mean_band_bins": float(widths.mean()), "sampled_focal_points": sample, "paths": {}}
     # fp16_graph: the banded plan's default, the contraction as a persistent
     # kernel walking the active tiles; fp16_graph_grid: one block per tile
-    # (MK_FLAG_GRID), the form the walk replaces
+    # (MK_FLAG_GRID), the form the walk replaces; fp16_1x_graph: one 16-bit
+    # plane of X (MK_FLAG_FAST_X), half the products and X bytes
     for name, rprec, flags in (("fp16_graph", 1, mk.MK_FLAG_GRAPH),
-                               ("fp16_graph_grid", 1, mk.MK_FLAG_GRAPH | mk.MK_FLAG_GRID), ("fp32", 0, 0)):
+                               ("fp16_graph_grid", 1, mk.MK_FLAG_GRAPH | mk.MK_FLAG_GRID),
+                               ("fp16_1x_graph", 1, mk.MK_FLAG_GRAPH | mk.MK_FLAG_FAST_X), ("fp32", 0, 0)):
         r = Runner(pm, rprec=rprec, flags=flags, niter=pm.niter)
         wall = r.time(args.steps, args.warmup)
         r.norms()
@@ -353,7 +355,7 @@ def mixed_leg(args) -> dict:
                               "max_rel_l2_vs_oracle": {k: float(f"{v:.3e}") for k, v in err.items()}}
         log(f"mixed {name}: {out['paths'][name]['ms_per_step']} ms per solve, worst error "
             f"{max(err.values()):.2e}")
-    for name in ("fp16_graph", "fp16_graph_grid"):
+    for name in ("fp16_graph", "fp16_graph_grid", "fp16_1x_graph"):
         out[f"{name}_over_fp32"] = round(out["paths"]["fp32"]["ms_per_step"] / out["paths"][name]["ms_per_step"], 3)
     if not args.no_profile:
         avg_s, _, variant = profile_contract(pm, 1)
