@@ -700,22 +700,31 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
                 const float ry = __shfl(x[QN - 1 - e].y, 63 - lane, 64);
                 xr[e] = make_float2(lane == 0 ? rb : ra, ry);
             }
+            // Outside the window N'' is zero and f1+ still holds N_-1 (no pass,
+            // tail or restart writes there), so f1+ keeps its value and rho is
+            // zero: only the pairs that meet the window are read and written.
+            auto inw = [&](int idx) -> bool { return valid & (win(2 * idx) | win(2 * idx + 1)); };
             constexpr int FCH = 8;              // elements whose reads are in flight together
 #pragma unroll
             for (int e0 = 0; e0 < QN; e0 += FCH) {
                 float2 b0[FCH], fo[FCH];
 #pragma unroll
                 for (int c = 0; c < FCH; ++c) {
-                    b0[c] = n0p[lane + 64 * (e0 + c)];
-                    fo[c] = fpp[lane + 64 * (e0 + c)];
+                    const int idx = lane + 64 * (e0 + c);
+                    b0[c] = n0p[inw(idx) ? idx : 0];
+                    fo[c] = fpp[inw(idx) ? idx : 0];
                 }
 #pragma unroll
                 for (int c = 0; c < FCH; ++c) {
-                    const int e = e0 + c;
+                    const int e = e0 + c, idx = lane + 64 * e;
                     const float2 nf2 = make_float2(b0[c].x - xr[e].x, b0[c].y - xr[e].y);
-                    const float2 rho = make_float2(nf2.x - fo[c].x, nf2.y - fo[c].y);
+                    float2 rho = make_float2(nf2.x - fo[c].x, nf2.y - fo[c].y);
+                    if (inw(idx)) {
+                        fpp[idx] = nf2;
+                    } else {
+                        rho = make_float2(0.f, 0.f);
+                    }
                     nacc += (double)rho.x * rho.x + (double)rho.y * rho.y;
-                    if (valid) fpp[lane + 64 * e] = nf2;
                     x[e] = rho;
                 }
             }
