@@ -544,7 +544,7 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
     }
     // window of the mute, |t| < L (loaded first: the f1 addresses depend on it)
     [[maybe_unused]] int L = 0;
-    if constexpr (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2)
+    if constexpr (MODE == TM_ITER || MODE == TM_RST1 || MODE == TM_RST2 || MODE == TM_GOUT)
         L = min(a.itd[f * a.nr + r] - a.shift, M);     // |t| < L; t = -M is never kept
     float2 tqv[TQP];
 #pragma unroll
@@ -679,10 +679,12 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
                 }
             }
         } else if constexpr (MODE == TM_RST1) {  // f1- := theta S f1+ = Q
-            if (valid) {
+            // Q is zero outside the window, where f1- already is: only the
+            // pairs that meet the window are written
 #pragma unroll
-                for (int e = 0; e < QN; ++e)
-                    reinterpret_cast<float2*>(a.f1m + tbase)[lane + 64 * e] = x[e];
+            for (int e = 0; e < QN; ++e) {
+                const int idx = lane + 64 * e;
+                if (valid & (win(2 * idx) | win(2 * idx + 1))) reinterpret_cast<float2*>(a.f1m + tbase)[idx] = x[e];
             }
         } else {
             // TM_RST2: N'' = -Q(-t); f1+ := N_-1 + N''; the residual rho = N_-1 + N'' - f1+
@@ -893,8 +895,18 @@ __global__ __launch_bounds__(256, (TPT == 64 && NT <= 2048) ? 4 : 1) void k_trac
             const bool plus = (fo & 1) != 0;
             if constexpr (TPT == 64 && M >= 64) {
                 if (!plus) {
+                    // f1- is zero outside the window: only the pairs that meet
+                    // it are read (the others load the trace's first pair and
+                    // mask the bits)
 #pragma unroll
-                    for (int p = 0; p < PM; ++p) out[p] = reinterpret_cast<const float2*>(a.f1m + tbase)[lane + 64 * p];
+                    for (int p = 0; p < PM; ++p) {
+                        const int m = lane + 64 * p;
+                        const bool w = win(2 * m) | win(2 * m + 1);
+                        const float2 v = reinterpret_cast<const float2*>(a.f1m + tbase)[w ? m : 0];
+                        const uint32_t msk = w ? 0xFFFFFFFFu : 0u;
+                        out[p] = make_float2(__uint_as_float(__float_as_uint(v.x) & msk),
+                                             __uint_as_float(__float_as_uint(v.y) & msk));
+                    }
                 } else {
                     load_reversed<NT>(a.f1p + tbase, lane, out);     // f1+(-t)
                 }
