@@ -11,6 +11,7 @@
 // when the run crosses into the next frequency), streams its rows with
 // non-temporal 16-byte loads, reduces each row across the wave with DPP adds,
 // and stores the run's results with one coalesced store per focal column.
+// The run length depends on the number of focal columns (RunShape below).
 #include "mk_internal.h"
 
 namespace {
@@ -18,8 +19,21 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
-constexpr int kWaves = 4;          // waves per block
-constexpr int kRowsPerWave = 32;   // rows per wave run (<= 64)
+// Rows per wave run (<= 64) and waves per block, by precision and focal
+// columns.  Short runs make short-lived waves, and the waves resident at any
+// moment then read a dense window of R, which streams faster than a few
+// thousand long runs spread over the whole matrix; but each run loads its
+// bin's X (from L2), which long runs amortise.  Measured at 601 x 601 x 1025
+// bins (us per launch, against 32-row runs of four waves): complex64 with one
+// column, one row per wave (405 against 447); with two, 4-row runs of eight
+// waves (440 against 467); 16-bit R with one column, 4-row runs (216 against
+// 238).  Four columns, and 16-bit R with two, keep 32-row runs.
+template <int PREC, int NF>
+struct RunShape {
+    static constexpr bool c64 = PREC == MK_R_C64;
+    static constexpr int rows = NF == 1 ? (c64 ? 1 : 4) : (NF == 2 && c64 ? 4 : 32);
+    static constexpr int waves = NF == 2 && c64 ? 8 : 4;
+};
 
 // Sum over the 64 lanes; the total lands in lane 63.
 __device__ __forceinline__ float wave_sum_to63(float v) {
@@ -52,15 +66,15 @@ __device__ __forceinline__ float2 unpack16(uint32_t u) {
 }
 
 // Complex64 R: one 16-byte load = 2 complex values.
-template <int J, int NF>
-__global__ __launch_bounds__(kWaves * 64) void k_contract_c64(
+template <int J, int NF, int RPW, int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_contract_c64(
     const v4f* __restrict__ R, const v4f* __restrict__ X, float2* __restrict__ Y,
     int nr, int n4, int nload4, int64_t nrows, int64_t xstride4, int64_t ystride, int64_t per_xcd, Ext3 ext) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = xcd_block(per_xcd) * kWaves + (threadIdx.x >> 6);
-    const int64_t q0 = wave * kRowsPerWave;
+    const int64_t wave = xcd_block(per_xcd) * WPB + (threadIdx.x >> 6);
+    const int64_t q0 = wave * RPW;
     if (q0 >= nrows) return;
-    const int64_t q1 = q0 + kRowsPerWave < nrows ? q0 + kRowsPerWave : nrows;
+    const int64_t q1 = q0 + RPW < nrows ? q0 + RPW : nrows;
     // checked build: this run's rows of R, its X slabs and its Y entries
     MK_DCHECK(((q1 - 1) * n4 + nload4) * 16 <= ext.r);
     MK_DCHECK(((NF - 1) * xstride4 + (q1 - 1) / nr * n4 + nload4) * 16 <= ext.x);
@@ -127,16 +141,16 @@ __global__ __launch_bounds__(kWaves * 64) void k_contract_c64(
 }
 
 // FP16/BF16 R with per-frequency scale: one 16-byte load = 4 complex values.
-template <int J, int NF, int PREC>
-__global__ __launch_bounds__(kWaves * 64) void k_contract_q16(
+template <int J, int NF, int PREC, int RPW, int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_contract_q16(
     const v4u* __restrict__ R, const v4f* __restrict__ X, const float* __restrict__ rscale,
     float2* __restrict__ Y, int nr, int n16, int nload16, int n4, int64_t nrows, int64_t xstride4,
     int64_t ystride, int64_t per_xcd, Ext3 ext) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = xcd_block(per_xcd) * kWaves + (threadIdx.x >> 6);
-    const int64_t q0 = wave * kRowsPerWave;
+    const int64_t wave = xcd_block(per_xcd) * WPB + (threadIdx.x >> 6);
+    const int64_t q0 = wave * RPW;
     if (q0 >= nrows) return;
-    const int64_t q1 = q0 + kRowsPerWave < nrows ? q0 + kRowsPerWave : nrows;
+    const int64_t q1 = q0 + RPW < nrows ? q0 + RPW : nrows;
     // checked build: this run's rows of R, its X slabs and its Y entries
     MK_DCHECK(((q1 - 1) * n16 + nload16) * 16 <= ext.r);
     MK_DCHECK(((NF - 1) * xstride4 + (q1 - 1) / nr * n4 + 2 * nload16) * 16 <= ext.x);
@@ -210,9 +224,20 @@ __global__ __launch_bounds__(kWaves * 64) void k_contract_q16(
     }
 }
 
+// grid of a launch over nrows rows in runs of rpw rows, wpb waves per block
+struct RunGrid {
+    dim3 grid, block;
+    int64_t per_xcd;
+};
+RunGrid run_grid(int64_t nrows, int rpw, int wpb) {
+    const int64_t waves = (nrows + rpw - 1) / rpw;
+    const int64_t blocks = (waves + wpb - 1) / wpb;
+    const int64_t per_xcd = (blocks + 7) / 8;
+    return {dim3((unsigned)(8 * per_xcd)), dim3(wpb * 64), per_xcd};
+}
+
 template <int J, int NF>
-void launch_one(const ContractArgs& c, const float2* X, float2* Yc, dim3 grid, dim3 block,
-                int64_t per_xcd, hipStream_t s) {
+void launch_one(const ContractArgs& c, const float2* X, float2* Yc, hipStream_t s) {
     const int64_t nrows = (int64_t)c.nb * c.nr;
     const int64_t xstride4 = (int64_t)c.B * (c.ns_pad / 2);
     const int64_t ystride = (int64_t)c.B * c.nr;
@@ -220,30 +245,31 @@ void launch_one(const ContractArgs& c, const float2* X, float2* Yc, dim3 grid, d
     const Ext3 ext{c.ext_r,
                    c.ext_x - (int64_t)(reinterpret_cast<const char*>(X) - static_cast<const char*>(c.X)),
                    c.ext_y - (int64_t)(reinterpret_cast<const char*>(Yc) - reinterpret_cast<const char*>(c.Y))};
+    const v4f* X4 = reinterpret_cast<const v4f*>(X);
+    const v4u* R16 = reinterpret_cast<const v4u*>(c.R);
     if (c.prec == MK_R_C64) {
-        hipLaunchKernelGGL((k_contract_c64<J, NF>), grid, block, 0, s,
-                           reinterpret_cast<const v4f*>(c.R), reinterpret_cast<const v4f*>(X), Yc, c.nr,
-                           c.ns_pad / 2, (c.ns + 1) / 2, nrows, xstride4, ystride, per_xcd, ext);
+        using S = RunShape<MK_R_C64, NF>;
+        const RunGrid g = run_grid(nrows, S::rows, S::waves);
+        hipLaunchKernelGGL((k_contract_c64<J, NF, S::rows, S::waves>), g.grid, g.block, 0, s,
+                           reinterpret_cast<const v4f*>(c.R), X4, Yc, c.nr, c.ns_pad / 2, (c.ns + 1) / 2, nrows,
+                           xstride4, ystride, g.per_xcd, ext);
     } else if (c.prec == MK_R_F16S) {
-        hipLaunchKernelGGL((k_contract_q16<J, NF, MK_R_F16S>), grid, block, 0, s,
-                           reinterpret_cast<const v4u*>(c.R), reinterpret_cast<const v4f*>(X), c.rscale,
-                           Yc, c.nr, c.ns_pad / 4, (c.ns + 3) / 4, c.ns_pad / 2, nrows, xstride4, ystride,
-                           per_xcd, ext);
+        using S = RunShape<MK_R_F16S, NF>;
+        const RunGrid g = run_grid(nrows, S::rows, S::waves);
+        hipLaunchKernelGGL((k_contract_q16<J, NF, MK_R_F16S, S::rows, S::waves>), g.grid, g.block, 0, s, R16, X4,
+                           c.rscale, Yc, c.nr, c.ns_pad / 4, (c.ns + 3) / 4, c.ns_pad / 2, nrows, xstride4,
+                           ystride, g.per_xcd, ext);
     } else {
-        hipLaunchKernelGGL((k_contract_q16<J, NF, MK_R_BF16S>), grid, block, 0, s,
-                           reinterpret_cast<const v4u*>(c.R), reinterpret_cast<const v4f*>(X), c.rscale,
-                           Yc, c.nr, c.ns_pad / 4, (c.ns + 3) / 4, c.ns_pad / 2, nrows, xstride4, ystride,
-                           per_xcd, ext);
+        using S = RunShape<MK_R_BF16S, NF>;
+        const RunGrid g = run_grid(nrows, S::rows, S::waves);
+        hipLaunchKernelGGL((k_contract_q16<J, NF, MK_R_BF16S, S::rows, S::waves>), g.grid, g.block, 0, s, R16, X4,
+                           c.rscale, Yc, c.nr, c.ns_pad / 4, (c.ns + 3) / 4, c.ns_pad / 2, nrows, xstride4,
+                           ystride, g.per_xcd, ext);
     }
 }
 
 template <int J>
 hipError_t launch_j(const ContractArgs& c, hipStream_t s) {
-    const int64_t nrows = (int64_t)c.nb * c.nr;
-    const int64_t waves = (nrows + kRowsPerWave - 1) / kRowsPerWave;
-    const int64_t blocks = (waves + kWaves - 1) / kWaves;
-    const int64_t per_xcd = (blocks + 7) / 8;
-    const dim3 grid((unsigned)(8 * per_xcd)), block(kWaves * 64);
     const int64_t xslab = (int64_t)c.B * c.ns_pad;     // complex elements per focal slab
     const int64_t yslab = (int64_t)c.B * c.nr;
     for (int c0 = 0; c0 < c.ncols;) {
@@ -251,13 +277,13 @@ hipError_t launch_j(const ContractArgs& c, hipStream_t s) {
         const float2* X = reinterpret_cast<const float2*>(c.X) + c0 * xslab;
         float2* Yc = c.Y + c0 * yslab;
         if (left >= 4) {
-            launch_one<J, 4>(c, X, Yc, grid, block, per_xcd, s);
+            launch_one<J, 4>(c, X, Yc, s);
             c0 += 4;
         } else if (left >= 2) {
-            launch_one<J, 2>(c, X, Yc, grid, block, per_xcd, s);
+            launch_one<J, 2>(c, X, Yc, s);
             c0 += 2;
         } else {
-            launch_one<J, 1>(c, X, Yc, grid, block, per_xcd, s);
+            launch_one<J, 1>(c, X, Yc, s);
             c0 += 1;
         }
         hipError_t e = hipGetLastError();
