@@ -47,7 +47,7 @@ PEAK_TFLOPS = {0: 157.3, 1: 2500.0, 2: 2500.0}     # dense MFMA: fp32, fp16, bf1
 # for the kernel source it was measured on (sha256 prefix of the file).
 TRAFFIC = {
     "k_contract_c64": {"source": "paper_2106_04649_amd/csrc/k_contract.hip",
-                       "sha": "b4ef6909a3f0320c", "bytes": 3006356480,
+                       "sha": "1dd152e5701403ed", "bytes": 3006343792,
                        "profile": "profiles/k_contract_c64_601x601_nt2048_nf1.md"},
 }
 
