@@ -242,10 +242,10 @@ __global__ __launch_bounds__(256) void k_contract_mfma(
     }
 }
 
-// LDS-staged variant for wide focal batches.  A block of 4 waves owns
-// 16*RA focal-real rows (8*RA focal columns) x 256 receivers of one bin;
-// wave v owns all of the block's rows x receivers [64 v, 64 v + 64), that is
-// RA x 4 accumulator tiles.
+// LDS-staged variant for wide focal batches.  A block of 4 (or 2, see
+// lds_block_waves) waves owns 16*RA focal-real rows (8*RA focal columns) x
+// 256 (128) receivers of one bin; wave v owns all of the block's rows x
+// receivers [64 v, 64 v + 64), that is RA x 4 accumulator tiles.
 //
 // The shot axis is cut into chunks of 128 bytes of every row (32 complex
 // shots in 16 bits, 16 in complex64), two matrix-core K steps each.  At the
@@ -282,7 +282,6 @@ template <int... J, typename F>
 __device__ __forceinline__ void for_each_index(std::integer_sequence<int, J...>, F&& f) {
     (f(std::integral_constant<int, J>{}), ...);
 }
-constexpr int kLdsRcv = kLdsTileReceivers;   // receivers per block
 
 // both embedding forms of a 16-byte X vector: form 0 (Re, -Im), form 1 (Im, Re)
 template <bool C64>
@@ -297,17 +296,29 @@ __device__ __forceinline__ void x_forms(v4u x, v4u& f0, v4u& f1) {
 }
 
 // LDS bytes of one block of the LDS-staged tiles
-template <int PREC, int RA, bool SPLIT>
-constexpr int lds_tile_bytes() {
-    constexpr int ROWS = 8 * RA * (SPLIT ? 2 : 1);
-    return (RA >= 8 ? 4 : 3) * 2 * ROWS * (kChunkBytes + 16);
+constexpr int lds_tile_bytes(int RA, bool SPLIT) {
+    return (RA >= 8 ? 4 : 3) * 2 * (8 * RA * (SPLIT ? 2 : 1)) * (kChunkBytes + 16);
+}
+
+// Waves per block (64 receivers each) of the LDS-staged tiles for nr
+// receivers: four, or two where 128-receiver blocks pad fewer rows than
+// 256-receiver ones (601 receivers: 640 against 768 rows, the last block's
+// idle waves otherwise holding a SIMD each for the block's whole life) and the
+// smaller blocks' LDS still lets every SIMD hold the waves its registers allow
+// (one for the 128-row tiles, two for the others: 2-wave blocks per CU = 2 x that).
+constexpr bool lds_two_wave_fits(int RA, bool SPLIT) {
+    return 2 * (RA >= 8 ? 1 : 2) * lds_tile_bytes(RA, SPLIT) <= 160 * 1024;
+}
+int lds_block_waves(int RA, bool SPLIT, int nr) {
+    const bool saves = (nr + 127) / 128 * 128 < (nr + 255) / 256 * 256;
+    return lds_two_wave_fits(RA, SPLIT) && saves ? 2 : 4;
 }
 
 // One tile of the LDS-staged contraction: tile index t = (w * rtiles + rt)
 // * ftiles + ft, on the block's LDS.  Every thread of the block calls it
 // with the same t; it returns early (block-uniformly) when the tile's focal
 // columns are past the bin's active count.
-template <int PREC, int RA, bool SPLIT, bool TILED>
+template <int PREC, int RA, bool SPLIT, bool TILED, int WV>
 __device__ __forceinline__ void contract_lds_tile(
     const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
     const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
@@ -323,8 +334,9 @@ __device__ __forceinline__ void contract_lds_tile(
     constexpr int BUFB = 2 * ROWS * ROWB;         // one buffer: both forms of every row
     constexpr int VPR = CB / 16;                  // 16-byte vectors per chunk row
     constexpr int NVEC = ROWS * VPR;              // staging vectors per chunk
-    constexpr int NV = (NVEC + 255) / 256;        // per thread
-    static_assert(NVEC % 256 == 0 || NVEC < 256, "staging vectors fill whole sweeps");
+    constexpr int TB = 64 * WV;                   // threads per block
+    constexpr int NV = (NVEC + TB - 1) / TB;      // per thread
+    static_assert(NVEC % TB == 0 || NVEC < TB, "staging vectors fill whole sweeps");
     // RA = 8 (one wave per SIMD) puts a barrier after every other chunk, which
     // takes four LDS buffers; the others close every chunk with one (three)
     constexpr bool PAIRED = RA >= 8;
@@ -340,7 +352,7 @@ __device__ __forceinline__ void contract_lds_tile(
     if (fbase >= nact) return;                    // uniform over the block
 
     const int i16 = lane & 15, g = lane >> 4;
-    const int r0 = rt * kLdsRcv + wv * 64;
+    const int r0 = rt * TB + wv * 64;             // 64 receivers per wave
     const int rowbytes = ns_pad * EB;
     const int nch = rowbytes / CB;                // rows are whole chunks (checked at launch)
     const int64_t lo_bytes = (int64_t)nfc * B * rowbytes;
@@ -357,7 +369,7 @@ __device__ __forceinline__ void contract_lds_tile(
     auto stage_load = [&](int c, v4u (&xr)[NV]) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const int v = min((int)threadIdx.x + 256 * i, NVEC - 1);   // extra threads repeat the last vector
+            const int v = min((int)threadIdx.x + TB * i, NVEC - 1);   // extra threads repeat the last vector
             const int row = v / VPR, col = v % VPR;
             const int f = min(fbase + row % NFB, nact - 1);
             xr[i] = *reinterpret_cast<const v4u*>(reinterpret_cast<const unsigned char*>(Xv) + (row / NFB) * lo_bytes +
@@ -368,7 +380,7 @@ __device__ __forceinline__ void contract_lds_tile(
     auto stage_store = [&](int buf, const v4u (&xr)[NV]) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const int v = min((int)threadIdx.x + 256 * i, NVEC - 1);   // same value, same place
+            const int v = min((int)threadIdx.x + TB * i, NVEC - 1);   // same value, same place
             const int row = v / VPR, col = v % VPR;
             v4u f0, f1;
             x_forms<C64>(xr[i], f0, f1);
@@ -569,18 +581,18 @@ __device__ __forceinline__ void contract_lds_tile(
 // smaller tiles run two waves per SIMD.  Grid form: one block per tile,
 // tiles dealt to the 8 XCDs in contiguous runs (focal tiles fastest, so the
 // focal tiles that share an R tile meet in one L2).
-template <int PREC, int RA, bool SPLIT, bool TILED>
-__global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
+template <int PREC, int RA, bool SPLIT, bool TILED, int WV>
+__global__ __launch_bounds__(64 * WV, RA >= 8 ? 1 : 2) void k_contract_lds(
     const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
     const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
     int ncols_mul, int nr, int ns_pad, int B, int nfc, int ftiles, int rtiles, int64_t ntiles,
     int64_t per_xcd, Ext3 ext) {
-    __shared__ __attribute__((aligned(16))) unsigned char lds[lds_tile_bytes<PREC, RA, SPLIT>()];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[lds_tile_bytes(RA, SPLIT)];
     const int64_t bid = blockIdx.x;
     const int64_t t = (bid & 7) * per_xcd + (bid >> 3);
     if (t >= ntiles) return;
-    contract_lds_tile<PREC, RA, SPLIT, TILED>(Rv, rscale, Xv, xscale, Y, ncols_w, ncols_mul, nr, ns_pad, B, nfc,
-                                              ftiles, rtiles, t, lds, ext);
+    contract_lds_tile<PREC, RA, SPLIT, TILED, WV>(Rv, rscale, Xv, xscale, Y, ncols_w, ncols_mul, nr, ns_pad, B,
+                                                  nfc, ftiles, rtiles, t, lds, ext);
 }
 
 // Persistent form: a fixed grid (every block resident at once) walks a list
@@ -589,44 +601,54 @@ __global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds(
 // list (ascending tile indices) is cut into 8 contiguous runs, one per XCD;
 // the blocks of an XCD stride through its run.  Every block leaves the loop
 // when its run is exhausted.
-template <int PREC, int RA, bool SPLIT, bool TILED>
-__global__ __launch_bounds__(256, RA >= 8 ? 1 : 2) void k_contract_lds_walk(
+template <int PREC, int RA, bool SPLIT, bool TILED, int WV>
+__global__ __launch_bounds__(64 * WV, RA >= 8 ? 1 : 2) void k_contract_lds_walk(
     const void* __restrict__ Rv, const float* __restrict__ rscale, const void* __restrict__ Xv,
     const float* __restrict__ xscale, float2* __restrict__ Y, const int* __restrict__ ncols_w,
     int ncols_mul, int nr, int ns_pad, int B, int nfc, int ftiles, int rtiles,
     const int* __restrict__ items, Ext3 ext) {
-    __shared__ __attribute__((aligned(16))) unsigned char lds[lds_tile_bytes<PREC, RA, SPLIT>()];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[lds_tile_bytes(RA, SPLIT)];
     const int nitems = items[0];                  // the list: [count, tiles...]
     const int x = (int)(blockIdx.x & 7);
     const int per_xcd = (nitems + 7) >> 3;
     const int lo = x * per_xcd, hi = min(lo + per_xcd, nitems);
     const int step = (int)(gridDim.x >> 3);
     for (int i = lo + (int)(blockIdx.x >> 3); i < hi; i += step) {
-        contract_lds_tile<PREC, RA, SPLIT, TILED>(Rv, rscale, Xv, xscale, Y, ncols_w, ncols_mul, nr, ns_pad, B,
-                                                  nfc, ftiles, rtiles, items[1 + i], lds, ext);
+        contract_lds_tile<PREC, RA, SPLIT, TILED, WV>(Rv, rscale, Xv, xscale, Y, ncols_w, ncols_mul, nr, ns_pad, B,
+                                                      nfc, ftiles, rtiles, items[1 + i], lds, ext);
         __syncthreads();                          // the next tile restages the LDS buffers
     }
+}
+
+template <int PREC, int RA, bool SPLIT, bool TILED, int WV>
+hipError_t launch_lw(const ContractArgs& c, hipStream_t s) {
+    constexpr int NFB = 8 * RA;
+    const int ftiles = (c.ncols + NFB - 1) / NFB;
+    const int rtiles = (c.nr + 64 * WV - 1) / (64 * WV);
+    if (c.items) {          // persistent form over the list of active tiles
+        // walk_blocks_per_xcd counts blocks of four waves, two waves per SIMD
+        const int blocks = c.walk_blocks_per_xcd * (4 / WV) / (RA >= 8 ? 2 : 1);
+        const int grid = 8 * std::max(1, blocks);
+        hipLaunchKernelGGL((k_contract_lds_walk<PREC, RA, SPLIT, TILED, WV>), dim3((unsigned)grid), dim3(64 * WV), 0,
+                           s, c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B,
+                           c.ncols, ftiles, rtiles, c.items, Ext3{c.ext_r, c.ext_x, c.ext_y});
+        return hipGetLastError();
+    }
+    const int64_t ntiles = (int64_t)ftiles * rtiles * c.nb;
+    const int64_t per_xcd = (ntiles + 7) / 8;
+    hipLaunchKernelGGL((k_contract_lds<PREC, RA, SPLIT, TILED, WV>), dim3((unsigned)(8 * per_xcd)), dim3(64 * WV), 0,
+                       s, c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B, c.ncols,
+                       ftiles, rtiles, ntiles, per_xcd, Ext3{c.ext_r, c.ext_x, c.ext_y});
+    return hipGetLastError();
 }
 
 template <int PREC, int RA, bool SPLIT, bool TILED>
 hipError_t launch_l(const ContractArgs& c, hipStream_t s) {
     if ((c.ns_pad * (PREC == MK_R_C64 ? 8 : 4)) % kChunkBytes != 0) return hipErrorInvalidValue;
-    constexpr int NFB = 8 * RA;
-    const int ftiles = (c.ncols + NFB - 1) / NFB;
-    const int rtiles = (c.nr + kLdsRcv - 1) / kLdsRcv;
-    if (c.items) {          // persistent form over the list of active tiles
-        const int grid = 8 * std::max(1, c.walk_blocks_per_xcd / (RA >= 8 ? 2 : 1));
-        hipLaunchKernelGGL((k_contract_lds_walk<PREC, RA, SPLIT, TILED>), dim3((unsigned)grid), dim3(256), 0, s,
-                           c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B, c.ncols,
-                           ftiles, rtiles, c.items, Ext3{c.ext_r, c.ext_x, c.ext_y});
-        return hipGetLastError();
+    if constexpr (lds_two_wave_fits(RA, SPLIT)) {
+        if (lds_block_waves(RA, SPLIT, c.nr) == 2) return launch_lw<PREC, RA, SPLIT, TILED, 2>(c, s);
     }
-    const int64_t ntiles = (int64_t)ftiles * rtiles * c.nb;
-    const int64_t per_xcd = (ntiles + 7) / 8;
-    hipLaunchKernelGGL((k_contract_lds<PREC, RA, SPLIT, TILED>), dim3((unsigned)(8 * per_xcd)), dim3(256), 0, s,
-                       c.R, c.rscale, c.X, c.xscale, c.Y, c.ncols_w, c.ncols_mul, c.nr, c.ns_pad, c.B, c.ncols,
-                       ftiles, rtiles, ntiles, per_xcd, Ext3{c.ext_r, c.ext_x, c.ext_y});
-    return hipGetLastError();
+    return launch_lw<PREC, RA, SPLIT, TILED, 4>(c, s);
 }
 
 template <int PREC, int WM, int WN, bool SPLIT>
@@ -678,6 +700,11 @@ int contract_mfma_variants() { return 8; }
 // focal columns per tile of LDS-staged variant v (6, 7, 8), 0 for the others
 int contract_variant_focal_tile(int variant) {
     return variant == 6 ? 64 : variant == 7 ? 32 : variant == 8 ? 16 : 0;
+}
+
+int contract_lds_receivers(int variant, bool xsplit, int nr) {
+    const int nfb = contract_variant_focal_tile(variant);
+    return nfb == 0 ? 0 : 64 * lds_block_waves(nfb / 8, xsplit, nr);
 }
 
 hipError_t launch_contract_mfma(const ContractArgs& c, int variant, hipStream_t s) {

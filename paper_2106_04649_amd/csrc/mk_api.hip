@@ -674,15 +674,18 @@ mk_status build_walk(mk_plan_t p) {
                       (p->has_fband && !p->r_stream && !(p->d.flags & MK_FLAG_GRID));
     if (!walk) return MK_OK;
     const ContractChoice* ch[2] = {&p->series_choice, &p->g_choice};
-    const int rtiles = (p->d.nr + kLdsTileReceivers - 1) / kLdsTileReceivers;
     for (int k = 0; k < 2; ++k) {
         const int nfb = contract_variant_focal_tile(ch[k]->variant);
         if (nfb == 0) continue;                   // not an LDS-staged choice
+        const bool xsplit = ch[k]->xprec == XP_F16X2 || ch[k]->xprec == XP_BF16X2;
+        const int rcv = contract_lds_receivers(ch[k]->variant, xsplit, p->d.nr);
+        const int rtiles = (p->d.nr + rcv - 1) / rcv;
         if (!p->walk_items[k]) {
             // sized once for the largest list (every tile of the narrowest
-            // LDS-staged tiles, 16 focal columns), so captured graphs keep a
-            // valid address across focal sets
-            const size_t cap = 1 + (size_t)p->B * rtiles * (((size_t)(k + 1) * p->d.nf_max + 15) / 16);
+            // LDS-staged tiles, 16 focal columns x 128 receivers), so
+            // captured graphs keep a valid address across focal sets
+            const size_t rmax = (size_t)(p->d.nr + 127) / 128;
+            const size_t cap = 1 + (size_t)p->B * rmax * (((size_t)(k + 1) * p->d.nf_max + 15) / 16);
             HIP_TRY(p, hipStreamSynchronize(p->stream));
             HIP_TRY(p, dalloc(&p->walk_items[k], cap));
         }

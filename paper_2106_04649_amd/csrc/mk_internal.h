@@ -294,7 +294,6 @@ hipError_t launch_rscale(const float* Rin, float* rscale, int nr, int B, int ns,
 // tiles follow in (w, rg, c) order, so one wave load of 64 x 16 bytes is 1 KB
 // of contiguous memory.  Receivers past nr and shots past ns are zero.
 constexpr int kTileRows = 16;
-constexpr int kLdsTileReceivers = 256;     // receivers per block of the LDS-staged contraction
 constexpr int kTileChunkBytes = 128;
 // R into the tiles of the LDS-staged contraction (any precision)
 hipError_t launch_repack_tiled(int prec, const float* Rin, void* Rout, const float* rscale, int nr, int B,
@@ -303,6 +302,10 @@ size_t tiled_R_bytes(int prec, int nr, int B, int ns_pad);
 bool contract_variant_reads_tiled(int variant);
 // focal columns per tile of LDS-staged contraction variant v (6, 7, 8); 0 for the others
 int contract_variant_focal_tile(int variant);
+// receivers per block (and per tile of the walk's list) of LDS-staged
+// variant v for nr receivers and one or two planes of X: 256 or 128; 0 for
+// the other variants
+int contract_lds_receivers(int variant, bool xsplit, int nr);
 hipError_t launch_check_finite(const float* x, int64_t n, int* flag, hipStream_t s);
 // x may be NULL: then only the per-trace scales are written
 hipError_t launch_tail_prep(const float* hist, int ntr, int k, int T, float* x, float* scale, hipStream_t s);

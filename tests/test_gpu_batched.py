@@ -26,8 +26,11 @@ def _flags(variant, tiled):
 
 
 @pytest.mark.parametrize("variant,tiled", [(v, False) for v in range(9)] + [(v, True) for v in (6, 7, 8)])
-@pytest.mark.parametrize("n,nt,nf", [(70, 64, 6), (37, 128, 40), (300, 32, 20)])
+@pytest.mark.parametrize("n,nt,nf", [(70, 64, 6), (37, 128, 40), (300, 32, 20), (250, 64, 20)])
 def test_every_contraction_variant_fp32(variant, tiled, n, nt, nf):
+    """Every variant against the oracle.  The LDS-staged tiles run blocks of
+    two waves (128 receivers) where that pads fewer receiver rows and their
+    LDS allows it (70, 37, 300 receivers) and of four (250 receivers)."""
     say(f"variant {variant} tiled {tiled} n={n} nt={nt} nf={nf}")
     p = small_problem(seed=20 + nf, n=n, nt=nt, nf=nf, niter=6)
     g = run_gpu(p, tune=variant, flags=_flags(variant, tiled))
@@ -52,6 +55,21 @@ def test_reduced_precision_R(rprec, variant, tiled):
     p = small_problem(seed=31, n=48, nt=128, nf=20, niter=8)
     g = run_gpu(p, rprec=rprec, tune=variant, flags=_flags(variant, tiled))
     assert_parity(g, run_oracle(p), tol=TOL[rprec], label=f"prec{rprec}-v{variant}")
+
+
+@pytest.mark.parametrize("rprec", [1, 2])
+@pytest.mark.parametrize("nf", [1, 2, 3, 5])
+def test_reduced_precision_gemv_few_columns(rprec, nf):
+    """16-bit R through the streaming contraction with one to five focal
+    columns: the one-, two- and four-column run shapes alone and together in
+    one pass (the G assembly doubles the columns), on a row count (37
+    receivers x 65 bins) that no run length divides."""
+    mk = require_gpu()
+    say(f"gemv rprec {rprec} nf {nf}")
+    p = small_problem(seed=60 + nf, n=37, nt=128, nf=nf, niter=6)
+    g = run_gpu(p, rprec=rprec, tune=0, flags=mk.MK_FLAG_ROW_R)
+    assert g["variant"] == 0
+    assert_parity(g, run_oracle(p), tol=TOL[rprec], label=f"gemv{rprec}-nf{nf}")
 
 
 @pytest.mark.parametrize("rprec", [1, 2])
