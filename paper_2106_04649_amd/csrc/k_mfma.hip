@@ -303,11 +303,14 @@ constexpr int lds_tile_bytes(int RA, bool SPLIT) {
 // Waves per block (64 receivers each) of the LDS-staged tiles for nr
 // receivers: four, or two where 128-receiver blocks pad fewer rows than
 // 256-receiver ones (601 receivers: 640 against 768 rows, the last block's
-// idle waves otherwise holding a SIMD each for the block's whole life) and the
-// smaller blocks' LDS still lets every SIMD hold the waves its registers allow
-// (one for the 128-row tiles, two for the others: 2-wave blocks per CU = 2 x that).
+// idle waves otherwise holding a SIMD each for the block's whole life), for
+// the tiles that run two waves per SIMD and whose LDS still fits four of the
+// smaller blocks per CU.  The 128-row tiles (one wave per SIMD) keep four
+// waves: measured at 601 receivers, two-wave blocks made the 16-bit one-plane
+// launch slower (445 against 436 us), while the complex64 32-column tiles
+// gained 12 % (1599 against 1805 us).
 constexpr bool lds_two_wave_fits(int RA, bool SPLIT) {
-    return 2 * (RA >= 8 ? 1 : 2) * lds_tile_bytes(RA, SPLIT) <= 160 * 1024;
+    return RA < 8 && 4 * lds_tile_bytes(RA, SPLIT) <= 160 * 1024;
 }
 int lds_block_waves(int RA, bool SPLIT, int nr) {
     const bool saves = (nr + 127) / 128 * 128 < (nr + 255) / 256 * 256;

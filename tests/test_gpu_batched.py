@@ -28,9 +28,10 @@ def _flags(variant, tiled):
 @pytest.mark.parametrize("variant,tiled", [(v, False) for v in range(9)] + [(v, True) for v in (6, 7, 8)])
 @pytest.mark.parametrize("n,nt,nf", [(70, 64, 6), (37, 128, 40), (300, 32, 20), (250, 64, 20)])
 def test_every_contraction_variant_fp32(variant, tiled, n, nt, nf):
-    """Every variant against the oracle.  The LDS-staged tiles run blocks of
-    two waves (128 receivers) where that pads fewer receiver rows and their
-    LDS allows it (70, 37, 300 receivers) and of four (250 receivers)."""
+    """Every variant against the oracle.  The LDS-staged tiles with two waves
+    per SIMD (variants 7, 8) run blocks of two waves (128 receivers) where
+    that pads fewer receiver rows (70, 37, 300 receivers) and of four
+    otherwise (250 receivers, and the 128-row tiles of variant 6)."""
     say(f"variant {variant} tiled {tiled} n={n} nt={nt} nf={nf}")
     p = small_problem(seed=20 + nf, n=n, nt=nt, nf=nf, niter=6)
     g = run_gpu(p, tune=variant, flags=_flags(variant, tiled))
