@@ -233,8 +233,9 @@ struct ContractArgs {
                            // X and Y keep the B-bin strides of the whole band)
     // LDS-staged variants only: when items is set, the persistent form walks
     // the tile list items = [count, tile indices (ascending)...] with
-    // walk_blocks_per_xcd blocks of two waves per SIMD on each of the 8 XCDs
-    // (half as many for the one-wave 128-row tiles)
+    // walk_blocks_per_xcd four-wave blocks (two waves per SIMD) on each of
+    // the 8 XCDs: half as many for the one-wave 128-row tiles, twice as many
+    // two-wave blocks where the tiles use those
     const int* items = nullptr;
     int walk_blocks_per_xcd = 0;
     // bytes from R, X and Y to the end of their allocations (checked build)
